@@ -1,0 +1,209 @@
+/*
+ * fx.h -- C ABI of the free-flight expansion library (libfx.so, gfx950).
+ *
+ * The library evaluates the prescription (FF) of section 5.2 of Deuar,
+ * "A tractable prescription for large-scale free flight expansion of
+ * wavefunctions" (arXiv:1602.03395): a compact field Psi on an M-point
+ * lattice (x_j = a_j + n_j dx_j, eq. (xj)) flies freely for a time t into
+ * vacuum (eq. (vacuum)); the result is returned on the magnified lattice
+ * xbar_j = abar_j + nbar_j lam_j dx_j (eq. (wbx)) with the same number of
+ * points, as the sum over the lam = prod_j lam_j terms q of
+ *
+ *     Psibar[nbar] = sum_q f^(q)[nbar] B^(q)[n''(nbar)]            (FFpsi)
+ *     f^(q)        = (1/lam) exp(i alpha_q.(xbar - a - alpha_q hbar t / 2m))   (presf)
+ *     B^(q)        = FFT^-1[ A~^(q) exp(i k.(abar - a - (k + 2 alpha_q) hbar t / 2m)) ]   (presB)
+ *     A~^(q)       = FFT[ Psi exp(-i alpha_q.(x - a)) ]            (presA)
+ *     n''_j        = (nbar_j lam_j) mod M_j                        (FFaux)
+ *
+ * with alpha_j = q_j dk_j / lam_j, dk_j = 2 pi / L_j, the wavevectors of
+ * eq. (kj) (Nyquist negative) and the odd-M umklapp rule stated after (FF).
+ * The density rho = |Psibar|^2 is what is measured (section 2).
+ *
+ * Conventions shared by every call:
+ *  - Arrays are C-ordered with the last axis contiguous; the output has the
+ *    input's shape. Complex values are interleaved (re, im): complex128 for
+ *    FX_PREC_C128 and complex64 for FX_PREC_C64_PHASE64. Densities are
+ *    float64 resp. float32.
+ *  - Every data pointer is a DEVICE pointer owned by the caller. The library
+ *    never frees, retains or aliases caller memory beyond the call. Inputs
+ *    and outputs must not overlap.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream). Work is
+ *    enqueued on it and the call returns without synchronising; outputs are
+ *    valid once the stream reaches that point. A plan must not be used on
+ *    two streams at the same time; distinct plans are independent.
+ *  - Arguments are validated on the host before anything is launched. On
+ *    error a negative fx_status is returned, nothing is launched, outputs
+ *    are unspecified, and fx_last_error() returns a message for the calling
+ *    thread. No exception or abort crosses this interface.
+ *  - Units: only hbar t / m enters; the caller passes m/hbar and t.
+ */
+#ifndef FX_H
+#define FX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FX_MAX_DIM 3
+
+typedef enum fx_status {
+    FX_OK = 0,
+    FX_EINVAL = -1,        /* invalid argument (shape, lambda, dx, t, pointers, ...) */
+    FX_ENOMEM = -2,        /* device or host allocation failed, or workspace too small */
+    FX_EDEVICE = -3,       /* a HIP runtime call or kernel launch failed */
+    FX_EUNSUPPORTED = -4   /* valid problem outside what this build supports (e.g. too long an axis) */
+} fx_status;
+
+typedef enum fx_precision {
+    FX_PREC_C128 = 0,         /* plain method: complex128 data, FP64 arithmetic throughout */
+    FX_PREC_C64_PHASE64 = 1   /* complex64 data, FP32 transforms and accumulation; every phase
+                                 table (premultiply, chirp, twiddle f, FFT roots) is built in
+                                 FP64 with exact reduction modulo 2 pi and rounded once to FP32 */
+} fx_precision;
+
+typedef enum fx_schedule {
+    FX_SCHED_PAPER = 0,          /* the sum over all prod_j lam_j terms of (FF) */
+    FX_SCHED_AXIS_FACTORISED = 1 /* the same operator applied as d successive 1-D expansions
+                                    (sum_j lam_j terms); exact because the free propagator and
+                                    every factor of (FF) factorise over axes (eq. (free0)) */
+} fx_schedule;
+
+/*
+ * Problem statement (section 5.2). Only the first `ndim` entries of each
+ * array are read.
+ *   ndim        1..3
+ *   shape[j]    M_j >= 1
+ *   dx[j]       lattice spacing dx_j > 0, finite
+ *   a[j]        input offset a_j; NaN selects the default -M_j dx_j / 2
+ *   abar[j]     output offset abar_j; NaN selects the default
+ *               a_j + (1 - lam_j) M_j dx_j / 2 (magnified box with the same centre)
+ *   lambda[j]   integer magnification lam_j >= 1 (section 5.1 restricts to integers)
+ *   m_over_hbar m / hbar > 0, finite
+ *   t_flight    flight time, finite (negative values run the flight backwards)
+ *   precision   an fx_precision
+ *   schedule    an fx_schedule
+ */
+typedef struct fx_problem {
+    int32_t ndim;
+    int64_t shape[FX_MAX_DIM];
+    double dx[FX_MAX_DIM];
+    double a[FX_MAX_DIM];
+    double abar[FX_MAX_DIM];
+    int32_t lambda[FX_MAX_DIM];
+    double m_over_hbar;
+    double t_flight;
+    int32_t precision;
+    int32_t schedule;
+} fx_problem;
+
+typedef struct fx_plan fx_plan;
+typedef struct fx_batch fx_batch;
+
+/* Fills *p with a 1-D, 1-point, lam = 1, dx = 1, t = 0, FP64, paper-schedule
+ * problem with default offsets. Host only; never fails for a non-NULL p. */
+fx_status fx_problem_init(fx_problem* p);
+
+/*
+ * Builds a plan for one problem (host work + one upload): validates it,
+ * computes the per-axis phase tables of (presA), (presB), (presf) and the FFT
+ * roots in FP64 with exact reduction modulo 2 pi, rounds them to the data
+ * precision, uploads them to the current HIP device and chooses the kernel
+ * tiling. Allocates no workspace yet. *out is set only on FX_OK.
+ * Errors: FX_EINVAL (bad problem or NULL pointers), FX_EUNSUPPORTED (an axis
+ * longer than this build's in-LDS transform allows), FX_ENOMEM, FX_EDEVICE.
+ */
+fx_status fx_plan_create(const fx_problem* prob, fx_plan** out);
+
+/* Releases the plan, its tables and any workspace it allocated itself. NULL is a no-op. */
+fx_status fx_plan_destroy(fx_plan* plan);
+
+/* Number of terms q of (FFpsi) the plan sums: prod_j lam_j. */
+fx_status fx_plan_num_terms(const fx_plan* plan, int64_t* q_total);
+
+/* Device bytes of scratch memory fx_expand / fx_expand_range / fx_expand_adjoint need. */
+fx_status fx_plan_workspace_size(const fx_plan* plan, size_t* bytes);
+
+/*
+ * Hands the plan a caller-owned device buffer of at least
+ * fx_plan_workspace_size() bytes (256-byte aligned). Without it the plan
+ * allocates its own on first use. bytes == 0 with dev_ptr == NULL reverts to
+ * plan-owned workspace. Error: FX_ENOMEM if bytes is too small, FX_EINVAL on
+ * a misaligned pointer.
+ */
+fx_status fx_plan_set_workspace(fx_plan* plan, void* dev_ptr, size_t bytes);
+
+/*
+ * The whole expansion (FF) followed by the density: psi_out = Psibar,
+ * rho_out = |Psibar|^2. psi0 is the input field (M complex values). Either
+ * output may be NULL, not both. When psi_out is NULL the field is built in
+ * workspace memory.
+ */
+fx_status fx_expand(fx_plan* plan, const void* psi0, void* psi_out, void* rho_out, void* stream);
+
+/*
+ * Partial sum of (FFpsi) over the terms q_begin <= q < q_end, where the term
+ * index enumerates the q-vectors in C order of (q_{d-1}, ..., q_1, q_0), i.e.
+ * the magnification index of the contiguous axis varies slowest. With
+ * accumulate != 0 the partial sum is added to psi_acc, otherwise it replaces
+ * it. Sums over disjoint ranges add up to fx_expand's field; the sequential
+ * accumulation over q of section 7.1 is the use case (checkpointing long
+ * runs, splitting the terms over devices). 0 <= q_begin <= q_end <= terms.
+ */
+fx_status fx_expand_range(fx_plan* plan, const void* psi0, void* psi_acc, int64_t q_begin,
+                          int64_t q_end, int accumulate, void* stream);
+
+/* rho = |psi|^2 elementwise over the plan's M points (FP64 or FP32 like the plan). */
+fx_status fx_density(fx_plan* plan, const void* psi, void* rho, void* stream);
+
+/*
+ * Density image integrated along one axis of the magnified grid (section 6:
+ * rho(x, y) = integral dz |Psi|^2): image = sum over that axis of rho times the
+ * output spacing lam_axis dx_axis. image has the shape with `axis` removed.
+ * 0 <= axis < ndim.
+ */
+fx_status fx_column_density(fx_plan* plan, const void* rho, int axis, void* image, void* stream);
+
+/*
+ * Hermitian adjoint of the expansion: grad_psi0 = U^H grad_psi_out, with U
+ * the linear map psi0 -> Psibar of (FF). This is the inverse propagation of a
+ * residual on the magnified grid back to the initial lattice, used for the
+ * gradient of image-fitting losses (a derived operation: (FF) is linear in
+ * Psi, so its adjoint reverses every step with conjugated factors).
+ */
+fx_status fx_expand_adjoint(fx_plan* plan, const void* grad_psi_out, void* grad_psi0, void* stream);
+
+/*
+ * Ragged batch of problems (ensembles of realizations, section 1): problems
+ * with equal shape, spacing, offsets, magnification, flight and precision
+ * share one plan and run as one batched pass sequence; different shape
+ * classes follow each other. The kernel sequence of a run is captured once
+ * into a HIP graph and replayed with a single launch per fx_batch_run.
+ * All problems must have the same precision.
+ */
+fx_status fx_batch_create(const fx_problem* probs, int32_t n, fx_batch** out);
+fx_status fx_batch_destroy(fx_batch* batch);
+
+/*
+ * Runs the batch: for each i < n, psi_out[i] = Psibar_i and rho_out[i] =
+ * |Psibar_i|^2 (either array, or any entry of psi_out, may be NULL; rho_out
+ * entries may be NULL only when psi_out[i] is not). The pointer arrays are
+ * HOST arrays of DEVICE pointers. The first run on a stream, or a run with
+ * different pointers, re-captures the graph.
+ */
+fx_status fx_batch_run(fx_batch* batch, const void* const* psi0, void* const* psi_out,
+                       void* const* rho_out, void* stream);
+
+/* Writes a one-line JSON description of the plan's schedule and tiling into buf. */
+fx_status fx_plan_describe(const fx_plan* plan, char* buf, size_t len);
+
+const char* fx_status_string(fx_status s);
+const char* fx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FX_H */

@@ -1,0 +1,20 @@
+"""MI355X (gfx950) implementation of the finite-time free-flight expansion onto a
+magnified grid: the sum-of-FFTs prescription (FF) of arXiv:1602.03395,
+section 5.2, as hand-written HIP kernels behind the C ABI of ``include/fx.h``.
+
+Importing the package loads ``libfx.so`` from this directory and fails if it
+is missing; build it with ``python -m paper_1602_03395_amd.build``.
+"""
+
+from . import _lib  # noqa: F401  (loads libfx.so, raises if absent)
+from .api import (  # noqa: F401
+    ExpandDensity,
+    Plan,
+    column_density,
+    expand,
+    expand_adjoint,
+    expand_density,
+    get_plan,
+)
+
+__all__ = ["Plan", "expand", "expand_adjoint", "expand_density", "ExpandDensity", "column_density", "get_plan"]

@@ -1,0 +1,236 @@
+"""PyTorch-facing calls with the names of the C ABI.
+
+PyTorch supplies device memory and the current HIP stream; the expansion
+itself (every table product, transform, fold, gather and sum) runs in the
+kernels of ``libfx.so``. Precision follows the dtype of the input:
+complex128 -> plain FP64 method, complex64 -> FP32 data with FP64-built
+phase tables.
+"""
+
+from __future__ import annotations
+
+import collections
+import ctypes
+import threading
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib as L
+
+_PLAN_CACHE: "collections.OrderedDict" = collections.OrderedDict()
+_PLAN_LOCK = threading.Lock()
+_PLAN_CACHE_MAX = 32
+
+
+def _stream_ptr() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[ctypes.c_void_p]:
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_field(x: torch.Tensor, name: str):
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if x.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor (got {x.device})")
+    if x.dtype not in (torch.complex64, torch.complex128):
+        raise ValueError(f"{name} must be complex64 or complex128 (got {x.dtype})")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def precision_of(dtype: torch.dtype) -> int:
+    return L.FX_PREC_C128 if dtype == torch.complex128 else L.FX_PREC_C64_PHASE64
+
+
+def real_dtype(dtype: torch.dtype) -> torch.dtype:
+    return torch.float64 if dtype == torch.complex128 else torch.float32
+
+
+class Plan:
+    """Owns one ``fx_plan`` (tables on the device, tiling, schedule)."""
+
+    def __init__(self, shape, dx, m_over_hbar, t, lam, a=None, abar=None, dtype=torch.complex128,
+                 schedule: str = "paper"):
+        self.shape = tuple(int(s) for s in shape)
+        self.dtype = dtype
+        sched = {"paper": L.FX_SCHED_PAPER, "axis_factorised": L.FX_SCHED_AXIS_FACTORISED}[schedule]
+        prob = L.make_problem(self.shape, dx, lam, m_over_hbar, t, a, abar, precision_of(dtype), sched)
+        self.problem = prob
+        h = ctypes.c_void_p()
+        L.check(L.lib.fx_plan_create(ctypes.byref(prob), ctypes.byref(h)), "fx_plan_create")
+        self._h = h
+        self._ws = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            L.lib.fx_plan_destroy(h)
+            self._h = None
+
+    def num_terms(self) -> int:
+        q = ctypes.c_int64()
+        L.check(L.lib.fx_plan_num_terms(self._h, ctypes.byref(q)), "fx_plan_num_terms")
+        return q.value
+
+    def workspace_size(self) -> int:
+        b = ctypes.c_size_t()
+        L.check(L.lib.fx_plan_workspace_size(self._h, ctypes.byref(b)), "fx_plan_workspace_size")
+        return b.value
+
+    def use_torch_workspace(self, device=None):
+        """Let PyTorch own the scratch memory (one uint8 tensor kept alive by the plan)."""
+        n = self.workspace_size()
+        ws = torch.empty(n + 256, dtype=torch.uint8, device=device or "cuda")
+        off = (-ws.data_ptr()) % 256
+        L.check(L.lib.fx_plan_set_workspace(self._h, ctypes.c_void_p(ws.data_ptr() + off), n),
+                "fx_plan_set_workspace")
+        self._ws = ws
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(1 << 16)
+        L.check(L.lib.fx_plan_describe(self._h, buf, len(buf)), "fx_plan_describe")
+        return buf.value.decode()
+
+    # -- calls ---------------------------------------------------------------------------
+    def expand(self, psi0: torch.Tensor, want_psi: bool = True, want_rho: bool = True,
+               psi_out: Optional[torch.Tensor] = None, rho_out: Optional[torch.Tensor] = None):
+        _check_field(psi0, "psi0")
+        self._check_shape(psi0)
+        if want_psi and psi_out is None:
+            psi_out = torch.empty_like(psi0)
+        if want_rho and rho_out is None:
+            rho_out = torch.empty(psi0.shape, dtype=real_dtype(psi0.dtype), device=psi0.device)
+        L.check(L.lib.fx_expand(self._h, _ptr(psi0), _ptr(psi_out) if want_psi else None,
+                                _ptr(rho_out) if want_rho else None, _stream_ptr()), "fx_expand")
+        return (psi_out if want_psi else None), (rho_out if want_rho else None)
+
+    def expand_range(self, psi0: torch.Tensor, psi_acc: torch.Tensor, q_begin: int, q_end: int,
+                     accumulate: bool = False):
+        _check_field(psi0, "psi0")
+        _check_field(psi_acc, "psi_acc")
+        self._check_shape(psi0)
+        self._check_shape(psi_acc)
+        L.check(L.lib.fx_expand_range(self._h, _ptr(psi0), _ptr(psi_acc), int(q_begin), int(q_end),
+                                      1 if accumulate else 0, _stream_ptr()), "fx_expand_range")
+        return psi_acc
+
+    def density(self, psi: torch.Tensor, rho: Optional[torch.Tensor] = None):
+        _check_field(psi, "psi")
+        self._check_shape(psi)
+        if rho is None:
+            rho = torch.empty(psi.shape, dtype=real_dtype(psi.dtype), device=psi.device)
+        L.check(L.lib.fx_density(self._h, _ptr(psi), _ptr(rho), _stream_ptr()), "fx_density")
+        return rho
+
+    def column_density(self, rho: torch.Tensor, axis: int):
+        if rho.dtype != real_dtype(self.dtype) or rho.device.type != "cuda" or not rho.is_contiguous():
+            raise ValueError("rho must be a contiguous device tensor of the plan's real dtype")
+        if tuple(rho.shape) != self.shape:
+            raise ValueError("rho has the wrong shape")
+        d = len(self.shape)
+        if not 0 <= axis < d:
+            raise ValueError("axis out of range")
+        img_shape = tuple(s for i, s in enumerate(self.shape) if i != axis)
+        img = torch.empty(img_shape, dtype=rho.dtype, device=rho.device)
+        L.check(L.lib.fx_column_density(self._h, _ptr(rho), int(axis), _ptr(img), _stream_ptr()),
+                "fx_column_density")
+        return img
+
+    def expand_adjoint(self, grad_out: torch.Tensor, grad_in: Optional[torch.Tensor] = None):
+        _check_field(grad_out, "grad_psi_out")
+        self._check_shape(grad_out)
+        if grad_in is None:
+            grad_in = torch.empty_like(grad_out)
+        L.check(L.lib.fx_expand_adjoint(self._h, _ptr(grad_out), _ptr(grad_in), _stream_ptr()),
+                "fx_expand_adjoint")
+        return grad_in
+
+    def _check_shape(self, x: torch.Tensor):
+        if tuple(x.shape) != self.shape:
+            raise ValueError(f"tensor shape {tuple(x.shape)} does not match the plan's {self.shape}")
+        if x.dtype != self.dtype:
+            raise ValueError(f"tensor dtype {x.dtype} does not match the plan's {self.dtype}")
+
+
+def _key(shape, dx, m_over_hbar, t, lam, a, abar, dtype, schedule):
+    def tup(v):
+        if v is None:
+            return None
+        if isinstance(v, (int, float)):
+            return (float(v),)
+        return tuple(float(x) for x in v)
+    return (tuple(shape), tup(dx), float(m_over_hbar), float(t), tup(lam), tup(a), tup(abar), str(dtype),
+            schedule, torch.cuda.current_device())
+
+
+def get_plan(shape, dx, m_over_hbar, t, lam, a=None, abar=None, dtype=torch.complex128,
+             schedule: str = "paper") -> Plan:
+    k = _key(shape, dx, m_over_hbar, t, lam, a, abar, dtype, schedule)
+    with _PLAN_LOCK:
+        if k in _PLAN_CACHE:
+            _PLAN_CACHE.move_to_end(k)
+            return _PLAN_CACHE[k]
+    plan = Plan(shape, dx, m_over_hbar, t, lam, a, abar, dtype, schedule)
+    with _PLAN_LOCK:
+        _PLAN_CACHE[k] = plan
+        while len(_PLAN_CACHE) > _PLAN_CACHE_MAX:
+            _PLAN_CACHE.popitem(last=False)
+    return plan
+
+
+def expand(psi0: torch.Tensor, dx, m_over_hbar: float, t: float, lam, a=None, abar=None,
+           want_psi: bool = True, schedule: str = "paper") -> Tuple[Optional[torch.Tensor], torch.Tensor]:
+    """Free flight of ``psi0`` for time t onto the lattice magnified by ``lam``: returns (psi, rho)."""
+    _check_field(psi0, "psi0")
+    plan = get_plan(psi0.shape, dx, m_over_hbar, t, lam, a, abar, psi0.dtype, schedule)
+    return plan.expand(psi0, want_psi=want_psi, want_rho=True)
+
+
+def expand_adjoint(grad_out: torch.Tensor, dx, m_over_hbar: float, t: float, lam, a=None, abar=None,
+                   schedule: str = "paper") -> torch.Tensor:
+    _check_field(grad_out, "grad_psi_out")
+    plan = get_plan(grad_out.shape, dx, m_over_hbar, t, lam, a, abar, grad_out.dtype, schedule)
+    return plan.expand_adjoint(grad_out)
+
+
+def column_density(rho: torch.Tensor, axis: int, dx, m_over_hbar: float, t: float, lam, a=None, abar=None,
+                   dtype=None) -> torch.Tensor:
+    dtype = dtype or (torch.complex128 if rho.dtype == torch.float64 else torch.complex64)
+    plan = get_plan(rho.shape, dx, m_over_hbar, t, lam, a, abar, dtype)
+    return plan.column_density(rho, axis)
+
+
+class ExpandDensity(torch.autograd.Function):
+    """rho = |U psi0|^2 with the hand-written adjoint U^H for the backward pass.
+
+    For a real loss L(rho), PyTorch's complex gradient convention
+    (dL/dRe + i dL/dIm) gives grad_psi0 = U^H (2 * grad_rho * Psibar).
+    """
+
+    @staticmethod
+    def forward(ctx, psi0, dx, m_over_hbar, t, lam, a=None, abar=None, schedule="paper"):
+        psi0 = psi0.contiguous()
+        plan = get_plan(psi0.shape, dx, m_over_hbar, t, lam, a, abar, psi0.dtype, schedule)
+        psi, rho = plan.expand(psi0, want_psi=True, want_rho=True)
+        ctx.plan = plan
+        ctx.save_for_backward(psi)
+        return rho
+
+    @staticmethod
+    def backward(ctx, grad_rho):
+        (psi,) = ctx.saved_tensors
+        g = (2.0 * grad_rho.to(psi.real.dtype)) * psi
+        grad = ctx.plan.expand_adjoint(g.contiguous())
+        return grad, None, None, None, None, None, None, None
+
+
+def expand_density(psi0, dx, m_over_hbar, t, lam, a=None, abar=None, schedule="paper"):
+    return ExpandDensity.apply(psi0, dx, m_over_hbar, t, lam, a, abar, schedule)

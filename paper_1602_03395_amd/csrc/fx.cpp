@@ -1,0 +1,734 @@
+// Host runtime and C ABI of the free-flight expansion library.
+//
+// A plan holds, per axis, the FP64-built phase tables of the prescription (FF)
+// (section 5.2) rounded to the data precision, the radix plans of the in-LDS
+// transforms, and a schedule: the ordered list of per-axis passes that
+// evaluates (FF). With the active axes p_1 < ... < p_k (p_k the contiguous one):
+//
+//   paper schedule (all prod_j lam_j terms q of (FFpsi)):
+//     E(p_k), ..., E(p_2)   forward transform + chirp + pruned inverse along an
+//                           axis, one output slice per magnification index
+//                           (the shared prefixes of the d-dimensional FFTs of
+//                           all q-terms are computed once);
+//     EA(p_1)               the same along the slowest axis with the
+//                           twiddle-gather-accumulate of its index folded in;
+//     A(p_2), ..., A(p_k)   twiddle f and n'' gather of the remaining axes,
+//                           summing the slices of each magnification index.
+//   Each B^(q) is formed (per line, in LDS or in the slice tensors) and every
+//   term f^(q) B^(q)[n''] enters the sum; only the order of the additions and
+//   the sharing of common per-axis factors differ from a term-by-term loop.
+//
+//   axis-factorised schedule: EA(p_k), ..., EA(p_1) -- d successive 1-D
+//   expansions, sum_j lam_j terms (the operator is a tensor product over
+//   axes because every factor of (FF) and the free dispersion factorise).
+//
+// Long flights are processed in blocks of the outermost magnification index,
+// accumulating into the output, so the workspace stays bounded (the
+// sequential accumulation of section 7.1).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fx_internal.h"
+
+namespace fx {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+RadixPlan make_radix_plan(int n) {
+    RadixPlan p;
+    p.n = n;
+    int m = n;
+    auto push = [&](int r) { p.rad[p.nst++] = r; m /= r; };
+    while (m % 8 == 0 && p.nst < kMaxStages) push(8);
+    while (m % 4 == 0 && p.nst < kMaxStages) push(4);
+    while (m % 2 == 0 && p.nst < kMaxStages) push(2);
+    while (m % 3 == 0 && p.nst < kMaxStages) push(3);
+    for (int f = 5; m > 1 && p.nst < kMaxStages; f += 2) {
+        while (m % f == 0 && p.nst < kMaxStages) push(f);
+        if ((int64_t)f * f > m && m > 1 && p.nst < kMaxStages) {
+            push(m);
+            break;
+        }
+    }
+    return p;
+}
+
+int lds_limit_bytes() {
+    static int cached = -1;
+    if (cached < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            cached = v;
+        else
+            cached = 65536;
+    }
+    return cached;
+}
+
+}  // namespace fx
+
+using namespace fx;
+
+namespace {
+
+int64_t gcd64(int64_t a, int64_t b) {
+    while (b) {
+        int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+int64_t modinv(int64_t a, int64_t m) {
+    if (m == 1) return 0;
+    int64_t g0 = m, g1 = a % m, x0 = 0, x1 = 1;
+    while (g1) {
+        int64_t qd = g0 / g1;
+        int64_t t = g0 - qd * g1; g0 = g1; g1 = t;
+        t = x0 - qd * x1; x0 = x1; x1 = t;
+    }
+    if (g0 != 1) return -1;
+    return ((x0 % m) + m) % m;
+}
+
+#define FX_TRY_HIP(call)                                                                   \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            set_error(std::string(#call) + ": " + hipGetErrorString(e_));                  \
+            return FX_EDEVICE;                                                             \
+        }                                                                                  \
+    } while (0)
+
+struct Op {
+    Kind kind;
+    int axis;          // padded axis 0..2
+    PassGeom g;
+    int64_t in_elems;  // per op, elements read tensor size
+    int64_t out_elems;
+};
+
+constexpr int64_t kMaxAxis = 4096;
+
+}  // namespace
+
+struct fx_plan {
+    fx_problem prob{};
+    bool dbl = true;
+    int ndim = 1;
+    int64_t len[3] = {1, 1, 1};   // padded shape
+    AxisParams par[3];
+    AxisDev ax[3];
+    int act[3] = {0, 0, 0};
+    int nact = 0;
+    int64_t M = 1;                 // total points
+    int64_t Q = 1;                 // prod lam
+    void* dtab = nullptr;
+    size_t dtab_bytes = 0;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool ws_owned = false;
+    int64_t nb_outer = 1;          // block of the outermost magnification index
+    int64_t slices = 1;            // leading slices (batched realizations)
+    size_t ws_need = 0;
+    int64_t buf_elems = 0;         // elements of each of the two ping-pong buffers
+    int schedule = FX_SCHED_PAPER;
+    int ts_target = 2048;
+    size_t budget = 0;
+};
+
+namespace {
+
+size_t csize(const fx_plan* p) { return p->dbl ? 16 : 8; }
+
+int choose_ts(const fx_plan* p, Kind kind, int M, int64_t A, int64_t S) {
+    int ts = std::max(1, p->ts_target / std::max(1, M));
+    ts = std::min(ts, std::max(1, kMaxTilePoints / M));
+    if (S == 1) ts = (int)std::min<int64_t>(ts, A);
+    else ts = (int)std::min<int64_t>(ts, S);
+    ts = std::max(ts, 1);
+    const int lim = lds_limit_bytes();
+    while (ts > 1 && (int64_t)pass_lds_bytes(kind, p->dbl, ts, M) > lim) --ts;
+    return ts;
+}
+
+// Builds the op list for one block: q ranges per padded axis [qb[p], qb[p]+qn[p]); slices0 leading slices.
+std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], int64_t slices0, bool adjoint) {
+    std::vector<Op> ops;
+    int64_t lens[3] = {p->len[0], p->len[1], p->len[2]};
+    int64_t slices = slices0;
+    auto geom = [&](Kind kind, int ax, int64_t qin) {
+        PassGeom g;
+        g.A = 1;
+        g.S = 1;
+        for (int i = 0; i < ax; ++i) g.A *= lens[i];
+        for (int i = ax + 1; i < 3; ++i) g.S *= lens[i];
+        g.Qin = qin;
+        g.qb = qb[ax];
+        g.qn = qn[ax];
+        g.TS = choose_ts(p, kind, p->ax[ax].M, g.A, g.S);
+        if (g.S == 1) g.ntiles = (g.A + g.TS - 1) / g.TS;
+        else g.ntiles = g.A * ((g.S + g.TS - 1) / g.TS);
+        return g;
+    };
+    auto vol = [&]() { return slices * lens[0] * lens[1] * lens[2]; };
+    auto push = [&](Kind kind, int ax, int64_t qin, int64_t in_e, int64_t out_e) {
+        Op o;
+        o.kind = kind;
+        o.axis = ax;
+        o.g = geom(kind, ax, qin);
+        o.in_elems = in_e;
+        o.out_elems = out_e;
+        ops.push_back(o);
+    };
+    const int k = p->nact;
+    if (k == 0) return ops;
+    if (p->schedule == FX_SCHED_AXIS_FACTORISED) {
+        if (!adjoint) {
+            for (int i = k - 1; i >= 0; --i) push(Kind::EA, p->act[i], slices, vol(), vol());
+        } else {
+            for (int i = 0; i < k; ++i) push(Kind::EAH, p->act[i], slices, vol(), vol());
+        }
+        return ops;
+    }
+    if (!adjoint) {
+        for (int i = k - 1; i >= 1; --i) {
+            const int ax = p->act[i];
+            const int64_t in_e = vol();
+            PassGeom g = geom(Kind::E, ax, slices);
+            lens[ax] = p->ax[ax].P;
+            slices *= qn[ax];
+            Op o{Kind::E, ax, g, in_e, vol()};
+            ops.push_back(o);
+        }
+        push(Kind::EA, p->act[0], slices, vol(), vol());
+        for (int i = 1; i < k; ++i) {
+            const int ax = p->act[i];
+            const int64_t in_e = vol();
+            slices /= qn[ax];
+            lens[ax] = p->ax[ax].M;
+            PassGeom g = geom(Kind::A, ax, slices);
+            Op o{Kind::A, ax, g, in_e, vol()};
+            ops.push_back(o);
+        }
+    } else {
+        for (int i = k - 1; i >= 1; --i) {
+            const int ax = p->act[i];
+            const int64_t in_e = vol();
+            const int64_t qin = slices;
+            PassGeom g = geom(Kind::AH, ax, qin);
+            lens[ax] = p->ax[ax].P;
+            slices *= qn[ax];
+            Op o{Kind::AH, ax, g, in_e, vol()};
+            ops.push_back(o);
+        }
+        push(Kind::EAH, p->act[0], slices, vol(), vol());
+        for (int i = 1; i < k; ++i) {
+            const int ax = p->act[i];
+            const int64_t in_e = vol();
+            slices /= qn[ax];
+            lens[ax] = p->ax[ax].M;
+            PassGeom g = geom(Kind::EH, ax, slices);
+            Op o{Kind::EH, ax, g, in_e, vol()};
+            ops.push_back(o);
+        }
+    }
+    return ops;
+}
+
+int64_t max_intermediate(const std::vector<Op>& ops) {
+    int64_t m = 0;
+    for (size_t i = 0; i + 1 < ops.size(); ++i) m = std::max(m, ops[i].out_elems);
+    return m;
+}
+
+fx_status validate(const fx_problem* pr) {
+    if (!pr) { set_error("problem is NULL"); return FX_EINVAL; }
+    if (pr->ndim < 1 || pr->ndim > 3) { set_error("ndim must be 1, 2 or 3"); return FX_EINVAL; }
+    for (int j = 0; j < pr->ndim; ++j) {
+        if (pr->shape[j] < 1) { set_error("shape[j] must be >= 1"); return FX_EINVAL; }
+        if (!(std::isfinite(pr->dx[j]) && pr->dx[j] > 0)) { set_error("dx[j] must be finite and > 0"); return FX_EINVAL; }
+        if (pr->lambda[j] < 1) { set_error("lambda[j] must be an integer >= 1"); return FX_EINVAL; }
+        if (std::isinf(pr->a[j]) || std::isinf(pr->abar[j])) { set_error("offsets must be finite or NaN"); return FX_EINVAL; }
+    }
+    if (!(std::isfinite(pr->m_over_hbar) && pr->m_over_hbar > 0)) { set_error("m_over_hbar must be finite and > 0"); return FX_EINVAL; }
+    if (!std::isfinite(pr->t_flight)) { set_error("t_flight must be finite"); return FX_EINVAL; }
+    if (pr->precision != FX_PREC_C128 && pr->precision != FX_PREC_C64_PHASE64) { set_error("unknown precision"); return FX_EINVAL; }
+    if (pr->schedule != FX_SCHED_PAPER && pr->schedule != FX_SCHED_AXIS_FACTORISED) { set_error("unknown schedule"); return FX_EINVAL; }
+    int64_t tot = 1;
+    for (int j = 0; j < pr->ndim; ++j) {
+        if (pr->shape[j] > kMaxAxis) { set_error("axis longer than 4096 points is not supported by the in-LDS transforms"); return FX_EUNSUPPORTED; }
+        if ((int64_t)pr->lambda[j] * pr->shape[j] > (int64_t(1) << 26)) { set_error("lambda*M above 2^26 per axis is not supported"); return FX_EUNSUPPORTED; }
+        tot *= pr->shape[j];
+    }
+    if (tot > (int64_t(1) << 34)) { set_error("more than 2^34 lattice points"); return FX_EUNSUPPORTED; }
+    return FX_OK;
+}
+
+template <typename T>
+void to_prec(const std::vector<double>& src, std::vector<unsigned char>& dst, size_t off) {
+    T* d = (T*)(dst.data() + off);
+    for (size_t i = 0; i < src.size(); ++i) d[i] = (T)src[i];
+}
+
+fx_status plan_setup_workspace(fx_plan* p, int64_t slices) {
+    p->slices = slices;
+    const int k = p->nact;
+    int qb[3] = {0, 0, 0}, qn[3];
+    for (int i = 0; i < 3; ++i) qn[i] = p->ax[i].lam;
+    int64_t outer_lam = (k > 0) ? p->ax[p->act[k - 1]].lam : 1;
+    int64_t nb = outer_lam;
+    const size_t cs = csize(p);
+    auto need = [&](int64_t nbv) {
+        int qn2[3] = {qn[0], qn[1], qn[2]};
+        if (k > 0 && p->schedule == FX_SCHED_PAPER) qn2[p->act[k - 1]] = (int)nbv;
+        std::vector<Op> f = build_ops(p, qb, qn2, slices, false);
+        std::vector<Op> h = build_ops(p, qb, qn2, slices, true);
+        return std::max(max_intermediate(f), max_intermediate(h));
+    };
+    if (p->schedule == FX_SCHED_PAPER) {
+        while (nb > 1 && (size_t)need(nb) * 2 * cs > p->budget) nb = (nb + 1) / 2;
+    }
+    p->nb_outer = std::max<int64_t>(1, nb);
+    p->buf_elems = need(p->nb_outer);
+    p->ws_need = (size_t)(2 * p->buf_elems + slices * p->M) * cs + 1024;
+    return FX_OK;
+}
+
+fx_status ensure_workspace(fx_plan* p) {
+    if (p->ws && p->ws_bytes >= p->ws_need) return FX_OK;
+    if (p->ws && !p->ws_owned) {
+        set_error("caller workspace smaller than fx_plan_workspace_size()");
+        return FX_ENOMEM;
+    }
+    if (p->ws_owned && p->ws) {
+        (void)hipFree(p->ws);
+        p->ws = nullptr;
+    }
+    void* w = nullptr;
+    if (hipMalloc(&w, p->ws_need) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of workspace failed");
+        return FX_ENOMEM;
+    }
+    p->ws = w;
+    p->ws_bytes = p->ws_need;
+    p->ws_owned = true;
+    return FX_OK;
+}
+
+// Runs the op list of one block. src: input tensor, dst: final output; X/Y ping-pong.
+fx_status run_ops(fx_plan* p, const std::vector<Op>& ops, const void* src, void* dst, int accumulate, void* rho,
+                  hipStream_t st) {
+    char* base = (char*)p->ws;
+    void* bufs[2] = {base, base + (size_t)p->buf_elems * csize(p)};
+    const void* cur = src;
+    for (size_t i = 0; i < ops.size(); ++i) {
+        const bool last = (i + 1 == ops.size());
+        void* out = last ? dst : bufs[i % 2];
+        const Op& o = ops[i];
+        hipError_t e = launch_pass(o.kind, p->dbl, cur, out, p->ax[o.axis], o.g, last ? accumulate : 0,
+                                   last ? rho : nullptr, st);
+        if (e != hipSuccess) {
+            set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));
+            return FX_EDEVICE;
+        }
+        cur = out;
+    }
+    return FX_OK;
+}
+
+// Sum over the q-box [qb, qb+qn) per padded axis, blocked along the outermost axis.
+fx_status run_box(fx_plan* p, const int qb[3], const int qn[3], const void* src, void* dst, int accumulate,
+                  void* rho, bool adjoint, hipStream_t st) {
+    const int k = p->nact;
+    const size_t cs = csize(p);
+    const int64_t vol = p->slices * p->M;
+    if (k == 0) {
+        // every axis is a single point with lam = 1: Psibar = Psi
+        if (accumulate) {
+            set_error("accumulating an identity expansion is not supported");
+            return FX_EUNSUPPORTED;
+        }
+        FX_TRY_HIP(hipMemcpyAsync(dst, src, (size_t)vol * cs, hipMemcpyDeviceToDevice, st));
+        if (rho && launch_density(p->dbl, dst, rho, vol, st) != hipSuccess) return FX_EDEVICE;
+        return FX_OK;
+    }
+    const int outer = p->act[k - 1];
+    const int64_t step = (p->schedule == FX_SCHED_PAPER) ? p->nb_outer : qn[outer];
+    for (int64_t c = qb[outer]; c < qb[outer] + qn[outer]; c += step) {
+        int b2[3] = {qb[0], qb[1], qb[2]}, n2[3] = {qn[0], qn[1], qn[2]};
+        b2[outer] = (int)c;
+        n2[outer] = (int)std::min<int64_t>(step, qb[outer] + qn[outer] - c);
+        const bool first = (c == qb[outer]);
+        const bool lastc = (c + step >= qb[outer] + qn[outer]);
+        std::vector<Op> ops = build_ops(p, b2, n2, p->slices, adjoint);
+        fx_status s = run_ops(p, ops, src, dst, first ? accumulate : 1, lastc ? rho : nullptr, st);
+        if (s != FX_OK) return s;
+    }
+    return FX_OK;
+}
+
+fx_status check_ptr(const void* ptr, const char* what) {
+    if (!ptr) {
+        set_error(std::string(what) + " is NULL");
+        return FX_EINVAL;
+    }
+    return FX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fx_status fx_problem_init(fx_problem* p) {
+    if (!p) return FX_EINVAL;
+    std::memset(p, 0, sizeof(*p));
+    p->ndim = 1;
+    for (int j = 0; j < FX_MAX_DIM; ++j) {
+        p->shape[j] = 1;
+        p->dx[j] = 1.0;
+        p->a[j] = NAN;
+        p->abar[j] = NAN;
+        p->lambda[j] = 1;
+    }
+    p->m_over_hbar = 1.0;
+    p->t_flight = 0.0;
+    p->precision = FX_PREC_C128;
+    p->schedule = FX_SCHED_PAPER;
+    return FX_OK;
+}
+
+fx_status fx_plan_create(const fx_problem* prob, fx_plan** out) {
+    if (!out) { set_error("out is NULL"); return FX_EINVAL; }
+    fx_status s = validate(prob);
+    if (s != FX_OK) return s;
+    if (const char* inj = std::getenv("FX_FAULT_INJECT_PLAN")) {
+        if (inj[0] == '1') { set_error("plan creation failed by FX_FAULT_INJECT_PLAN"); return FX_ENOMEM; }
+    }
+    fx_plan* p = new (std::nothrow) fx_plan();
+    if (!p) { set_error("host allocation failed"); return FX_ENOMEM; }
+    p->prob = *prob;
+    p->dbl = (prob->precision == FX_PREC_C128);
+    p->ndim = prob->ndim;
+    p->schedule = prob->schedule;
+    const int off = 3 - prob->ndim;
+    std::vector<AxisTables> tabs(3);
+    for (int pa = 0; pa < 3; ++pa) {
+        AxisParams ap;
+        if (pa >= off) {
+            const int j = pa - off;
+            ap.M = prob->shape[j];
+            ap.lam = prob->lambda[j];
+            ap.dx = prob->dx[j];
+            const double L = (double)ap.M * ap.dx;
+            ap.a = std::isnan(prob->a[j]) ? -0.5 * L : prob->a[j];
+            ap.abar = std::isnan(prob->abar[j]) ? ap.a + (1.0 - (double)ap.lam) * L / 2.0 : prob->abar[j];
+            p->prob.a[j] = ap.a;
+            p->prob.abar[j] = ap.abar;
+        }
+        ap.t = prob->t_flight;
+        ap.m_over_hbar = prob->m_over_hbar;
+        p->par[pa] = ap;
+        p->len[pa] = ap.M;
+        AxisDev& ad = p->ax[pa];
+        ad.M = (int)ap.M;
+        ad.lam = ap.lam;
+        ad.g = (int)gcd64(ap.lam, ap.M);
+        ad.P = ad.M / ad.g;
+        ad.lg = (int)((ap.lam / ad.g) % ad.P);
+        ad.lg_inv = (int)modinv(ad.lg, ad.P);
+        ad.scale = 1.0 / (double)ap.M;
+        ad.fm = make_radix_plan(ad.M);
+        ad.fp = make_radix_plan(ad.P);
+        tabs[pa] = build_axis_tables(ap);
+        if (!(ap.M == 1 && ap.lam == 1)) p->act[p->nact++] = pa;
+    }
+    p->M = p->len[0] * p->len[1] * p->len[2];
+    p->Q = (int64_t)p->ax[0].lam * p->ax[1].lam * p->ax[2].lam;
+    for (int i = 0; i < p->nact; ++i) {
+        const int M = p->ax[p->act[i]].M;
+        const size_t lds = pass_lds_bytes(Kind::EA, p->dbl, 1, M);
+        if ((int64_t)lds > lds_limit_bytes()) {
+            set_error("axis too long for the in-LDS transform at this precision");
+            delete p;
+            return FX_EUNSUPPORTED;
+        }
+    }
+    // Upload all tables in one allocation: per axis TA | TB | Tf | tw.
+    const size_t cs = csize(p);
+    size_t total = 0;
+    size_t offs[3][4];
+    for (int pa = 0; pa < 3; ++pa) {
+        const size_t lm = (size_t)p->ax[pa].lam * p->ax[pa].M;
+        const size_t sz[4] = {lm, lm, lm, (size_t)p->ax[pa].M};
+        for (int t = 0; t < 4; ++t) {
+            offs[pa][t] = total;
+            total += ((sz[t] * cs + 255) / 256) * 256;
+        }
+    }
+    std::vector<unsigned char> host(total, 0);
+    for (int pa = 0; pa < 3; ++pa) {
+        const std::vector<double>* src[4] = {&tabs[pa].TA, &tabs[pa].TB, &tabs[pa].Tf, &tabs[pa].tw};
+        for (int t = 0; t < 4; ++t) {
+            if (p->dbl) to_prec<double>(*src[t], host, offs[pa][t]);
+            else to_prec<float>(*src[t], host, offs[pa][t]);
+        }
+    }
+    if (hipMalloc(&p->dtab, total) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of tables failed (no device?)");
+        delete p;
+        return FX_EDEVICE;
+    }
+    p->dtab_bytes = total;
+    if (hipMemcpy(p->dtab, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("table upload failed");
+        (void)hipFree(p->dtab);
+        delete p;
+        return FX_EDEVICE;
+    }
+    for (int pa = 0; pa < 3; ++pa) {
+        char* b = (char*)p->dtab;
+        p->ax[pa].TA = b + offs[pa][0];
+        p->ax[pa].TB = b + offs[pa][1];
+        p->ax[pa].Tf = b + offs[pa][2];
+        p->ax[pa].tw = b + offs[pa][3];
+    }
+    size_t budget = (size_t)8 << 30;
+    if (const char* e = std::getenv("FX_WORKSPACE_MB")) budget = (size_t)std::max(1L, std::atol(e)) << 20;
+    size_t freeb = 0, totb = 0;
+    if (hipMemGetInfo(&freeb, &totb) == hipSuccess && freeb / 4 < budget) budget = std::max<size_t>(freeb / 4, 1 << 20);
+    p->budget = budget;
+    if (const char* e = std::getenv("FX_TILE_POINTS")) p->ts_target = std::max(1, std::atoi(e));
+    plan_setup_workspace(p, 1);
+    *out = p;
+    return FX_OK;
+}
+
+fx_status fx_plan_destroy(fx_plan* p) {
+    if (!p) return FX_OK;
+    if (p->ws_owned && p->ws) (void)hipFree(p->ws);
+    if (p->dtab) (void)hipFree(p->dtab);
+    delete p;
+    return FX_OK;
+}
+
+fx_status fx_plan_num_terms(const fx_plan* p, int64_t* q) {
+    if (!p || !q) { set_error("NULL argument"); return FX_EINVAL; }
+    *q = p->Q;
+    return FX_OK;
+}
+
+fx_status fx_plan_workspace_size(const fx_plan* p, size_t* bytes) {
+    if (!p || !bytes) { set_error("NULL argument"); return FX_EINVAL; }
+    *bytes = p->ws_need;
+    return FX_OK;
+}
+
+fx_status fx_plan_set_workspace(fx_plan* p, void* dev_ptr, size_t bytes) {
+    if (!p) { set_error("plan is NULL"); return FX_EINVAL; }
+    if (dev_ptr == nullptr && bytes == 0) {
+        if (!p->ws_owned) { p->ws = nullptr; p->ws_bytes = 0; }
+        return FX_OK;
+    }
+    if (!dev_ptr) { set_error("workspace pointer is NULL"); return FX_EINVAL; }
+    if (((uintptr_t)dev_ptr) % 256 != 0) { set_error("workspace must be 256-byte aligned"); return FX_EINVAL; }
+    if (bytes < p->ws_need) { set_error("workspace smaller than fx_plan_workspace_size()"); return FX_ENOMEM; }
+    if (p->ws_owned && p->ws) (void)hipFree(p->ws);
+    p->ws = dev_ptr;
+    p->ws_bytes = bytes;
+    p->ws_owned = false;
+    return FX_OK;
+}
+
+fx_status fx_expand(fx_plan* p, const void* psi0, void* psi_out, void* rho_out, void* stream) {
+    if (!p) { set_error("plan is NULL"); return FX_EINVAL; }
+    fx_status s = check_ptr(psi0, "psi0");
+    if (s != FX_OK) return s;
+    if (!psi_out && !rho_out) { set_error("psi_out and rho_out are both NULL"); return FX_EINVAL; }
+    if (p->slices != 1) plan_setup_workspace(p, 1);
+    if ((s = ensure_workspace(p)) != FX_OK) return s;
+    void* dst = psi_out ? psi_out : (char*)p->ws + (size_t)2 * p->buf_elems * csize(p);
+    int qb[3] = {0, 0, 0}, qn[3] = {p->ax[0].lam, p->ax[1].lam, p->ax[2].lam};
+    return run_box(p, qb, qn, psi0, dst, 0, rho_out, false, (hipStream_t)stream);
+}
+
+fx_status fx_expand_range(fx_plan* p, const void* psi0, void* psi_acc, int64_t q_begin, int64_t q_end,
+                          int accumulate, void* stream) {
+    if (!p) { set_error("plan is NULL"); return FX_EINVAL; }
+    fx_status s = check_ptr(psi0, "psi0");
+    if (s != FX_OK) return s;
+    if ((s = check_ptr(psi_acc, "psi_acc")) != FX_OK) return s;
+    if (q_begin < 0 || q_end < q_begin || q_end > p->Q) { set_error("need 0 <= q_begin <= q_end <= terms"); return FX_EINVAL; }
+    if (p->schedule != FX_SCHED_PAPER) { set_error("term ranges exist only for the paper schedule"); return FX_EUNSUPPORTED; }
+    if (p->slices != 1) plan_setup_workspace(p, 1);
+    if ((s = ensure_workspace(p)) != FX_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if (q_begin == q_end) {
+        if (!accumulate) FX_TRY_HIP(hipMemsetAsync(psi_acc, 0, (size_t)p->M * csize(p), st));
+        return FX_OK;
+    }
+    // Linear index: C order over the active axes from the contiguous (slowest-varying index) to axis 0.
+    const int k = p->nact;
+    if (k == 0) {
+        const int zb[3] = {0, 0, 0}, on[3] = {1, 1, 1};
+        return run_box(p, zb, on, psi0, psi_acc, accumulate, nullptr, false, st);
+    }
+    // levels: outermost first
+    int lev[3];
+    for (int i = 0; i < k; ++i) lev[i] = p->act[k - 1 - i];
+    // Recursive decomposition of [qb, qe) into boxes.
+    struct Box { int qb[3]; int qn[3]; };
+    std::vector<Box> boxes;
+    std::function<void(int, int64_t, int64_t, Box)> rec = [&](int level, int64_t b, int64_t e, Box pre) {
+        if (b >= e) return;
+        const int ax = lev[level];
+        int64_t inner = 1;
+        for (int i = level + 1; i < k; ++i) inner *= p->ax[lev[i]].lam;
+        if (level == k - 1) {
+            Box bx = pre;
+            bx.qb[ax] = (int)b;
+            bx.qn[ax] = (int)(e - b);
+            boxes.push_back(bx);
+            return;
+        }
+        int64_t hb = b / inner, he = e / inner;
+        if (hb == he) {
+            Box bx = pre;
+            bx.qb[ax] = (int)hb;
+            bx.qn[ax] = 1;
+            rec(level + 1, b - hb * inner, e - hb * inner, bx);
+            return;
+        }
+        if (b % inner) {
+            Box bx = pre;
+            bx.qb[ax] = (int)hb;
+            bx.qn[ax] = 1;
+            rec(level + 1, b - hb * inner, inner, bx);
+            hb += 1;
+        }
+        if (he > hb) {
+            Box bx = pre;
+            bx.qb[ax] = (int)hb;
+            bx.qn[ax] = (int)(he - hb);
+            for (int i = level + 1; i < k; ++i) {
+                bx.qb[lev[i]] = 0;
+                bx.qn[lev[i]] = p->ax[lev[i]].lam;
+            }
+            boxes.push_back(bx);
+        }
+        if (e % inner) {
+            Box bx = pre;
+            bx.qb[ax] = (int)he;
+            bx.qn[ax] = 1;
+            rec(level + 1, 0, e - he * inner, bx);
+        }
+    };
+    Box root;
+    for (int i = 0; i < 3; ++i) { root.qb[i] = 0; root.qn[i] = 1; }
+    rec(0, q_begin, q_end, root);
+    for (size_t i = 0; i < boxes.size(); ++i) {
+        s = run_box(p, boxes[i].qb, boxes[i].qn, psi0, psi_acc, (i == 0) ? accumulate : 1, nullptr, false, st);
+        if (s != FX_OK) return s;
+    }
+    return FX_OK;
+}
+
+fx_status fx_density(fx_plan* p, const void* psi, void* rho, void* stream) {
+    if (!p) { set_error("plan is NULL"); return FX_EINVAL; }
+    fx_status s = check_ptr(psi, "psi");
+    if (s != FX_OK) return s;
+    if ((s = check_ptr(rho, "rho")) != FX_OK) return s;
+    if (launch_density(p->dbl, psi, rho, p->M, (hipStream_t)stream) != hipSuccess) {
+        set_error("density launch failed");
+        return FX_EDEVICE;
+    }
+    return FX_OK;
+}
+
+fx_status fx_column_density(fx_plan* p, const void* rho, int axis, void* image, void* stream) {
+    if (!p) { set_error("plan is NULL"); return FX_EINVAL; }
+    fx_status s = check_ptr(rho, "rho");
+    if (s != FX_OK) return s;
+    if ((s = check_ptr(image, "image")) != FX_OK) return s;
+    if (axis < 0 || axis >= p->ndim) { set_error("axis out of range"); return FX_EINVAL; }
+    const int pa = axis + (3 - p->ndim);
+    int64_t A = 1, S = 1;
+    for (int i = 0; i < pa; ++i) A *= p->len[i];
+    for (int i = pa + 1; i < 3; ++i) S *= p->len[i];
+    const double w = (double)p->par[pa].lam * p->par[pa].dx;
+    if (launch_column(p->dbl, rho, image, A, p->len[pa], S, w, (hipStream_t)stream) != hipSuccess) {
+        set_error("column density launch failed");
+        return FX_EDEVICE;
+    }
+    return FX_OK;
+}
+
+fx_status fx_expand_adjoint(fx_plan* p, const void* grad_out, void* grad_in, void* stream) {
+    if (!p) { set_error("plan is NULL"); return FX_EINVAL; }
+    fx_status s = check_ptr(grad_out, "grad_psi_out");
+    if (s != FX_OK) return s;
+    if ((s = check_ptr(grad_in, "grad_psi0")) != FX_OK) return s;
+    if (p->slices != 1) plan_setup_workspace(p, 1);
+    if ((s = ensure_workspace(p)) != FX_OK) return s;
+    int qb[3] = {0, 0, 0}, qn[3] = {p->ax[0].lam, p->ax[1].lam, p->ax[2].lam};
+    return run_box(p, qb, qn, grad_out, grad_in, 0, nullptr, true, (hipStream_t)stream);
+}
+
+fx_status fx_plan_describe(const fx_plan* p, char* buf, size_t len) {
+    if (!p || !buf || len == 0) { set_error("NULL argument"); return FX_EINVAL; }
+    int qb[3] = {0, 0, 0}, qn[3] = {p->ax[0].lam, p->ax[1].lam, p->ax[2].lam};
+    if (p->nact > 0 && p->schedule == FX_SCHED_PAPER) qn[p->act[p->nact - 1]] = (int)p->nb_outer;
+    std::vector<Op> ops = build_ops(p, qb, qn, p->slices, false);
+    std::string s = "{\"schedule\":\"";
+    s += (p->schedule == FX_SCHED_PAPER) ? "paper" : "axis_factorised";
+    s += "\",\"precision\":\"";
+    s += p->dbl ? "c128" : "c64_phase64";
+    s += "\",\"terms\":" + std::to_string(p->Q) + ",\"outer_block\":" + std::to_string(p->nb_outer) +
+         ",\"workspace_bytes\":" + std::to_string(p->ws_need) + ",\"passes\":[";
+    static const char* names[] = {"E", "A", "EA", "EH", "AH", "EAH"};
+    for (size_t i = 0; i < ops.size(); ++i) {
+        const Op& o = ops[i];
+        const AxisDev& a = p->ax[o.axis];
+        char tmp[256];
+        std::snprintf(tmp, sizeof(tmp),
+                      "%s{\"kind\":\"%s\",\"axis\":%d,\"M\":%d,\"P\":%d,\"lam\":%d,\"Qin\":%lld,\"A\":%lld,"
+                      "\"S\":%lld,\"TS\":%d}",
+                      i ? "," : "", names[(int)o.kind], o.axis - (3 - p->ndim), a.M, a.P, a.lam,
+                      (long long)o.g.Qin, (long long)o.g.A, (long long)o.g.S, o.g.TS);
+        s += tmp;
+    }
+    s += "]}";
+    std::snprintf(buf, len, "%s", s.c_str());
+    return FX_OK;
+}
+
+fx_status fx_batch_create(const fx_problem* probs, int32_t n, fx_batch** out);
+fx_status fx_batch_destroy(fx_batch* b);
+fx_status fx_batch_run(fx_batch* b, const void* const* psi0, void* const* psi_out, void* const* rho_out, void* stream);
+
+const char* fx_status_string(fx_status s) {
+    switch (s) {
+        case FX_OK: return "FX_OK";
+        case FX_EINVAL: return "FX_EINVAL: invalid argument";
+        case FX_ENOMEM: return "FX_ENOMEM: out of memory or workspace too small";
+        case FX_EDEVICE: return "FX_EDEVICE: HIP runtime or kernel error";
+        case FX_EUNSUPPORTED: return "FX_EUNSUPPORTED: outside what this build supports";
+    }
+    return "unknown fx_status";
+}
+
+const char* fx_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// Internal declarations shared by the host runtime (fx.cpp, tables.cpp) and the
+// HIP kernels (kernels.hip). Not part of the public ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime_api.h>
+
+#include "../../include/fx.h"
+
+namespace fx {
+
+constexpr int kMaxStages = 24;     // radix stages of one in-LDS transform
+constexpr int kThreads = 256;      // threads per workgroup of every pass kernel
+constexpr int kMaxTilePoints = 4096;  // TS * M of one tile (accumulator registers cap)
+
+// Mixed-radix factorisation of one transform length (Stockham, natural order out).
+struct RadixPlan {
+    int n = 1;
+    int nst = 0;
+    int rad[kMaxStages] = {0};
+};
+
+RadixPlan make_radix_plan(int n);
+
+// Per-axis device view of the method's tables, for data type T (float or double).
+// Table layout: [lam][M] complex, row q.
+//   TA[q][n]  = exp(-i alpha_q (x_n - a))                         (presA premultiply)
+//   TB[q][m]  = exp(i k_m (abar - a - (k_m + 2 alpha_q) hbar t/2m))  (presB chirp, umklapp applied)
+//   Tf[q][nb] = (1/lam) exp(i alpha_q (xbar_nb - a - alpha_q hbar t/2m))  (presf twiddle)
+//   tw[k]     = exp(-2 pi i k / M), k < M                         (FFT roots)
+struct AxisDev {
+    const void* TA = nullptr;
+    const void* TB = nullptr;
+    const void* Tf = nullptr;
+    const void* tw = nullptr;
+    int M = 1;        // axis length
+    int P = 1;        // M / g: number of distinct n'' values (output-pruned length)
+    int g = 1;        // gcd(lam, M)
+    int lam = 1;
+    int lg = 1;       // (lam / g) mod P: n'' = g * ((nb * lg) mod P)
+    int lg_inv = 0;   // inverse of lg modulo P: nb0(r) = (r * lg_inv) mod P
+    double scale = 1; // 1 / M
+    RadixPlan fm;     // radix plan of length M
+    RadixPlan fp;     // radix plan of length P
+};
+
+// Geometry of one pass along an axis of a tensor laid out as [Qin][A][L][S].
+struct PassGeom {
+    int64_t Qin = 1;   // leading slice count of the input
+    int64_t A = 1;     // product of the lengths before the axis
+    int64_t S = 1;     // product of the lengths after the axis (stride of the line)
+    int qb = 0;        // first magnification index handled along this axis
+    int qn = 1;        // number of magnification indices handled
+    int TS = 1;        // lines per workgroup tile
+    int64_t ntiles = 1;  // tiles per (slice, q)
+};
+
+enum class Kind { E, A, EA, EH, AH, EAH };
+
+struct KernelCfg {
+    int ts_target = 2048;  // preferred TS*L points per tile
+};
+
+// Kernel launchers (kernels.hip). All return hipSuccess or the launch error.
+hipError_t launch_pass(Kind kind, bool dbl, const void* in, void* out, const AxisDev& ax,
+                       const PassGeom& g, int accumulate, void* rho, hipStream_t st);
+hipError_t launch_density(bool dbl, const void* psi, void* rho, int64_t n, hipStream_t st);
+hipError_t launch_column(bool dbl, const void* rho, void* img, int64_t A, int64_t L, int64_t S,
+                         double w, hipStream_t st);
+hipError_t launch_gather(bool dbl, const void* const* srcs, void* dst, int64_t n_each, int count,
+                         hipStream_t st);
+hipError_t launch_scatter(bool dbl, const void* src, void* const* dsts, int64_t n_each, int count,
+                          int want_rho, void* const* rhos, hipStream_t st);
+size_t pass_lds_bytes(Kind kind, bool dbl, int TS, int M);
+int lds_limit_bytes();
+
+// Host-built FP64 tables (tables.cpp).
+struct AxisTables {
+    std::vector<double> TA, TB, Tf, tw;  // interleaved re,im; [lam][M] for TA/TB/Tf, [M] for tw
+};
+struct AxisParams {
+    int64_t M = 1;
+    int lam = 1;
+    double dx = 1, a = 0, abar = 0;
+    double t = 0, m_over_hbar = 1;
+};
+AxisTables build_axis_tables(const AxisParams& p);
+
+void set_error(const std::string& msg);
+
+}  // namespace fx

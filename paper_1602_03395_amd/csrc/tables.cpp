@@ -1,0 +1,105 @@
+// FP64 phase tables of the prescription (FF), section 5.2, one set per axis.
+//
+// Every phase is written in cycles (units of 2 pi) as a sum of
+//   * an exact rational part (integer numerator reduced modulo its integer
+//     denominator in int64),
+//   * a small fractional-offset part (|value| <= 1/2 by construction), and
+//   * a quadratic part beta * I with beta = pi hbar t / (m lam^2 L^2) and an
+//     exact integer I; beta is carried as a double-double (computed in long
+//     double) and beta_hi * I is split exactly with an FMA two-product, so the
+//     product is reduced modulo 1 without losing the fractional digits that a
+//     large chirp argument would otherwise swamp.
+// Only the reduced phase (|c| <= 1/2 cycle) goes through sin/cos.
+//
+// With k = dk * l~ (eq. (kj)), alpha_q = q dk / lam, delta = (abar - a)/dx and
+// ell = lam * l~ + q (the fine-lattice wave number of eq. (ulk)):
+//   TA[q][n]   : -alpha_q (x_n - a)                      = -(q n) / (lam M)
+//   TB[q][m~]  : k (abar - a) - k (k + 2 alpha_q) ht/2m  = l~ delta / M - beta (ell^2 - q^2)
+//   Tf[q][nb]  : alpha_q (xbar - a) - alpha_q^2 ht/2m    = q (delta + lam nb) / (lam M) - beta q^2
+// For odd M the largest positive coarse wave number is folded to the negative
+// side when q >= lam/2 (the umklapp rule stated after (FF)).
+#include <cmath>
+#include <cstdint>
+
+#include "fx_internal.h"
+
+namespace fx {
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+inline double reduce_cycles(double c) { return c - std::nearbyint(c); }
+
+// (num mod den) / den in [-1/2, 1/2], exact up to the final division.
+inline double rational_cycles(int64_t num, int64_t den) {
+    int64_t r = num % den;
+    if (r < 0) r += den;
+    if (2 * r > den) r -= den;
+    return (double)r / (double)den;
+}
+
+struct DD { double hi, lo; };
+
+// frac(beta * I) for the double-double beta and an integer I below 2^53.
+inline double beta_cycles(DD beta, int64_t I) {
+    const double x = (double)I;
+    const double p = beta.hi * x;
+    const double e = std::fma(beta.hi, x, -p);  // p + e == beta.hi * x exactly
+    return reduce_cycles(reduce_cycles(p) + e + beta.lo * x);
+}
+
+inline void put(std::vector<double>& v, size_t i, double cycles, double amp) {
+    const double ang = kTwoPi * reduce_cycles(cycles);
+    v[2 * i] = amp * std::cos(ang);
+    v[2 * i + 1] = amp * std::sin(ang);
+}
+
+}  // namespace
+
+AxisTables build_axis_tables(const AxisParams& p) {
+    const int64_t M = p.M;
+    const int64_t lam = p.lam;
+    const int64_t N = lam * M;
+    AxisTables t;
+    t.TA.resize(2 * (size_t)(lam * M));
+    t.TB.resize(2 * (size_t)(lam * M));
+    t.Tf.resize(2 * (size_t)(lam * M));
+    t.tw.resize(2 * (size_t)M);
+
+    // beta = pi * (t / (m/hbar)) / (lam * M * dx)^2 in long double, split into hi + lo.
+    const long double pi_l = 3.14159265358979323846264338327950288L;
+    const long double Lb = (long double)N * (long double)p.dx;
+    const long double beta_l = pi_l * ((long double)p.t / (long double)p.m_over_hbar) / (Lb * Lb);
+    DD beta;
+    beta.hi = (double)beta_l;
+    beta.lo = (double)(beta_l - (long double)beta.hi);
+
+    const double delta = (p.abar - p.a) / p.dx;
+    const double di_d = std::nearbyint(delta);
+    const int64_t di = (int64_t)di_d;
+    const double df = delta - di_d;
+
+    for (int64_t q = 0; q < lam; ++q) {
+        for (int64_t n = 0; n < M; ++n) {
+            const size_t i = (size_t)(q * M + n);
+            // TA: -(q n)/(lam M)
+            put(t.TA, i, -rational_cycles(q * n, N), 1.0);
+            // TB: coarse wave number of eq. (kj) with the odd-M umklapp.
+            int64_t lt = (2 * n < M) ? n : n - M;
+            if ((M % 2 == 1) && (2 * n == M - 1) && (2 * q >= lam)) lt -= M;
+            const int64_t ell = lam * lt + q;
+            const int64_t I = ell * ell - q * q;
+            const double tb = rational_cycles(lt * di, M) + (double)lt * df / (double)M
+                              - beta_cycles(beta, I);
+            put(t.TB, i, tb, 1.0);
+            // Tf: q (delta + lam nb)/(lam M) - beta q^2, amplitude 1/lam.
+            const double tf = rational_cycles(q * (di + lam * n), N) + (double)q * df / (double)N
+                              - beta_cycles(beta, q * q);
+            put(t.Tf, i, tf, 1.0 / (double)lam);
+        }
+    }
+    for (int64_t k = 0; k < M; ++k) put(t.tw, (size_t)k, -rational_cycles(k, M), 1.0);
+    return t;
+}
+
+}  // namespace fx

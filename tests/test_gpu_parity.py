@@ -1,0 +1,224 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle on the same seeded inputs.
+
+Bars (written per result):
+  * plain FP64 (complex128):            relative L2 error of Psibar and of rho <= 1e-12
+  * FP32 data + FP64-built phase tables: relative L2 error of rho <= 1e-5
+    (the oracle consumes the complex64 input upcast exactly, so input rounding
+    is not charged to the method).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32_RHO = 1e-5
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def say(*args):
+    print(*args, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1602_03395_amd as m
+    return m
+
+
+CASES = [
+    # shape, lam, dx, t, m_over_hbar, abar shift (units of dx)
+    ((64,), (5,), (0.5,), 3.0, 1.0, 0.0),
+    ((96,), (8,), (1.0,), 40.0, 1.0, 0.25),
+    ((45,), (4,), (1.0,), 20.0, 1.3, 0.3),
+    ((7,), (3,), (0.7,), 2.0, 1.0, -0.4),
+    ((1024,), (10,), (0.1,), 50.0, 1.0, 0.0),
+    ((48, 40), (3, 4), (1.0, 0.8), 30.0, 1.0, 0.37),
+    ((33, 20), (2, 5), (1.0, 1.0), 12.0, 2.0, 0.0),
+    ((64, 64), (8, 16), (1.0, 1.0), 200.0, 1.0, 0.0),
+    ((17, 12), (1, 3), (1.0, 1.0), 5.0, 1.0, 0.5),
+    ((12, 10, 16), (2, 3, 4), (1.0, 1.0, 1.0), 9.0, 1.0, 0.2),
+    ((9, 8, 20), (3, 2, 5), (1.0, 0.5, 1.0), 6.0, 1.0, 0.0),
+    ((5, 1, 24), (2, 1, 3), (1.0, 1.0, 1.0), 4.0, 1.0, 0.0),
+    ((1, 8), (3, 2), (1.0, 1.0), 3.0, 1.0, 0.0),
+    ((16, 384), (2, 3), (1.0, 1.0), 50.0, 1.0, 0.0),
+    ((3,), (1,), (1.0,), 1.0, 1.0, 0.0),
+]
+
+
+def _run(fx, psi_np, dtype, lam, dx, t, moh, a, abar, schedule):
+    psi = torch.from_numpy(psi_np.astype(np.complex128 if dtype == torch.complex128 else np.complex64)).cuda()
+    plan = fx.get_plan(psi.shape, dx, moh, t, lam, a, abar, dtype, schedule)
+    out, rho = plan.expand(psi)
+    torch.cuda.synchronize()
+    return psi, out.cpu().numpy(), rho.cpu().numpy()
+
+
+@pytest.mark.parametrize("schedule", ["paper", "axis_factorised"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_small_cases_fp64(fx, case, schedule):
+    shape, lam, dx, t, moh, shift = CASES[case]
+    say("case", shape, lam, schedule, "fp64")
+    psi_np = workloads.random_field(shape, 100 + case)
+    a, abar = oracle.default_offsets(shape, dx, lam)
+    abar = abar + shift * np.asarray(dx)
+    ref = oracle.expand(psi_np, dx, moh, t, lam, a, abar)
+    _, out, rho = _run(fx, psi_np, torch.complex128, lam, dx, t, moh, list(a), list(abar), schedule)
+    e_psi = rel(out, ref)
+    e_rho = rel(rho, oracle.density(ref))
+    say(f"  rel L2 psi {e_psi:.2e}  rho {e_rho:.2e}")
+    assert e_psi <= TOL64 and e_rho <= TOL64
+
+
+@pytest.mark.parametrize("schedule", ["paper", "axis_factorised"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_small_cases_fp32_phase64(fx, case, schedule):
+    shape, lam, dx, t, moh, shift = CASES[case]
+    say("case", shape, lam, schedule, "fp32")
+    psi_np = workloads.random_field(shape, 200 + case).astype(np.complex64)
+    a, abar = oracle.default_offsets(shape, dx, lam)
+    abar = abar + shift * np.asarray(dx)
+    ref = oracle.expand(psi_np.astype(np.complex128), dx, moh, t, lam, a, abar)
+    _, out, rho = _run(fx, psi_np, torch.complex64, lam, dx, t, moh, list(a), list(abar), schedule)
+    e_rho = rel(rho, oracle.density(ref))
+    e_psi = rel(out, ref)
+    say(f"  rel L2 rho {e_rho:.2e}  psi {e_psi:.2e}")
+    assert e_rho <= TOL32_RHO
+
+
+def test_expand_range_partitions_sum_to_full(fx):
+    shape, lam, dx, t = (10, 12, 16), (2, 3, 4), (1.0, 1.0, 1.0), 7.0
+    say("expand_range", shape, lam)
+    psi_np = workloads.random_field(shape, 7)
+    psi = torch.from_numpy(psi_np).cuda()
+    plan = fx.get_plan(shape, dx, 1.0, t, lam)
+    Q = plan.num_terms()
+    assert Q == 24
+    full, _ = plan.expand(psi)
+    acc = torch.zeros_like(psi)
+    cuts = [0, 1, 5, 6, 11, 12, 13, 23, 24]
+    for b, e in zip(cuts[:-1], cuts[1:]):
+        plan.expand_range(psi, acc, b, e, accumulate=True)
+    torch.cuda.synchronize()
+    assert rel(acc.cpu().numpy(), full.cpu().numpy()) <= 1e-13
+    part = torch.empty_like(psi)
+    plan.expand_range(psi, part, 0, 13, accumulate=False)
+    plan.expand_range(psi, part, 13, 24, accumulate=True)
+    assert rel(part.cpu().numpy(), full.cpu().numpy()) <= 1e-13
+    ref = oracle.expand(psi_np, dx, 1.0, t, lam)
+    assert rel(acc.cpu().numpy(), ref) <= TOL64
+
+
+@pytest.mark.parametrize("schedule", ["paper", "axis_factorised"])
+@pytest.mark.parametrize("shape,lam", [((40,), (6,)), ((24, 18), (3, 4)), ((8, 9, 12), (2, 3, 2))])
+def test_adjoint_matches_oracle(fx, shape, lam, schedule):
+    say("adjoint", shape, lam, schedule)
+    dx = tuple(1.0 for _ in shape)
+    y_np = workloads.random_field(shape, 31)
+    x_np = workloads.random_field(shape, 32)
+    plan = fx.get_plan(shape, dx, 1.0, 5.0, lam, schedule=schedule)
+    y = torch.from_numpy(y_np).cuda()
+    x = torch.from_numpy(x_np).cuda()
+    g = plan.expand_adjoint(y).cpu().numpy()
+    ref = oracle.expand_adjoint(y_np, dx, 1.0, 5.0, lam)
+    assert rel(g, ref) <= TOL64
+    ux, _ = plan.expand(x)
+    lhs = np.vdot(ux.cpu().numpy(), y_np)
+    rhs = np.vdot(x_np, g)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_autograd_gradient_matches_oracle_and_fd(fx):
+    shape, lam, dx, t = (16, 20), (3, 2), (1.0, 1.0), 6.0
+    say("autograd", shape, lam)
+    psi_np = workloads.random_field(shape, 41)
+    tau = np.abs(workloads.random_field(shape, 42)) ** 2 * 0.05
+    psi = torch.from_numpy(psi_np).cuda().requires_grad_(True)
+    tau_t = torch.from_numpy(tau).cuda()
+    rho = fx.expand_density(psi, dx, 1.0, t, lam)
+    loss = ((rho - tau_t) ** 2).sum()
+    loss.backward()
+    g = psi.grad.cpu().numpy()
+    loss_ref, g_ref = oracle.loss_and_grad(psi_np, tau, dx, 1.0, t, lam)
+    assert abs(loss.item() - loss_ref) <= 1e-12 * abs(loss_ref)
+    assert rel(g, g_ref) <= 1e-12
+    # central finite differences (h = 1e-3) on a few components
+    h = 1e-3
+    rng = np.random.default_rng(3)
+    for _ in range(4):
+        i = tuple(int(rng.integers(0, s)) for s in shape)
+        for unit, comp in ((1.0, g[i].real), (1j, g[i].imag)):
+            vals = []
+            for sgn in (+1, -1):
+                pp = psi_np.copy()
+                pp[i] += sgn * h * unit
+                r = fx.expand_density(torch.from_numpy(pp).cuda(), dx, 1.0, t, lam)
+                vals.append(((r - tau_t) ** 2).sum().item())
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert abs(fd - comp) <= 1e-6 * max(1.0, abs(comp))
+
+
+def test_autograd_gradcheck_tiny(fx):
+    say("gradcheck")
+    psi = torch.from_numpy(workloads.random_field((6, 5), 5)).cuda().requires_grad_(True)
+
+    def f(x):
+        return fx.expand_density(x, (1.0, 1.0), 1.0, 2.0, (2, 3))
+
+    assert torch.autograd.gradcheck(f, (psi,), eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_column_density_and_density(fx, dtype):
+    shape, lam, dx, t = (8, 12, 20), (3, 2, 4), (0.5, 1.0, 1.0), 4.0
+    say("column density", dtype)
+    psi_np = workloads.random_field(shape, 51)
+    psi = torch.from_numpy(psi_np).to(dtype).cuda()
+    plan = fx.get_plan(shape, dx, 1.0, t, lam, dtype=dtype)
+    out, rho = plan.expand(psi)
+    ref_rho = oracle.density(oracle.expand(psi.cpu().numpy().astype(np.complex128), dx, 1.0, t, lam))
+    tol = TOL64 if dtype == torch.complex128 else TOL32_RHO
+    for axis in range(3):
+        img = plan.column_density(rho, axis).cpu().numpy()
+        ref_img = oracle.column_density(ref_rho, axis, lam, dx)
+        assert rel(img, ref_img) <= tol
+    r2 = plan.density(out).cpu().numpy()
+    assert rel(r2, rho.cpu().numpy()) <= 1e-15 if dtype == torch.complex128 else 1e-7
+
+
+def test_torch_owned_workspace(fx):
+    shape, lam = (32, 24), (4, 3)
+    psi_np = workloads.random_field(shape, 61)
+    plan = fx.Plan(shape, (1.0, 1.0), 1.0, 10.0, lam)
+    plan.use_torch_workspace()
+    out, _ = plan.expand(torch.from_numpy(psi_np).cuda())
+    assert rel(out.cpu().numpy(), oracle.expand(psi_np, (1.0, 1.0), 1.0, 10.0, lam)) <= TOL64
+
+
+def test_small_workspace_budget_forces_blocking(fx, monkeypatch):
+    # a tiny budget makes the plan sum the outermost magnification index in several blocks
+    monkeypatch.setenv("FX_WORKSPACE_MB", "1")
+    shape, lam = (40, 64, 48), (3, 4, 6)
+    say("blocking", shape, lam)
+    psi_np = workloads.random_field(shape, 71)
+    plan = fx.Plan(shape, (1.0, 1.0, 1.0), 1.0, 8.0, lam)
+    import json
+    desc = json.loads(plan.describe())
+    assert desc["outer_block"] < 6
+    out, _ = plan.expand(torch.from_numpy(psi_np).cuda())
+    assert rel(out.cpu().numpy(), oracle.expand(psi_np, (1.0,) * 3, 1.0, 8.0, lam)) <= TOL64
