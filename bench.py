@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Throughput of the free-flight expansion (prescription (FF), section 5.2) on one MI355X.
+
+A step is one whole expansion of the workload's field: every q-term of (FFpsi)
+(premultiply, forward transform, chirp, pruned inverse, twiddle-gather-
+accumulate) and the density |Psibar|^2, with the input already resident in
+device memory. The default workload is the 2D 512x512 elongated
+quasicondensate, magnification 32 per axis (1024 terms), FP32 data with
+FP64-built phase tables.
+
+Prints one JSON line with the throughput in output lattice points per second,
+the roofline of the dominant pass (timed with HIP events on its own launch
+stream inside the timed region) and the CPU oracle timed on the host as a
+baseline.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+
+
+def pass_cost(p: dict, csize: int, outer_chunks: int = 1):
+    """Algorithmic flops and unique bytes of one launch of a pass (roofline model).
+
+    Counting convention: complex multiply 6 flops, complex add 2, complex
+    multiply-add 8, a length-N transform 5 N log2 N.
+    """
+    kind, M, P, lam = p["kind"], p["M"], p["P"], p["lam"]
+    qn = p.get("qn", lam)
+    lines = p["Qin"] * p["A"] * p["S"]
+    lg = lambda n: math.log2(n) if n > 1 else 0.0
+    e_line = 6 * M + 5 * M * lg(M) + 6 * M + 2 * (M - P) + 5 * P * lg(P) + 2 * P
+    if kind in ("E", "EH"):
+        flops = lines * qn * e_line
+        byts = (lines * M + lines * qn * P) * csize
+    elif kind in ("EA", "EAH"):
+        flops = lines * qn * (e_line + 8 * M) + lines * M * 2
+        byts = 2 * lines * M * csize
+    else:  # A, AH
+        outs = p["Qin"] * p["A"] * M * p["S"]
+        flops = outs * 8 * qn
+        byts = (outs + p["Qin"] * qn * p["A"] * P * p["S"]) * csize
+    return flops, byts
+
+
+def kernels_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1602_03395_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_key: str):
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernels_hash") != kernels_hash():
+        return None
+    ent = d.get("passes", {}).get(kernel_key)
+    if not ent:
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(wl, field, lam, dx, t):
+    import numpy as np
+
+    import oracle
+    from oracle import propagator as OP
+    OP._axis_matrix_cached.cache_clear()
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = min(threads, os.cpu_count() or threads)
+    t0 = time.perf_counter()
+    ref = oracle.expand(field.astype(np.complex128), dx, wl.m_over_hbar, t, lam)
+    rho = oracle.density(ref)
+    dt = time.perf_counter() - t0
+    return ref, rho, {"value": field.size / dt, "unit": "output lattice pts/s", "cores": threads,
+                      "kind": "oracle", "seconds": dt,
+                      "sample": f"one full field of the workload ({field.size} output points): per-axis "
+                                f"long-double kernel tables + FP64 per-axis contraction"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c5"])
+    ap.add_argument("--dtype", default=None, choices=[None, "c64", "c128"])
+    ap.add_argument("--schedule", default="paper", choices=["paper", "axis_factorised"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pass-timing", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(sharding over q-terms is described in DESIGN.md)"}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1602_03395_amd as fx
+    import workloads
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(3)
+
+    wl = workloads.make_workload(args.config)
+    if args.config == "c5":
+        wl.fields = wl.fields[:1]
+    dtype_name = args.dtype or wl.dtype
+    dtype = torch.complex64 if dtype_name == "c64" else torch.complex128
+    field = wl.fields[0].astype(np.complex64 if dtype_name == "c64" else np.complex128)
+    dx, lam, t = wl.dx, wl.lam, wl.t
+
+    dev = torch.device("cuda:0")
+    psi = torch.from_numpy(field).to(dev)
+    plan = fx.Plan(psi.shape, dx, wl.m_over_hbar, t, lam, dtype=dtype, schedule=args.schedule)
+    desc = json.loads(plan.describe())
+    out = torch.empty_like(psi)
+    rho = torch.empty(psi.shape, dtype=torch.float32 if dtype == torch.complex64 else torch.float64, device=dev)
+
+    for _ in range(args.warmup):
+        plan.expand(psi, psi_out=out, rho_out=rho)
+    torch.cuda.synchronize()
+
+    timing = not args.no_pass_timing
+    if timing:
+        plan.set_timing(True)
+        plan.pass_times()  # clear
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.expand(psi, psi_out=out, rho_out=rho)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_ms = ev0.elapsed_time(ev1)
+    passes = plan.pass_times() if timing else []
+    plan.set_timing(False)
+
+    ms_per_step = gpu_ms / args.steps
+    npts = int(np.prod(psi.shape))
+    value = npts / (ms_per_step * 1e-3)
+    terms = plan.num_terms()
+
+    csize = 8 if dtype == torch.complex64 else 16
+    peak_alu = PEAK_FP32_TFLOPS if dtype == torch.complex64 else PEAK_FP64_TFLOPS
+    ridge = peak_alu * 1e12 / (PEAK_HBM_GBS * 1e9)
+    pass_rows = []
+    for i, (n_launch, tot_ms) in enumerate(passes):
+        p = dict(desc["passes"][i]) if i < len(desc["passes"]) else {"kind": "?"}
+        avg_ms = tot_ms / max(n_launch, 1)
+        flops, byts = pass_cost(p, csize)
+        pass_rows.append({"pass": f'{p["kind"]}(axis{p.get("axis")})', "launches_per_step": n_launch / args.steps,
+                          "avg_ms": avg_ms, "flops": flops, "bytes": byts,
+                          "tflops": flops / (avg_ms * 1e-3) / 1e12, "gbs": byts / (avg_ms * 1e-3) / 1e9})
+    roofline = None
+    if pass_rows:
+        dom = max(pass_rows, key=lambda r: r["avg_ms"] * r["launches_per_step"])
+        ai = dom["flops"] / max(dom["bytes"], 1)
+        if ai >= ridge:
+            roofline = {"bound": "alu", "achieved": dom["tflops"], "peak": peak_alu, "unit": "TFLOP/s",
+                        "frac": dom["tflops"] / peak_alu}
+        else:
+            roofline = {"bound": "hbm", "achieved": dom["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": dom["gbs"] / PEAK_HBM_GBS}
+        roofline["kernel"] = dom["pass"]
+        roofline["traffic"] = load_traffic(dom["pass"])
+
+    result = {
+        "metric": "expanded lattice pts/s + HBM roofline %, FP32/FP64-phase vs FP64 at 1e-5 err",
+        "value": value,
+        "unit": "output lattice pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "wall_ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if dtype == torch.complex64 else "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "shape": list(psi.shape), "lam": list(lam), "dx": list(dx), "t": t,
+                   "terms": terms, "schedule": args.schedule,
+                   "precision": "c64_phase64" if dtype == torch.complex64 else "c128",
+                   "outer_block": desc["outer_block"]},
+        "q_term_pts_per_s": npts * terms / (ms_per_step * 1e-3),
+        "roofline": roofline,
+        "passes": pass_rows,
+    }
+
+    if not args.no_cpu_baseline:
+        ref, ref_rho, cb = cpu_baseline(wl, field, lam, dx, t)
+        result["cpu_baseline"] = cb
+        got = rho.cpu().numpy().astype(np.float64)
+        result["rel_l2_rho_vs_oracle"] = float(np.linalg.norm(got - ref_rho) / np.linalg.norm(ref_rho))
+        result["rel_l2_psi_vs_oracle"] = float(np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref))
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -196,6 +196,17 @@ fx_status fx_batch_destroy(fx_batch* batch);
 fx_status fx_batch_run(fx_batch* batch, const void* const* psi0, void* const* psi_out,
                        void* const* rho_out, void* stream);
 
+/*
+ * Per-pass timing (profiling aid). With enable != 0 every pass launch of this
+ * plan is bracketed by two HIP events recorded on the stream the pass is
+ * launched on. fx_plan_pass_times waits for the recorded events and returns,
+ * for each pass of the schedule in order (at most max entries; *n_passes gets
+ * the count), the number of timed launches and their summed duration in
+ * milliseconds, then clears the counters. Arrays are host memory.
+ */
+fx_status fx_plan_set_timing(fx_plan* plan, int enable);
+fx_status fx_plan_pass_times(fx_plan* plan, int32_t* n_passes, int64_t* launches, double* ms, int32_t max);
+
 /* Writes a one-line JSON description of the plan's schedule and tiling into buf. */
 fx_status fx_plan_describe(const fx_plan* plan, char* buf, size_t len);
 

@@ -3,7 +3,7 @@ magnified grid: the sum-of-FFTs prescription (FF) of arXiv:1602.03395,
 section 5.2, as hand-written HIP kernels behind the C ABI of ``include/fx.h``.
 
 Importing the package loads ``libfx.so`` from this directory and fails if it
-is missing; build it with ``python -m paper_1602_03395_amd.build``.
+is missing; build it with ``python paper_1602_03395_amd/build.py``.
 """
 
 from . import _lib  # noqa: F401  (loads libfx.so, raises if absent)

@@ -62,7 +62,7 @@ def _raise(status: int, where: str):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
-            f"{LIB_PATH} is missing: build it with `python -m paper_1602_03395_amd.build` "
+            f"{LIB_PATH} is missing: build it with `python paper_1602_03395_amd/build.py` "
             "(or __graft_entry__.build()); there is no CPU fallback.")
     lib = ctypes.CDLL(LIB_PATH)
     vp = ctypes.c_void_p
@@ -83,6 +83,9 @@ def _load():
         "fx_batch_destroy": (ctypes.c_int, [vp]),
         "fx_batch_run": (ctypes.c_int, [vp, P(vp), P(vp), P(vp), vp]),
         "fx_plan_describe": (ctypes.c_int, [vp, ctypes.c_char_p, ctypes.c_size_t]),
+        "fx_plan_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
+        "fx_plan_pass_times": (ctypes.c_int, [vp, P(ctypes.c_int32), P(ctypes.c_int64), P(ctypes.c_double),
+                                              ctypes.c_int32]),
         "fx_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "fx_last_error": (ctypes.c_char_p, []),
     }

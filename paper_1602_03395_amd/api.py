@@ -94,6 +94,18 @@ class Plan:
                 "fx_plan_set_workspace")
         self._ws = ws
 
+    def set_timing(self, enable: bool = True):
+        L.check(L.lib.fx_plan_set_timing(self._h, 1 if enable else 0), "fx_plan_set_timing")
+
+    def pass_times(self):
+        """[(launches, total_ms)] per pass of the schedule since the last call (waits for the events)."""
+        n = ctypes.c_int32()
+        cap = 64
+        la = (ctypes.c_int64 * cap)()
+        ms = (ctypes.c_double * cap)()
+        L.check(L.lib.fx_plan_pass_times(self._h, ctypes.byref(n), la, ms, cap), "fx_plan_pass_times")
+        return [(la[i], ms[i]) for i in range(min(n.value, cap))]
+
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(1 << 16)
         L.check(L.lib.fx_plan_describe(self._h, buf, len(buf)), "fx_plan_describe")

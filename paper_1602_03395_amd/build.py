@@ -1,6 +1,7 @@
 """Compile the HIP library ``libfx.so`` in-tree for gfx950.
 
-Usage: ``python -m paper_1602_03395_amd.build`` (or ``build()`` from Python).
+Usage: ``python paper_1602_03395_amd/build.py`` (or ``__graft_entry__.build()``); run it as a
+script, since importing the package loads the library.
 Packed FP32 instructions are disabled in device code
 (``-target-feature -packed-fp32-ops``); hipcc's host pass warns that it does
 not know the feature, which is harmless.

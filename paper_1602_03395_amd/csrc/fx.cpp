@@ -145,6 +145,13 @@ struct fx_plan {
     int schedule = FX_SCHED_PAPER;
     int ts_target = 2048;
     size_t budget = 0;
+    // per-pass timing
+    bool timing = false;
+    struct Pending { int op; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    std::vector<int64_t> t_launch;
+    std::vector<double> t_ms;
 };
 
 namespace {
@@ -337,8 +344,20 @@ fx_status run_ops(fx_plan* p, const std::vector<Op>& ops, const void* src, void*
         const bool last = (i + 1 == ops.size());
         void* out = last ? dst : bufs[i % 2];
         const Op& o = ops[i];
+        hipEvent_t ea = nullptr, eb = nullptr;
+        if (p->timing) {
+            for (hipEvent_t* ev : {&ea, &eb}) {
+                if (!p->pool.empty()) { *ev = p->pool.back(); p->pool.pop_back(); }
+                else FX_TRY_HIP(hipEventCreate(ev));
+            }
+            FX_TRY_HIP(hipEventRecord(ea, st));
+        }
         hipError_t e = launch_pass(o.kind, p->dbl, cur, out, p->ax[o.axis], o.g, last ? accumulate : 0,
                                    last ? rho : nullptr, st);
+        if (p->timing) {
+            FX_TRY_HIP(hipEventRecord(eb, st));
+            p->pending.push_back({(int)i, ea, eb});
+        }
         if (e != hipSuccess) {
             set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));
             return FX_EDEVICE;
@@ -518,6 +537,12 @@ fx_status fx_plan_create(const fx_problem* prob, fx_plan** out) {
 
 fx_status fx_plan_destroy(fx_plan* p) {
     if (!p) return FX_OK;
+    for (const auto& pe : p->pending) {
+        (void)hipEventSynchronize(pe.b);
+        p->pool.push_back(pe.a);
+        p->pool.push_back(pe.b);
+    }
+    for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
     if (p->ws_owned && p->ws) (void)hipFree(p->ws);
     if (p->dtab) (void)hipFree(p->dtab);
     delete p;
@@ -686,6 +711,39 @@ fx_status fx_expand_adjoint(fx_plan* p, const void* grad_out, void* grad_in, voi
     return run_box(p, qb, qn, grad_out, grad_in, 0, nullptr, true, (hipStream_t)stream);
 }
 
+fx_status fx_plan_set_timing(fx_plan* p, int enable) {
+    if (!p) { set_error("plan is NULL"); return FX_EINVAL; }
+    p->timing = (enable != 0);
+    return FX_OK;
+}
+
+fx_status fx_plan_pass_times(fx_plan* p, int32_t* n_passes, int64_t* launches, double* ms, int32_t max) {
+    if (!p || !n_passes) { set_error("NULL argument"); return FX_EINVAL; }
+    for (const auto& pe : p->pending) {
+        FX_TRY_HIP(hipEventSynchronize(pe.b));
+        float f = 0.f;
+        FX_TRY_HIP(hipEventElapsedTime(&f, pe.a, pe.b));
+        if ((int)p->t_ms.size() <= pe.op) {
+            p->t_ms.resize(pe.op + 1, 0.0);
+            p->t_launch.resize(pe.op + 1, 0);
+        }
+        p->t_ms[pe.op] += f;
+        p->t_launch[pe.op] += 1;
+        p->pool.push_back(pe.a);
+        p->pool.push_back(pe.b);
+    }
+    p->pending.clear();
+    const int n = (int)p->t_ms.size();
+    *n_passes = n;
+    for (int i = 0; i < n && i < max; ++i) {
+        if (launches) launches[i] = p->t_launch[i];
+        if (ms) ms[i] = p->t_ms[i];
+    }
+    p->t_ms.clear();
+    p->t_launch.clear();
+    return FX_OK;
+}
+
 fx_status fx_plan_describe(const fx_plan* p, char* buf, size_t len) {
     if (!p || !buf || len == 0) { set_error("NULL argument"); return FX_EINVAL; }
     int qb[3] = {0, 0, 0}, qn[3] = {p->ax[0].lam, p->ax[1].lam, p->ax[2].lam};
@@ -703,9 +761,9 @@ fx_status fx_plan_describe(const fx_plan* p, char* buf, size_t len) {
         const AxisDev& a = p->ax[o.axis];
         char tmp[256];
         std::snprintf(tmp, sizeof(tmp),
-                      "%s{\"kind\":\"%s\",\"axis\":%d,\"M\":%d,\"P\":%d,\"lam\":%d,\"Qin\":%lld,\"A\":%lld,"
-                      "\"S\":%lld,\"TS\":%d}",
-                      i ? "," : "", names[(int)o.kind], o.axis - (3 - p->ndim), a.M, a.P, a.lam,
+                      "%s{\"kind\":\"%s\",\"axis\":%d,\"M\":%d,\"P\":%d,\"lam\":%d,\"qn\":%d,\"Qin\":%lld,"
+                      "\"A\":%lld,\"S\":%lld,\"TS\":%d}",
+                      i ? "," : "", names[(int)o.kind], o.axis - (3 - p->ndim), a.M, a.P, a.lam, o.g.qn,
                       (long long)o.g.Qin, (long long)o.g.A, (long long)o.g.S, o.g.TS);
         s += tmp;
     }
