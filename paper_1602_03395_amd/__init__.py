@@ -8,13 +8,15 @@ is missing; build it with ``python paper_1602_03395_amd/build.py``.
 
 from . import _lib  # noqa: F401  (loads libfx.so, raises if absent)
 from .api import (  # noqa: F401
+    Batch,
     ExpandDensity,
     Plan,
     column_density,
     expand,
     expand_adjoint,
+    expand_batch,
     expand_density,
     get_plan,
 )
 
-__all__ = ["Plan", "expand", "expand_adjoint", "expand_density", "ExpandDensity", "column_density", "get_plan"]
+__all__ = ["Plan", "Batch", "expand_batch", "expand", "expand_adjoint", "expand_density", "ExpandDensity", "column_density", "get_plan"]

@@ -220,6 +220,64 @@ def column_density(rho: torch.Tensor, axis: int, dx, m_over_hbar: float, t: floa
     return plan.column_density(rho, axis)
 
 
+class Batch:
+    """Owns one ``fx_batch``: a ragged list of problems run as one captured graph per call.
+
+    ``problems`` is a list of dicts with keys shape, dx, m_over_hbar, t, lam and
+    optionally a, abar; all realizations share ``dtype``.
+    """
+
+    def __init__(self, problems, dtype=torch.complex64, schedule: str = "paper"):
+        sched = {"paper": L.FX_SCHED_PAPER, "axis_factorised": L.FX_SCHED_AXIS_FACTORISED}[schedule]
+        self.dtype = dtype
+        self.shapes = [tuple(int(x) for x in pr["shape"]) for pr in problems]
+        arr = (L.fx_problem * len(problems))()
+        for i, pr in enumerate(problems):
+            arr[i] = L.make_problem(pr["shape"], pr["dx"], pr["lam"], pr.get("m_over_hbar", 1.0), pr["t"],
+                                    pr.get("a"), pr.get("abar"), precision_of(dtype), sched)
+        self._arr = arr
+        h = ctypes.c_void_p()
+        L.check(L.lib.fx_batch_create(arr, len(problems), ctypes.byref(h)), "fx_batch_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            L.lib.fx_batch_destroy(h)
+            self._h = None
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def run(self, psis, psi_outs=None, rho_outs=None, want_psi=True, want_rho=True):
+        n = len(self.shapes)
+        if len(psis) != n:
+            raise ValueError("wrong number of input fields")
+        for x, shp in zip(psis, self.shapes):
+            _check_field(x, "psi0")
+            if tuple(x.shape) != shp or x.dtype != self.dtype:
+                raise ValueError("input field does not match its problem")
+        if want_psi and psi_outs is None:
+            psi_outs = [torch.empty_like(x) for x in psis]
+        if want_rho and rho_outs is None:
+            rho_outs = [torch.empty(x.shape, dtype=real_dtype(x.dtype), device=x.device) for x in psis]
+        VP = ctypes.c_void_p * n
+        pin = VP(*[x.data_ptr() for x in psis])
+        pout = VP(*[x.data_ptr() for x in psi_outs]) if want_psi else None
+        prho = VP(*[x.data_ptr() for x in rho_outs]) if want_rho else None
+        L.check(L.lib.fx_batch_run(self._h, pin, pout, prho, _stream_ptr()), "fx_batch_run")
+        return (psi_outs if want_psi else None), (rho_outs if want_rho else None)
+
+
+def expand_batch(psis, specs, schedule: str = "paper"):
+    """Expands a ragged list of fields; ``specs`` is one dict (shared) or one per field."""
+    if isinstance(specs, dict):
+        specs = [specs] * len(psis)
+    probs = [dict(s, shape=tuple(x.shape)) for s, x in zip(specs, psis)]
+    b = Batch(probs, dtype=psis[0].dtype, schedule=schedule)
+    return b.run(psis)
+
+
 class ExpandDensity(torch.autograd.Function):
     """rho = |U psi0|^2 with the hand-written adjoint U^H for the backward pass.
 

@@ -36,6 +36,7 @@
 #include <vector>
 
 #include "fx_internal.h"
+#include "plan.h"
 
 namespace fx {
 
@@ -101,60 +102,9 @@ int64_t modinv(int64_t a, int64_t m) {
     return ((x0 % m) + m) % m;
 }
 
-#define FX_TRY_HIP(call)                                                                   \
-    do {                                                                                   \
-        hipError_t e_ = (call);                                                            \
-        if (e_ != hipSuccess) {                                                            \
-            set_error(std::string(#call) + ": " + hipGetErrorString(e_));                  \
-            return FX_EDEVICE;                                                             \
-        }                                                                                  \
-    } while (0)
-
-struct Op {
-    Kind kind;
-    int axis;          // padded axis 0..2
-    PassGeom g;
-    int64_t in_elems;  // per op, elements read tensor size
-    int64_t out_elems;
-};
-
-constexpr int64_t kMaxAxis = 4096;
-
 }  // namespace
 
-struct fx_plan {
-    fx_problem prob{};
-    bool dbl = true;
-    int ndim = 1;
-    int64_t len[3] = {1, 1, 1};   // padded shape
-    AxisParams par[3];
-    AxisDev ax[3];
-    int act[3] = {0, 0, 0};
-    int nact = 0;
-    int64_t M = 1;                 // total points
-    int64_t Q = 1;                 // prod lam
-    void* dtab = nullptr;
-    size_t dtab_bytes = 0;
-    void* ws = nullptr;
-    size_t ws_bytes = 0;
-    bool ws_owned = false;
-    int64_t nb_outer = 1;          // block of the outermost magnification index
-    int64_t slices = 1;            // leading slices (batched realizations)
-    size_t ws_need = 0;
-    int64_t buf_elems = 0;         // elements of each of the two ping-pong buffers
-    int schedule = FX_SCHED_PAPER;
-    int ts_target = 2048;
-    size_t budget = 0;
-    // per-pass timing
-    bool timing = false;
-    struct Pending { int op; hipEvent_t a, b; };
-    std::vector<Pending> pending;
-    std::vector<hipEvent_t> pool;
-    std::vector<int64_t> t_launch;
-    std::vector<double> t_ms;
-};
-
-namespace {
+namespace fx {
 
 size_t csize(const fx_plan* p) { return p->dbl ? 16 : 8; }
 
@@ -170,6 +120,22 @@ int choose_ts(const fx_plan* p, Kind kind, int M, int64_t A, int64_t S) {
 }
 
 // Builds the op list for one block: q ranges per padded axis [qb[p], qb[p]+qn[p]); slices0 leading slices.
+int num_cus() {
+    static int cached = -1;
+    if (cached < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cached = v;
+        else
+            cached = 256;
+    }
+    return cached;
+}
+
+// Builds the op list for one block: q ranges per padded axis [qb[p], qb[p]+qn[p]); slices0 leading slices.
+// A fused EA pass whose lines alone cannot fill the device is split into E (parallel over the
+// magnification index as well) followed by A; likewise EAH into AH + EH.
 std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], int64_t slices0, bool adjoint) {
     std::vector<Op> ops;
     int64_t lens[3] = {p->len[0], p->len[1], p->len[2]};
@@ -186,69 +152,73 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
         g.TS = choose_ts(p, kind, p->ax[ax].M, g.A, g.S);
         if (g.S == 1) g.ntiles = (g.A + g.TS - 1) / g.TS;
         else g.ntiles = g.A * ((g.S + g.TS - 1) / g.TS);
+        g.max_blocks = p->persist > 0 ? p->persist * num_cus() : 0;
         return g;
     };
     auto vol = [&]() { return slices * lens[0] * lens[1] * lens[2]; };
-    auto push = [&](Kind kind, int ax, int64_t qin, int64_t in_e, int64_t out_e) {
-        Op o;
-        o.kind = kind;
-        o.axis = ax;
-        o.g = geom(kind, ax, qin);
-        o.in_elems = in_e;
-        o.out_elems = out_e;
+    auto emit = [&](Kind kind, int ax, const PassGeom& g, int64_t in_e) {
+        Op o{kind, ax, g, in_e, vol()};
         ops.push_back(o);
+    };
+    // forward E: axis full -> pruned, slices x qn
+    auto do_E = [&](int ax) {
+        const int64_t in_e = vol();
+        PassGeom g = geom(Kind::E, ax, slices);
+        lens[ax] = p->ax[ax].P;
+        slices *= qn[ax];
+        emit(Kind::E, ax, g, in_e);
+    };
+    // forward A: axis pruned -> full, slices / qn
+    auto do_A = [&](int ax) {
+        const int64_t in_e = vol();
+        slices /= qn[ax];
+        lens[ax] = p->ax[ax].M;
+        emit(Kind::A, ax, geom(Kind::A, ax, slices), in_e);
+    };
+    auto do_AH = [&](int ax) {
+        const int64_t in_e = vol();
+        PassGeom g = geom(Kind::AH, ax, slices);
+        lens[ax] = p->ax[ax].P;
+        slices *= qn[ax];
+        emit(Kind::AH, ax, g, in_e);
+    };
+    auto do_EH = [&](int ax) {
+        const int64_t in_e = vol();
+        slices /= qn[ax];
+        lens[ax] = p->ax[ax].M;
+        emit(Kind::EH, ax, geom(Kind::EH, ax, slices), in_e);
+    };
+    auto split = [&](Kind kind, int ax) {
+        if (!p->allow_split || qn[ax] < 2) return false;
+        PassGeom g = geom(kind, ax, slices);
+        return g.Qin * g.ntiles < 2 * (int64_t)num_cus();
+    };
+    auto do_EA = [&](int ax) {
+        if (split(Kind::EA, ax)) { do_E(ax); do_A(ax); return; }
+        emit(Kind::EA, ax, geom(Kind::EA, ax, slices), vol());
+    };
+    auto do_EAH = [&](int ax) {
+        if (split(Kind::EAH, ax)) { do_AH(ax); do_EH(ax); return; }
+        emit(Kind::EAH, ax, geom(Kind::EAH, ax, slices), vol());
     };
     const int k = p->nact;
     if (k == 0) return ops;
     if (p->schedule == FX_SCHED_AXIS_FACTORISED) {
         if (!adjoint) {
-            for (int i = k - 1; i >= 0; --i) push(Kind::EA, p->act[i], slices, vol(), vol());
+            for (int i = k - 1; i >= 0; --i) do_EA(p->act[i]);
         } else {
-            for (int i = 0; i < k; ++i) push(Kind::EAH, p->act[i], slices, vol(), vol());
+            for (int i = 0; i < k; ++i) do_EAH(p->act[i]);
         }
         return ops;
     }
     if (!adjoint) {
-        for (int i = k - 1; i >= 1; --i) {
-            const int ax = p->act[i];
-            const int64_t in_e = vol();
-            PassGeom g = geom(Kind::E, ax, slices);
-            lens[ax] = p->ax[ax].P;
-            slices *= qn[ax];
-            Op o{Kind::E, ax, g, in_e, vol()};
-            ops.push_back(o);
-        }
-        push(Kind::EA, p->act[0], slices, vol(), vol());
-        for (int i = 1; i < k; ++i) {
-            const int ax = p->act[i];
-            const int64_t in_e = vol();
-            slices /= qn[ax];
-            lens[ax] = p->ax[ax].M;
-            PassGeom g = geom(Kind::A, ax, slices);
-            Op o{Kind::A, ax, g, in_e, vol()};
-            ops.push_back(o);
-        }
+        for (int i = k - 1; i >= 1; --i) do_E(p->act[i]);
+        do_EA(p->act[0]);
+        for (int i = 1; i < k; ++i) do_A(p->act[i]);
     } else {
-        for (int i = k - 1; i >= 1; --i) {
-            const int ax = p->act[i];
-            const int64_t in_e = vol();
-            const int64_t qin = slices;
-            PassGeom g = geom(Kind::AH, ax, qin);
-            lens[ax] = p->ax[ax].P;
-            slices *= qn[ax];
-            Op o{Kind::AH, ax, g, in_e, vol()};
-            ops.push_back(o);
-        }
-        push(Kind::EAH, p->act[0], slices, vol(), vol());
-        for (int i = 1; i < k; ++i) {
-            const int ax = p->act[i];
-            const int64_t in_e = vol();
-            slices /= qn[ax];
-            lens[ax] = p->ax[ax].M;
-            PassGeom g = geom(Kind::EH, ax, slices);
-            Op o{Kind::EH, ax, g, in_e, vol()};
-            ops.push_back(o);
-        }
+        for (int i = k - 1; i >= 1; --i) do_AH(p->act[i]);
+        do_EAH(p->act[0]);
+        for (int i = 1; i < k; ++i) do_EH(p->act[i]);
     }
     return ops;
 }
@@ -278,7 +248,7 @@ fx_status validate(const fx_problem* pr) {
         if ((int64_t)pr->lambda[j] * pr->shape[j] > (int64_t(1) << 26)) { set_error("lambda*M above 2^26 per axis is not supported"); return FX_EUNSUPPORTED; }
         tot *= pr->shape[j];
     }
-    if (tot > (int64_t(1) << 34)) { set_error("more than 2^34 lattice points"); return FX_EUNSUPPORTED; }
+    if (tot >= (int64_t(1) << 31)) { set_error("2^31 or more lattice points per field"); return FX_EUNSUPPORTED; }
     return FX_OK;
 }
 
@@ -304,7 +274,9 @@ fx_status plan_setup_workspace(fx_plan* p, int64_t slices) {
         return std::max(max_intermediate(f), max_intermediate(h));
     };
     if (p->schedule == FX_SCHED_PAPER) {
-        while (nb > 1 && (size_t)need(nb) * 2 * cs > p->budget) nb = (nb + 1) / 2;
+        if (p->nb_fixed > 0) nb = std::min<int64_t>(p->nb_fixed, outer_lam);
+        else
+            while (nb > 1 && (size_t)need(nb) * 2 * cs > p->budget) nb = (nb + 1) / 2;
     }
     p->nb_outer = std::max<int64_t>(1, nb);
     p->buf_elems = need(p->nb_outer);
@@ -406,7 +378,7 @@ fx_status check_ptr(const void* ptr, const char* what) {
     return FX_OK;
 }
 
-}  // namespace
+}  // namespace fx
 
 extern "C" {
 
@@ -438,6 +410,7 @@ fx_status fx_plan_create(const fx_problem* prob, fx_plan** out) {
     fx_plan* p = new (std::nothrow) fx_plan();
     if (!p) { set_error("host allocation failed"); return FX_ENOMEM; }
     p->prob = *prob;
+    p->prob_in = *prob;
     p->dbl = (prob->precision == FX_PREC_C128);
     p->ndim = prob->ndim;
     p->schedule = prob->schedule;
@@ -530,6 +503,7 @@ fx_status fx_plan_create(const fx_problem* prob, fx_plan** out) {
     if (hipMemGetInfo(&freeb, &totb) == hipSuccess && freeb / 4 < budget) budget = std::max<size_t>(freeb / 4, 1 << 20);
     p->budget = budget;
     if (const char* e = std::getenv("FX_TILE_POINTS")) p->ts_target = std::max(1, std::atoi(e));
+    if (const char* e = std::getenv("FX_NO_SPLIT")) p->allow_split = (e[0] != '1');
     plan_setup_workspace(p, 1);
     *out = p;
     return FX_OK;

@@ -57,6 +57,7 @@ struct PassGeom {
     int qn = 1;        // number of magnification indices handled
     int TS = 1;        // lines per workgroup tile
     int64_t ntiles = 1;  // tiles per (slice, q)
+    int max_blocks = 0;  // persistent grid: cap on workgroups (0 = one per tile)
 };
 
 enum class Kind { E, A, EA, EH, AH, EAH };

@@ -30,6 +30,9 @@
 // (S > 1) they walk across the TS adjacent lines.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <set>
+
 #include "fx_internal.h"
 
 namespace fx {
@@ -123,6 +126,31 @@ template <typename T> struct Bfly<T, 8> {
     }
 };
 
+// Division by a workgroup-uniform divisor: shifts for powers of two, otherwise a
+// float-reciprocal quotient corrected to the exact one (x < 2^22), else the
+// integer divide.
+struct FDiv {
+    int d;
+    int sh;
+    float inv;
+    bool p2;
+    __device__ __forceinline__ explicit FDiv(int dd) : d(dd) {
+        p2 = (dd & (dd - 1)) == 0;
+        sh = p2 ? (__ffs(dd) - 1) : 0;
+        inv = 1.0f / (float)dd;
+    }
+    __device__ __forceinline__ int div(int x) const {
+        if (p2) return x >> sh;
+        if (x >= (1 << 22)) return x / d;
+        int q = (int)((float)x * inv);
+        int r = x - q * d;
+        if (r < 0) { q -= 1; r += d; }
+        if (r >= d) { q += 1; }
+        return q;
+    }
+    __device__ __forceinline__ int mod(int x) const { return x - div(x) * d; }
+};
+
 template <typename T> __device__ __forceinline__ C<T> root(const C<T>* __restrict__ tw, int idx, bool inv) {
     C<T> w = tw[idx];
     if (inv) w.y = -w.y;
@@ -132,16 +160,17 @@ template <typename T> __device__ __forceinline__ C<T> root(const C<T>* __restric
 // One Stockham stage with a compile-time radix over nl lines of length N at LDS stride ls.
 template <typename T, int R>
 __device__ void stage_r(const C<T>* __restrict__ X, C<T>* __restrict__ Y, int nl, int ls, int N, int Ns,
-                        const C<T>* __restrict__ tw, int tws, bool inv) {
+                        const C<T>* __restrict__ tw, int tws, bool inv, const C<T>* __restrict__ post) {
     const int nb = N / R;
     const int total = nl * nb;
     const int tstep = (N / (Ns * R)) * tws;
+    const FDiv fnb(nb), fns(Ns);
     for (int j = threadIdx.x; j < total; j += blockDim.x) {
-        const int l = j / nb;
+        const int l = fnb.div(j);
         const int jj = j - l * nb;
         const C<T>* x = X + l * ls;
         C<T>* y = Y + l * ls;
-        const int k = jj % Ns;
+        const int k = fns.mod(jj);
         C<T> v[R];
 #pragma unroll
         for (int t = 0; t < R; ++t) v[t] = x[jj + t * nb];
@@ -150,16 +179,21 @@ __device__ void stage_r(const C<T>* __restrict__ X, C<T>* __restrict__ Y, int nl
             for (int t = 1; t < R; ++t) v[t] = cmul<T>(v[t], root<T>(tw, t * k * tstep, inv));
         }
         Bfly<T, R>::run(v, inv);
-        const int base = (jj / Ns) * Ns * R + k;
+        const int base = (jj - k) * R + k;
+        if (post) {
 #pragma unroll
-        for (int t = 0; t < R; ++t) y[base + t * Ns] = v[t];
+            for (int t = 0; t < R; ++t) y[base + t * Ns] = cmul<T>(v[t], post[base + t * Ns]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < R; ++t) y[base + t * Ns] = v[t];
+        }
     }
 }
 
 // Any radix: direct R-point DFT per butterfly, roots from the same table.
 template <typename T>
 __device__ void stage_gen(const C<T>* __restrict__ X, C<T>* __restrict__ Y, int nl, int ls, int N, int Ns,
-                          int R, const C<T>* __restrict__ tw, int tws, bool inv) {
+                          int R, const C<T>* __restrict__ tw, int tws, bool inv, const C<T>* __restrict__ post) {
     const int nb = N / R;
     const int total = nl * nb;
     const int tstep = (N / (Ns * R)) * tws;
@@ -178,25 +212,36 @@ __device__ void stage_gen(const C<T>* __restrict__ X, C<T>* __restrict__ Y, int 
                 if (Ns > 1 && t > 0) v = cmul<T>(v, root<T>(tw, t * k * tstep, inv));
                 acc = cfma<T>(acc, v, root<T>(tw, ((t * u) % R) * rstep, inv));
             }
-            y[base + u * Ns] = acc;
+            y[base + u * Ns] = post ? cmul<T>(acc, post[base + u * Ns]) : acc;
         }
     }
 }
 
 // Transform nl lines of length pl.n held in X (stride ls); returns the buffer holding the result.
+// With `post` (a global row of pl.n values) the output is multiplied by it elementwise in the
+// last stage (the chirp of (presB) fused into the forward transform).
 template <typename T>
 __device__ C<T>* lds_fft(C<T>* X, C<T>* Y, int nl, int ls, const RadixPlan& pl, const C<T>* __restrict__ tw,
-                         int tws, bool inv) {
+                         int tws, bool inv, const C<T>* __restrict__ post = nullptr) {
     int Ns = 1;
     const int N = pl.n;
+    if (pl.nst == 0 && post) {
+        for (int e = threadIdx.x; e < nl * N; e += blockDim.x) {
+            const int l = e / N;
+            const int n = e - l * N;
+            X[l * ls + n] = cmul<T>(X[l * ls + n], post[n]);
+        }
+        __syncthreads();
+    }
     for (int s = 0; s < pl.nst; ++s) {
         const int R = pl.rad[s];
+        const C<T>* pp = (s + 1 == pl.nst) ? post : nullptr;
         switch (R) {
-            case 2: stage_r<T, 2>(X, Y, nl, ls, N, Ns, tw, tws, inv); break;
-            case 3: stage_r<T, 3>(X, Y, nl, ls, N, Ns, tw, tws, inv); break;
-            case 4: stage_r<T, 4>(X, Y, nl, ls, N, Ns, tw, tws, inv); break;
-            case 8: stage_r<T, 8>(X, Y, nl, ls, N, Ns, tw, tws, inv); break;
-            default: stage_gen<T>(X, Y, nl, ls, N, Ns, R, tw, tws, inv); break;
+            case 2: stage_r<T, 2>(X, Y, nl, ls, N, Ns, tw, tws, inv, pp); break;
+            case 3: stage_r<T, 3>(X, Y, nl, ls, N, Ns, tw, tws, inv, pp); break;
+            case 4: stage_r<T, 4>(X, Y, nl, ls, N, Ns, tw, tws, inv, pp); break;
+            case 8: stage_r<T, 8>(X, Y, nl, ls, N, Ns, tw, tws, inv, pp); break;
+            default: stage_gen<T>(X, Y, nl, ls, N, Ns, R, tw, tws, inv, pp); break;
         }
         __syncthreads();
         C<T>* t = X;
@@ -205,6 +250,49 @@ __device__ C<T>* lds_fft(C<T>* X, C<T>* Y, int nl, int ls, const RadixPlan& pl, 
         Ns *= R;
     }
     return X;
+}
+
+// Z[l][u] = sum_{c<g} Y[l][u + c P] for nl lines (line stride ls). Several threads share an
+// output when there are few outputs; their partial sums meet in the scratch W (blockDim entries).
+template <typename T>
+__device__ void fold_lines(const C<T>* __restrict__ Y, C<T>* __restrict__ Z, C<T>* __restrict__ W, int nl, int ls,
+                           int P, int g, const FDiv& fP) {
+    const int outs = nl * P;
+    int K = 1;
+    while (K * 2 <= g && outs * K * 2 <= (int)blockDim.x) K *= 2;
+    if (K == 1) {
+        for (int e = threadIdx.x; e < outs; e += blockDim.x) {
+            const int l = fP.div(e);
+            const int u = e - l * P;
+            const C<T>* y = Y + l * ls + u;
+            C<T> acc = mk<T>(0, 0);
+            for (int c = 0; c < g; ++c) acc = cadd<T>(acc, y[c * P]);
+            Z[l * ls + u] = acc;
+        }
+        __syncthreads();
+        return;
+    }
+    const int kb = __ffs(K) - 1;
+    const int t = threadIdx.x;
+    if (t < outs * K) {
+        const int o = t >> kb;
+        const int kk = t & (K - 1);
+        const int l = fP.div(o);
+        const int u = o - l * P;
+        const C<T>* y = Y + l * ls + u;
+        C<T> acc = mk<T>(0, 0);
+        for (int c = kk; c < g; c += K) acc = cadd<T>(acc, y[c * P]);
+        W[t] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < outs; e += blockDim.x) {
+        const int l = fP.div(e);
+        const int u = e - l * P;
+        C<T> acc = W[e << kb];
+        for (int kk = 1; kk < K; ++kk) acc = cadd<T>(acc, W[(e << kb) + kk]);
+        Z[l * ls + u] = acc;
+    }
+    __syncthreads();
 }
 
 // ------------------------------------------------------------------------------------
@@ -232,19 +320,33 @@ __device__ __forceinline__ Tile decode_tile(const PassGeom& g, int64_t t) {
 }
 
 // Element e of a tile of nl lines of length L -> (line l, position n) and global offset in slice `slice`.
-__device__ __forceinline__ int64_t tile_elem(const PassGeom& g, const Tile& tl, int64_t slice, int L, int e,
-                                             int& l, int& n) {
+// `fd` divides by L when the lines are contiguous (S == 1) and by nl otherwise.
+__device__ __forceinline__ int64_t tile_elem(const PassGeom& g, const Tile& tl, int64_t slice, int L,
+                                             const FDiv& fd, int e, int& l, int& n) {
     if (g.S == 1) {
-        l = e / L;
+        l = fd.div(e);
         n = e - l * L;
         return (slice * g.A + tl.a0 + l) * L + n;
     }
-    n = e / tl.nl;
+    n = fd.div(e);
     l = e - n * tl.nl;
     return ((slice * g.A + tl.a0) * L + n) * g.S + tl.s0 + l;
 }
 
+__device__ __forceinline__ FDiv tile_div(const PassGeom& g, const Tile& tl, int L) {
+    return FDiv(g.S == 1 ? L : tl.nl);
+}
+
 template <typename T> __device__ __forceinline__ const C<T>* tab(const void* p) { return (const C<T>*)p; }
+
+// Copies the axis' FFT roots into LDS (after the tile buffers) once per workgroup.
+template <typename T>
+__device__ const C<T>* stage_roots(C<T>* dst, const AxisDev& ax) {
+    const C<T>* src = (const C<T>*)ax.tw;
+    for (int i = threadIdx.x; i < ax.M; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+    return dst;
+}
 
 // ------------------------------------------------------------------------------------
 // E: per q, line of M -> P values of B^(q) along this axis (times 1/M).
@@ -255,11 +357,13 @@ __global__ __launch_bounds__(kThreads) void k_E(const C<T>* __restrict__ in, C<T
                                                 PassGeom g) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int M = ax.M, P = ax.P;
+    const FDiv fM(M), fP(P);
     C<T>* B0 = (C<T>*)smem;
     C<T>* B1 = B0 + g.TS * M;
     const C<T>* TA = tab<T>(ax.TA);
     const C<T>* TB = tab<T>(ax.TB);
-    const C<T>* tw = tab<T>(ax.tw);
+    const C<T>* tw = stage_roots<T>(B1 + g.TS * M, ax);
+    C<T>* Wsc = B1 + g.TS * M + M;  // fold scratch, kThreads entries
     const T scale = (T)ax.scale;
     const int64_t total = g.Qin * g.qn * g.ntiles;
     for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
@@ -269,31 +373,22 @@ __global__ __launch_bounds__(kThreads) void k_E(const C<T>* __restrict__ in, C<T
         const int64_t qi = rest / g.qn;
         const int q = g.qb + qq;
         const Tile tl = decode_tile(g, tt);
+        const FDiv fdM = tile_div(g, tl, M), fdP = tile_div(g, tl, P);
         const int nl = tl.nl;
         for (int e = threadIdx.x; e < nl * M; e += blockDim.x) {
             int l, n;
-            const int64_t off = tile_elem(g, tl, qi, M, e, l, n);
+            const int64_t off = tile_elem(g, tl, qi, M, fdM, e, l, n);
             B0[l * M + n] = cmul<T>(in[off], TA[q * M + n]);
         }
         __syncthreads();
-        C<T>* Y = lds_fft<T>(B0, B1, nl, M, ax.fm, tw, 1, false);
+        C<T>* Y = lds_fft<T>(B0, B1, nl, M, ax.fm, tw, 1, false, TB + q * M);
         C<T>* Z = (Y == B0) ? B1 : B0;
-        for (int e = threadIdx.x; e < nl * P; e += blockDim.x) {
-            const int l = e / P;
-            const int u = e - l * P;
-            C<T> acc = mk<T>(0, 0);
-            for (int c = 0; c < ax.g; ++c) {
-                const int m = u + c * P;
-                acc = cfma<T>(acc, Y[l * M + m], TB[q * M + m]);
-            }
-            Z[l * M + u] = acc;
-        }
-        __syncthreads();
+        fold_lines<T>(Y, Z, Wsc, nl, M, P, ax.g, fP);
         C<T>* Rz = lds_fft<T>(Z, Y, nl, M, ax.fp, tw, ax.g, true);
         const int64_t qo = qi * g.qn + qq;
         for (int e = threadIdx.x; e < nl * P; e += blockDim.x) {
             int l, u;
-            const int64_t off = tile_elem(g, tl, qo, P, e, l, u);
+            const int64_t off = tile_elem(g, tl, qo, P, fdP, e, l, u);
             out[off] = cscale<T>(Rz[l * M + u], scale);
         }
         __syncthreads();
@@ -306,25 +401,32 @@ __global__ __launch_bounds__(kThreads) void k_E(const C<T>* __restrict__ in, C<T
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_A(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
                                                 PassGeom g, int accumulate, T* __restrict__ rho) {
+    // grid: x over the (nb, s) plane of one (qo, a) row, y over rows
     const int M = ax.M, P = ax.P;
+    const int S = (int)g.S;
+    const int MS = M * S;
+    const FDiv fS(S), fP(P);
     const C<T>* Tf = tab<T>(ax.Tf);
-    const int64_t total = g.Qin * g.A * (int64_t)M * g.S;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t s = e % g.S;
-        int64_t t = e / g.S;
-        const int n = (int)(t % M);
-        t /= M;
-        const int64_t a = t % g.A;
-        const int64_t qo = t / g.A;
-        const int r = (int)(((int64_t)n * ax.lg) % P);
-        C<T> acc = mk<T>(0, 0);
-        const int64_t step = g.A * (int64_t)P * g.S;
-        int64_t src = (((qo * g.qn) * g.A + a) * P + r) * g.S + s;
-        for (int i = 0; i < g.qn; ++i, src += step) acc = cfma<T>(acc, Tf[(g.qb + i) * M + n], in[src]);
-        if (accumulate) acc = cadd<T>(acc, out[e]);
-        out[e] = acc;
-        if (rho) rho[e] = acc.x * acc.x + acc.y * acc.y;
+    const int64_t rows = g.Qin * g.A;
+    const int64_t step = g.A * (int64_t)P * S;  // one magnification slice of the input
+    for (int64_t row = blockIdx.y; row < rows; row += gridDim.y) {
+        const int64_t qo = row / g.A;
+        const int64_t a = row - qo * g.A;
+        const C<T>* src0 = in + ((qo * g.qn) * g.A + a) * (int64_t)P * S;
+        C<T>* dst = out + row * (int64_t)MS;
+        T* rdst = rho ? rho + row * (int64_t)MS : nullptr;
+        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < MS; e += gridDim.x * blockDim.x) {
+            const int n = fS.div(e);
+            const int s = e - n * S;
+            const int r = fP.mod(n * ax.lg);
+            const C<T>* src = src0 + r * S + s;
+            const C<T>* tf = Tf + g.qb * M + n;
+            C<T> acc = mk<T>(0, 0);
+            for (int i = 0; i < g.qn; ++i) acc = cfma<T>(acc, tf[i * M], src[i * step]);
+            if (accumulate) acc = cadd<T>(acc, dst[e]);
+            dst[e] = acc;
+            if (rdst) rdst[e] = acc.x * acc.x + acc.y * acc.y;
+        }
     }
 }
 
@@ -337,19 +439,22 @@ __global__ __launch_bounds__(kThreads) void k_EA(const C<T>* __restrict__ in, C<
                                                  PassGeom g, int accumulate, T* __restrict__ rho) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int M = ax.M, P = ax.P;
+    const FDiv fM(M), fP(P);
     C<T>* RAW = (C<T>*)smem;
     C<T>* B0 = RAW + g.TS * M;
     C<T>* B1 = B0 + g.TS * M;
     const C<T>* TA = tab<T>(ax.TA);
     const C<T>* TB = tab<T>(ax.TB);
     const C<T>* Tf = tab<T>(ax.Tf);
-    const C<T>* tw = tab<T>(ax.tw);
+    const C<T>* tw = stage_roots<T>(B1 + g.TS * M, ax);
+    C<T>* Wsc = B1 + g.TS * M + M;  // fold scratch, kThreads entries
     const T scale = (T)ax.scale;
     const int64_t total = g.Qin * g.ntiles;
     for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
         const int64_t tt = bid % g.ntiles;
         const int64_t qi = bid / g.ntiles;
         const Tile tl = decode_tile(g, tt);
+        const FDiv fdM = tile_div(g, tl, M), fdP = tile_div(g, tl, P);
         const int nl = tl.nl;
         const int cnt = nl * M;
         int el[ACCN], en[ACCN];
@@ -363,7 +468,7 @@ __global__ __launch_bounds__(kThreads) void k_EA(const C<T>* __restrict__ in, C<
             eoff[k] = 0;
             acc[k] = mk<T>(0, 0);
             if (e < cnt) {
-                eoff[k] = tile_elem(g, tl, qi, M, e, el[k], en[k]);
+                eoff[k] = tile_elem(g, tl, qi, M, fdM, e, el[k], en[k]);
                 RAW[el[k] * M + en[k]] = in[eoff[k]];
             }
         }
@@ -371,31 +476,19 @@ __global__ __launch_bounds__(kThreads) void k_EA(const C<T>* __restrict__ in, C<
         for (int i = 0; i < g.qn; ++i) {
             const int q = g.qb + i;
             for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-                const int l = e / M;
-                const int n = e - l * M;
+                const int n = fM.mod(e);
                 B0[e] = cmul<T>(RAW[e], TA[q * M + n]);
-                (void)l;
             }
             __syncthreads();
-            C<T>* Y = lds_fft<T>(B0, B1, nl, M, ax.fm, tw, 1, false);
+            C<T>* Y = lds_fft<T>(B0, B1, nl, M, ax.fm, tw, 1, false, TB + q * M);
             C<T>* Z = (Y == B0) ? B1 : B0;
-            for (int e = threadIdx.x; e < nl * P; e += blockDim.x) {
-                const int l = e / P;
-                const int u = e - l * P;
-                C<T> a2 = mk<T>(0, 0);
-                for (int c = 0; c < ax.g; ++c) {
-                    const int m = u + c * P;
-                    a2 = cfma<T>(a2, Y[l * M + m], TB[q * M + m]);
-                }
-                Z[l * M + u] = a2;
-            }
-            __syncthreads();
+            fold_lines<T>(Y, Z, Wsc, nl, M, P, ax.g, fP);
             C<T>* Rz = lds_fft<T>(Z, Y, nl, M, ax.fp, tw, ax.g, true);
 #pragma unroll
             for (int k = 0; k < ACCN; ++k) {
                 const int e = threadIdx.x + k * kThreads;
                 if (e < cnt) {
-                    const int r = (int)(((int64_t)en[k] * ax.lg) % P);
+                    const int r = fP.mod(en[k] * ax.lg);
                     acc[k] = cfma<T>(acc[k], Tf[q * M + en[k]], Rz[el[k] * M + r]);
                 }
             }
@@ -425,17 +518,20 @@ __global__ __launch_bounds__(kThreads) void k_EH(const C<T>* __restrict__ in, C<
                                                  PassGeom g, int accumulate) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int M = ax.M, P = ax.P;
+    const FDiv fM(M), fP(P);
     C<T>* B0 = (C<T>*)smem;
     C<T>* B1 = B0 + g.TS * M;
     const C<T>* TA = tab<T>(ax.TA);
     const C<T>* TB = tab<T>(ax.TB);
-    const C<T>* tw = tab<T>(ax.tw);
+    const C<T>* tw = stage_roots<T>(B1 + g.TS * M, ax);
+    C<T>* Wsc = B1 + g.TS * M + M;  // fold scratch, kThreads entries
     const T scale = (T)ax.scale;
     const int64_t total = g.Qin * g.ntiles;  // Qin = output slices here
     for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
         const int64_t tt = bid % g.ntiles;
         const int64_t qo = bid / g.ntiles;
         const Tile tl = decode_tile(g, tt);
+        const FDiv fdM = tile_div(g, tl, M), fdP = tile_div(g, tl, P);
         const int nl = tl.nl;
         const int cnt = nl * M;
         int el[ACCN], en[ACCN];
@@ -447,23 +543,23 @@ __global__ __launch_bounds__(kThreads) void k_EH(const C<T>* __restrict__ in, C<
             el[k] = en[k] = 0;
             eoff[k] = 0;
             acc[k] = mk<T>(0, 0);
-            if (e < cnt) eoff[k] = tile_elem(g, tl, qo, M, e, el[k], en[k]);
+            if (e < cnt) eoff[k] = tile_elem(g, tl, qo, M, fdM, e, el[k], en[k]);
         }
         for (int i = 0; i < g.qn; ++i) {
             const int q = g.qb + i;
             const int64_t si = qo * g.qn + i;
             for (int e = threadIdx.x; e < nl * P; e += blockDim.x) {
                 int l, u;
-                const int64_t off = tile_elem(g, tl, si, P, e, l, u);
+                const int64_t off = tile_elem(g, tl, si, P, fdP, e, l, u);
                 B0[l * M + u] = in[off];
             }
             __syncthreads();
             C<T>* Z = lds_fft<T>(B0, B1, nl, M, ax.fp, tw, ax.g, false);
             C<T>* Yb = (Z == B0) ? B1 : B0;
             for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-                const int l = e / M;
+                const int l = fM.div(e);
                 const int m = e - l * M;
-                Yb[e] = cmulc<T>(Z[l * M + (m % P)], TB[q * M + m]);
+                Yb[e] = cmulc<T>(Z[l * M + fP.mod(m)], TB[q * M + m]);
             }
             __syncthreads();
             C<T>* Y = lds_fft<T>(Yb, Z, nl, M, ax.fm, tw, 1, true);
@@ -495,27 +591,32 @@ __global__ __launch_bounds__(kThreads) void k_EH(const C<T>* __restrict__ in, C<
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_AH(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
                                                  PassGeom g) {
+    // grid: x over the (r, s) plane of one output slice row, y over rows (qo, i, a)
     const int M = ax.M, P = ax.P;
+    const int S = (int)g.S;
+    const int PS = P * S;
+    const FDiv fS(S), fP(P);
     const C<T>* Tf = tab<T>(ax.Tf);
-    const int64_t total = g.Qin * g.qn * g.A * (int64_t)P * g.S;  // Qin = input slices (Qo)
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t s = e % g.S;
-        int64_t t = e / g.S;
-        const int r = (int)(t % P);
-        t /= P;
-        const int64_t a = t % g.A;
-        t /= g.A;
+    const int64_t rows = g.Qin * g.qn * g.A;  // Qin = input slices (Qo)
+    for (int64_t row = blockIdx.y; row < rows; row += gridDim.y) {
+        const int64_t a = row % g.A;
+        const int64_t t = row / g.A;
         const int i = (int)(t % g.qn);
         const int64_t qo = t / g.qn;
         const int q = g.qb + i;
-        const int n0 = (int)(((int64_t)r * ax.lg_inv) % P);
-        C<T> acc = mk<T>(0, 0);
-        for (int c = 0; c < ax.g; ++c) {
-            const int n = n0 + c * P;
-            acc = cfmac<T>(acc, in[((qo * g.A + a) * M + n) * g.S + s], Tf[q * M + n]);
+        const C<T>* src0 = in + (qo * g.A + a) * (int64_t)M * S;
+        C<T>* dst = out + row * (int64_t)PS;
+        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < PS; e += gridDim.x * blockDim.x) {
+            const int r = fS.div(e);
+            const int s = e - r * S;
+            const int n0 = fP.mod(r * ax.lg_inv);
+            C<T> acc = mk<T>(0, 0);
+            for (int c = 0; c < ax.g; ++c) {
+                const int n = n0 + c * P;
+                acc = cfmac<T>(acc, src0[n * S + s], Tf[q * M + n]);
+            }
+            dst[e] = acc;
         }
-        out[e] = acc;
     }
 }
 
@@ -527,19 +628,22 @@ __global__ __launch_bounds__(kThreads) void k_EAH(const C<T>* __restrict__ in, C
                                                   PassGeom g, int accumulate) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int M = ax.M, P = ax.P;
+    const FDiv fM(M), fP(P);
     C<T>* RAW = (C<T>*)smem;
     C<T>* B0 = RAW + g.TS * M;
     C<T>* B1 = B0 + g.TS * M;
     const C<T>* TA = tab<T>(ax.TA);
     const C<T>* TB = tab<T>(ax.TB);
     const C<T>* Tf = tab<T>(ax.Tf);
-    const C<T>* tw = tab<T>(ax.tw);
+    const C<T>* tw = stage_roots<T>(B1 + g.TS * M, ax);
+    C<T>* Wsc = B1 + g.TS * M + M;  // fold scratch, kThreads entries
     const T scale = (T)ax.scale;
     const int64_t total = g.Qin * g.ntiles;
     for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
         const int64_t tt = bid % g.ntiles;
         const int64_t qi = bid / g.ntiles;
         const Tile tl = decode_tile(g, tt);
+        const FDiv fdM = tile_div(g, tl, M), fdP = tile_div(g, tl, P);
         const int nl = tl.nl;
         const int cnt = nl * M;
         int el[ACCN], en[ACCN];
@@ -552,7 +656,7 @@ __global__ __launch_bounds__(kThreads) void k_EAH(const C<T>* __restrict__ in, C
             eoff[k] = 0;
             acc[k] = mk<T>(0, 0);
             if (e < cnt) {
-                eoff[k] = tile_elem(g, tl, qi, M, e, el[k], en[k]);
+                eoff[k] = tile_elem(g, tl, qi, M, fdM, e, el[k], en[k]);
                 RAW[el[k] * M + en[k]] = in[eoff[k]];
             }
         }
@@ -560,9 +664,9 @@ __global__ __launch_bounds__(kThreads) void k_EAH(const C<T>* __restrict__ in, C
         for (int i = 0; i < g.qn; ++i) {
             const int q = g.qb + i;
             for (int e = threadIdx.x; e < nl * P; e += blockDim.x) {
-                const int l = e / P;
+                const int l = fP.div(e);
                 const int r = e - l * P;
-                const int n0 = (int)(((int64_t)r * ax.lg_inv) % P);
+                const int n0 = fP.mod(r * ax.lg_inv);
                 C<T> a2 = mk<T>(0, 0);
                 for (int c = 0; c < ax.g; ++c) {
                     const int n = n0 + c * P;
@@ -574,9 +678,9 @@ __global__ __launch_bounds__(kThreads) void k_EAH(const C<T>* __restrict__ in, C
             C<T>* Z = lds_fft<T>(B0, B1, nl, M, ax.fp, tw, ax.g, false);
             C<T>* Yb = (Z == B0) ? B1 : B0;
             for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-                const int l = e / M;
+                const int l = fM.div(e);
                 const int m = e - l * M;
-                Yb[e] = cmulc<T>(Z[l * M + (m % P)], TB[q * M + m]);
+                Yb[e] = cmulc<T>(Z[l * M + fP.mod(m)], TB[q * M + m]);
             }
             __syncthreads();
             C<T>* Y = lds_fft<T>(Yb, Z, nl, M, ax.fm, tw, 1, true);
@@ -668,23 +772,42 @@ int elem_blocks(int64_t total) {
     return (int)b;
 }
 
-int tile_blocks(int64_t total) {
+dim3 plane_grid(int64_t plane, int64_t rows) {
+    int64_t bx = (plane + kThreads - 1) / kThreads;
+    if (bx < 1) bx = 1;
+    if (bx > 65535) bx = 65535;
+    int64_t by = rows < 1 ? 1 : rows;
+    if (by > 65535) by = 65535;
+    return dim3((unsigned)bx, (unsigned)by);
+}
+
+int tile_blocks(int64_t total, int cap = 0) {
     if (total < 1) total = 1;
     if (total > (1 << 22)) total = 1 << 22;
+    if (cap > 0 && total > cap) total = cap;
     return (int)total;
 }
 
+// Raises a kernel's dynamic-LDS limit to the device maximum once (before any graph capture
+// that launches it: the plan and batch set-up runs every kernel eagerly first).
 template <typename K>
 hipError_t prep_lds(K kernel, size_t bytes) {
-    if (bytes > 65536) return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    return hipSuccess;
+    if (bytes <= 65536) return hipSuccess;
+    static std::mutex mu;
+    static std::set<const void*> done;
+    std::lock_guard<std::mutex> lk(mu);
+    if (done.count((const void*)kernel)) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       lds_limit_bytes());
+    if (e == hipSuccess) done.insert((const void*)kernel);
+    return e;
 }
 
 template <typename T, int ACCN>
 hipError_t launch_acc_kind(Kind kind, const void* in, void* out, const AxisDev& ax, const PassGeom& g,
                            int accumulate, void* rho, hipStream_t st) {
     const size_t lds = pass_lds_bytes(kind, sizeof(T) == 8, g.TS, ax.M);
-    const int blocks = tile_blocks(g.Qin * g.ntiles);
+    const int blocks = tile_blocks(g.Qin * g.ntiles, g.max_blocks);
     hipError_t err = hipSuccess;
     switch (kind) {
         case Kind::EA: {
@@ -722,20 +845,19 @@ hipError_t launch_T(Kind kind, const void* in, void* out, const AxisDev& ax, con
             auto k = k_E<T>;
             hipError_t err = prep_lds(k, lds);
             if (err != hipSuccess) return err;
-            hipLaunchKernelGGL(k, dim3(tile_blocks(g.Qin * g.qn * g.ntiles)), dim3(kThreads), lds, st,
+            hipLaunchKernelGGL(k, dim3(tile_blocks(g.Qin * g.qn * g.ntiles, g.max_blocks)), dim3(kThreads), lds, st,
                                (const C<T>*)in, (C<T>*)out, ax, g);
             return hipGetLastError();
         }
         case Kind::A: {
-            const int64_t total = g.Qin * g.A * (int64_t)ax.M * g.S;
-            hipLaunchKernelGGL(k_A<T>, dim3(elem_blocks(total)), dim3(kThreads), 0, st, (const C<T>*)in,
-                               (C<T>*)out, ax, g, accumulate, (T*)rho);
+            const dim3 grid = plane_grid((int64_t)ax.M * g.S, g.Qin * g.A);
+            hipLaunchKernelGGL(k_A<T>, grid, dim3(kThreads), 0, st, (const C<T>*)in, (C<T>*)out, ax, g,
+                               accumulate, (T*)rho);
             return hipGetLastError();
         }
         case Kind::AH: {
-            const int64_t total = g.Qin * g.qn * g.A * (int64_t)ax.P * g.S;
-            hipLaunchKernelGGL(k_AH<T>, dim3(elem_blocks(total)), dim3(kThreads), 0, st, (const C<T>*)in,
-                               (C<T>*)out, ax, g);
+            const dim3 grid = plane_grid((int64_t)ax.P * g.S, g.Qin * g.qn * g.A);
+            hipLaunchKernelGGL(k_AH<T>, grid, dim3(kThreads), 0, st, (const C<T>*)in, (C<T>*)out, ax, g);
             return hipGetLastError();
         }
         default: break;
@@ -756,9 +878,9 @@ size_t pass_lds_bytes(Kind kind, bool dbl, int TS, int M) {
     const size_t c = dbl ? 16 : 8;
     switch (kind) {
         case Kind::E:
-        case Kind::EH: return 2 * (size_t)TS * M * c;
+        case Kind::EH: return ((2 * (size_t)TS + 1) * M + kThreads) * c;
         case Kind::EA:
-        case Kind::EAH: return 3 * (size_t)TS * M * c;
+        case Kind::EAH: return ((3 * (size_t)TS + 1) * M + kThreads) * c;
         default: return 0;
     }
 }

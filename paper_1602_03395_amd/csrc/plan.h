@@ -1,0 +1,82 @@
+// Plan object and schedule helpers shared by the host runtime files (not public ABI).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "fx_internal.h"
+
+#define FX_TRY_HIP(call)                                                                   \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            fx::set_error(std::string(#call) + ": " + hipGetErrorString(e_));                  \
+            return FX_EDEVICE;                                                             \
+        }                                                                                  \
+    } while (0)
+
+namespace fx {
+
+struct Op {
+    Kind kind;
+    int axis;          // padded axis 0..2
+    PassGeom g;
+    int64_t in_elems;  // per op, elements read tensor size
+    int64_t out_elems;
+};
+
+constexpr int64_t kMaxAxis = 4096;
+
+}  // namespace fx
+
+struct fx_plan {
+    fx_problem prob{};             // with default offsets resolved
+    fx_problem prob_in{};          // as given by the caller
+    bool dbl = true;
+    int ndim = 1;
+    int64_t len[3] = {1, 1, 1};   // padded shape
+    fx::AxisParams par[3];
+    fx::AxisDev ax[3];
+    int act[3] = {0, 0, 0};
+    int nact = 0;
+    int64_t M = 1;                 // total points
+    int64_t Q = 1;                 // prod lam
+    void* dtab = nullptr;
+    size_t dtab_bytes = 0;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool ws_owned = false;
+    int64_t nb_outer = 1;          // block of the outermost magnification index
+    int64_t nb_fixed = 0;          // >0: use this block instead of fitting the budget
+    int64_t slices = 1;            // leading slices (batched realizations)
+    size_t ws_need = 0;
+    int64_t buf_elems = 0;         // elements of each of the two ping-pong buffers
+    int schedule = FX_SCHED_PAPER;
+    int ts_target = 2048;
+    bool allow_split = true;       // split a starved fused EA pass into E + A
+    int persist = 0;               // >0: tile passes run as persistent grids of persist x CUs workgroups
+    size_t budget = 0;
+    // per-pass timing
+    bool timing = false;
+    struct Pending { int op; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    std::vector<int64_t> t_launch;
+    std::vector<double> t_ms;
+};
+
+namespace fx {
+
+size_t csize(const fx_plan* p);
+std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], int64_t slices0, bool adjoint);
+int64_t max_intermediate(const std::vector<Op>& ops);
+fx_status validate(const fx_problem* pr);
+fx_status plan_setup_workspace(fx_plan* p, int64_t slices);
+fx_status ensure_workspace(fx_plan* p);
+fx_status run_ops(fx_plan* p, const std::vector<Op>& ops, const void* src, void* dst, int accumulate, void* rho,
+                  hipStream_t st);
+fx_status run_box(fx_plan* p, const int qb[3], const int qn[3], const void* src, void* dst, int accumulate,
+                  void* rho, bool adjoint, hipStream_t st);
+fx_status check_ptr(const void* ptr, const char* what);
+
+}  // namespace fx

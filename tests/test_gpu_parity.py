@@ -222,3 +222,42 @@ def test_small_workspace_budget_forces_blocking(fx, monkeypatch):
     assert desc["outer_block"] < 6
     out, _ = plan.expand(torch.from_numpy(psi_np).cuda())
     assert rel(out.cpu().numpy(), oracle.expand(psi_np, (1.0,) * 3, 1.0, 8.0, lam)) <= TOL64
+
+
+def test_batch_ragged_matches_single_plans_and_replays(fx):
+    shapes = [(12, 10, 16), (8, 8, 24), (12, 10, 16), (8, 8, 24), (12, 10, 16)]
+    lam = (2, 3, 4)
+    say("batch", shapes)
+    specs = [dict(shape=s, dx=(1.0, 1.0, 1.0), lam=lam, t=9.0) for s in shapes]
+    for dtype, tol in ((torch.complex128, 1e-12), (torch.complex64, 1e-5)):
+        fields = [workloads.random_field(s, 300 + i) for i, s in enumerate(shapes)]
+        psis = [torch.from_numpy(f).to(dtype).cuda() for f in fields]
+        b = fx.Batch(specs, dtype=dtype)
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            outs, rhos = b.run(psis)
+        stream.synchronize()
+        for i, (f, s) in enumerate(zip(fields, shapes)):
+            ref = oracle.expand(psis[i].cpu().numpy().astype(np.complex128), (1.0,) * 3, 1.0, 9.0, lam)
+            if dtype == torch.complex128:
+                assert rel(outs[i].cpu().numpy(), ref) <= tol
+            assert rel(rhos[i].cpu().numpy(), oracle.density(ref)) <= tol
+        first = [o.cpu().numpy().copy() for o in outs]
+        # replays of the captured graph, with eager work in between, reproduce the first run
+        for rep in range(3):
+            with torch.cuda.stream(stream):
+                for o in outs:
+                    o.zero_()
+                _ = fx.expand(psis[0], (1.0,) * 3, 1.0, 9.0, lam)
+                b.run(psis, psi_outs=outs, rho_outs=rhos)
+            stream.synchronize()
+            for i in range(len(shapes)):
+                assert np.array_equal(outs[i].cpu().numpy(), first[i])
+
+
+def test_batch_rejects_bad_arguments(fx):
+    with pytest.raises(ValueError):
+        fx.Batch([dict(shape=(8,), dx=1.0, lam=2, t=1.0), dict(shape=(8,), dx=1.0, lam=0, t=1.0)])
+    b = fx.Batch([dict(shape=(8,), dx=1.0, lam=2, t=1.0)], dtype=torch.complex128)
+    with pytest.raises(ValueError):
+        b.run([torch.zeros(9, dtype=torch.complex128, device="cuda")])
