@@ -98,16 +98,89 @@ def cpu_baseline(wl, field, lam, dx, t):
                                 f"long-double kernel tables + FP64 per-axis contraction"}
 
 
+def bench_batch(args):
+    """Ragged ensemble: every realization of the workload expanded by one graph launch per step."""
+    import numpy as np
+    import torch
+
+    import paper_1602_03395_amd as fx
+    import workloads
+
+    n = args.members
+    dtype_name = args.dtype or "c64"
+    dtype = torch.complex64 if dtype_name == "c64" else torch.complex128
+    npdt = np.complex64 if dtype_name == "c64" else np.complex128
+    seqs = np.random.SeedSequence(3).spawn(768)
+    dev = torch.device("cuda:0")
+    psis = []
+    t_gen = time.perf_counter()
+    for i in range(n):
+        f = workloads.ensemble_member_3d(workloads.C4_SHAPES[i % 3], seqs[i]).astype(npdt)
+        psis.append(torch.from_numpy(f).to(dev))
+    t_gen = time.perf_counter() - t_gen
+    specs = [dict(shape=tuple(p.shape), dx=(1.0, 1.0, 1.0), lam=(40, 40, 40), t=400.0) for p in psis]
+    t0 = time.perf_counter()
+    b = fx.Batch(specs, dtype=dtype, schedule=args.schedule)
+    t_create = time.perf_counter() - t0
+    outs = [torch.empty_like(p) for p in psis]
+    rhos = [torch.empty(p.shape, dtype=torch.float32 if dtype == torch.complex64 else torch.float64, device=dev)
+            for p in psis]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            b.run(psis, psi_outs=outs, rho_outs=rhos)
+        stream.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            b.run(psis, psi_outs=outs, rho_outs=rhos)
+        ev1.record(stream)
+        stream.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    npts = sum(int(np.prod(p.shape)) for p in psis)
+    result = {
+        "metric": "expanded lattice pts/s + HBM roofline %, FP32/FP64-phase vs FP64 at 1e-5 err",
+        "value": npts / (ms * 1e-3), "unit": "output lattice pts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if dtype == torch.complex64 else "f64", "data": "synthetic",
+        "config": {"workload": "c4_ragged_ensemble", "members": n, "shapes": [list(s) for s in workloads.C4_SHAPES],
+                   "lam": [40, 40, 40], "t": 400.0, "terms_per_member": 64000, "schedule": args.schedule,
+                   "precision": "c64_phase64" if dtype == torch.complex64 else "c128"},
+        "q_term_pts_per_s": npts * 64000 / (ms * 1e-3),
+        "batch_create_s": t_create, "input_generation_s": t_gen, "roofline": None, "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import propagator as OP
+        OP._axis_matrix_cached.cache_clear()
+        f0 = psis[0].cpu().numpy().astype(np.complex128)
+        tc = time.perf_counter()
+        ref = oracle.expand(f0, (1.0, 1.0, 1.0), 1.0, 400.0, (40, 40, 40))
+        dt = time.perf_counter() - tc
+        threads = min(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1)
+        result["cpu_baseline"] = {"value": f0.size / dt, "unit": "output lattice pts/s", "cores": threads,
+                                  "kind": "oracle", "seconds": dt,
+                                  "sample": "realization 0 (32x32x256) of the ensemble, full oracle solve"}
+        got = rhos[0].cpu().numpy().astype(np.float64)
+        rr = oracle.density(ref)
+        result["rel_l2_rho_vs_oracle_member0"] = float(np.linalg.norm(got - rr) / np.linalg.norm(rr))
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c5"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--members", type=int, default=768, help="c4 only: number of realizations")
     ap.add_argument("--dtype", default=None, choices=[None, "c64", "c128"])
     ap.add_argument("--schedule", default="paper", choices=["paper", "axis_factorised"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -126,6 +199,9 @@ def main():
         print(json.dumps({"error": "no GPU visible"}), flush=True)
         sys.exit(3)
 
+    if args.config == "c4":
+        return bench_batch(args)
+
     wl = workloads.make_workload(args.config)
     if args.config == "c5":
         wl.fields = wl.fields[:1]
@@ -135,6 +211,15 @@ def main():
     dx, lam, t = wl.dx, wl.lam, wl.t
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy_mb > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters calibrate the traffic figures
+        nb = args.calibrate_copy_mb << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     psi = torch.from_numpy(field).to(dev)
     plan = fx.Plan(psi.shape, dx, wl.m_over_hbar, t, lam, dtype=dtype, schedule=args.schedule)
     desc = json.loads(plan.describe())
@@ -173,11 +258,15 @@ def main():
     peak_alu = PEAK_FP32_TFLOPS if dtype == torch.complex64 else PEAK_FP64_TFLOPS
     ridge = peak_alu * 1e12 / (PEAK_HBM_GBS * 1e9)
     pass_rows = []
+    seen = {}
     for i, (n_launch, tot_ms) in enumerate(passes):
         p = dict(desc["passes"][i]) if i < len(desc["passes"]) else {"kind": "?"}
+        key = f'{p["kind"]}#{seen.get(p["kind"], 0)}'
+        seen[p["kind"]] = seen.get(p["kind"], 0) + 1
         avg_ms = tot_ms / max(n_launch, 1)
         flops, byts = pass_cost(p, csize)
-        pass_rows.append({"pass": f'{p["kind"]}(axis{p.get("axis")})', "launches_per_step": n_launch / args.steps,
+        pass_rows.append({"pass": f'{p["kind"]}(axis{p.get("axis")})', "key": key,
+                          "launches_per_step": n_launch / args.steps,
                           "avg_ms": avg_ms, "flops": flops, "bytes": byts,
                           "tflops": flops / (avg_ms * 1e-3) / 1e12, "gbs": byts / (avg_ms * 1e-3) / 1e9})
     roofline = None
@@ -191,7 +280,7 @@ def main():
             roofline = {"bound": "hbm", "achieved": dom["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                         "frac": dom["gbs"] / PEAK_HBM_GBS}
         roofline["kernel"] = dom["pass"]
-        roofline["traffic"] = load_traffic(dom["pass"])
+        roofline["traffic"] = load_traffic(dom["key"])
 
     result = {
         "metric": "expanded lattice pts/s + HBM roofline %, FP32/FP64-phase vs FP64 at 1e-5 err",

@@ -109,6 +109,8 @@ namespace fx {
 size_t csize(const fx_plan* p) { return p->dbl ? 16 : 8; }
 
 int choose_ts(const fx_plan* p, Kind kind, int M, int64_t A, int64_t S) {
+    if (p->use_p2 && p2_applicable(kind, M) && (int64_t)p2_lds_bytes(kind, p->dbl, M) <= lds_limit_bytes())
+        return p2_tile_lines(M);
     int ts = std::max(1, p->ts_target / std::max(1, M));
     ts = std::min(ts, std::max(1, kMaxTilePoints / M));
     if (S == 1) ts = (int)std::min<int64_t>(ts, A);
@@ -504,6 +506,7 @@ fx_status fx_plan_create(const fx_problem* prob, fx_plan** out) {
     p->budget = budget;
     if (const char* e = std::getenv("FX_TILE_POINTS")) p->ts_target = std::max(1, std::atoi(e));
     if (const char* e = std::getenv("FX_NO_SPLIT")) p->allow_split = (e[0] != '1');
+    if (const char* e = std::getenv("FX_NO_P2")) p->use_p2 = (e[0] != '1');
     plan_setup_workspace(p, 1);
     *out = p;
     return FX_OK;

@@ -77,6 +77,13 @@ hipError_t launch_gather(bool dbl, const void* const* srcs, void* dst, int64_t n
 hipError_t launch_scatter(bool dbl, const void* src, void* const* dsts, int64_t n_each, int count,
                           int want_rho, void* const* rhos, hipStream_t st);
 size_t pass_lds_bytes(Kind kind, bool dbl, int TS, int M);
+// Compile-time specialised E / EA kernels for power-of-two axes of 8..2048 points (kernels_p2.hip):
+// they always take tiles of p2_tile_lines(M) lines.
+bool p2_applicable(Kind kind, int M);
+int p2_tile_lines(int M);
+size_t p2_lds_bytes(Kind kind, bool dbl, int M);
+hipError_t launch_pass_p2(Kind kind, bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g,
+                          int accumulate, void* rho, hipStream_t st);
 int lds_limit_bytes();
 
 // Host-built FP64 tables (tables.cpp).

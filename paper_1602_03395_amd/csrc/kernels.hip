@@ -34,310 +34,9 @@
 #include <set>
 
 #include "fx_internal.h"
+#include "device_common.h"
 
 namespace fx {
-
-template <typename T> struct CT;
-template <> struct CT<float> { using type = float2; };
-template <> struct CT<double> { using type = double2; };
-template <typename T> using C = typename CT<T>::type;
-
-template <typename T> __device__ __forceinline__ C<T> mk(T x, T y) { C<T> r; r.x = x; r.y = y; return r; }
-template <typename T> __device__ __forceinline__ C<T> cadd(C<T> a, C<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
-template <typename T> __device__ __forceinline__ C<T> csub(C<T> a, C<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
-template <typename T> __device__ __forceinline__ C<T> cmul(C<T> a, C<T> b) {
-    return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-// a * conj(b)
-template <typename T> __device__ __forceinline__ C<T> cmulc(C<T> a, C<T> b) {
-    return mk<T>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
-}
-// acc + a * b
-template <typename T> __device__ __forceinline__ C<T> cfma(C<T> acc, C<T> a, C<T> b) {
-    return mk<T>(acc.x + a.x * b.x - a.y * b.y, acc.y + a.x * b.y + a.y * b.x);
-}
-// acc + a * conj(b)
-template <typename T> __device__ __forceinline__ C<T> cfmac(C<T> acc, C<T> a, C<T> b) {
-    return mk<T>(acc.x + a.x * b.x + a.y * b.y, acc.y + a.y * b.x - a.x * b.y);
-}
-template <typename T> __device__ __forceinline__ C<T> cscale(C<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
-// multiply by -i (forward) or +i (inverse)
-template <typename T> __device__ __forceinline__ C<T> rot(C<T> a, bool inv) {
-    return inv ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
-}
-
-// ------------------------------------------------------------------------------------
-// Register butterflies: v <- DFT_R(v), sign - (forward) or + (inverse), unnormalised.
-// ------------------------------------------------------------------------------------
-template <typename T, int R> struct Bfly;
-
-template <typename T> struct Bfly<T, 2> {
-    static __device__ __forceinline__ void run(C<T>* v, bool) {
-        C<T> a = v[0], b = v[1];
-        v[0] = cadd<T>(a, b);
-        v[1] = csub<T>(a, b);
-    }
-};
-
-template <typename T> struct Bfly<T, 3> {
-    static __device__ __forceinline__ void run(C<T>* v, bool inv) {
-        const T h = (T)0.86602540378443864676372317075294;  // sin(pi/3)
-        C<T> s = cadd<T>(v[1], v[2]);
-        C<T> d = csub<T>(v[1], v[2]);
-        C<T> m = mk<T>(v[0].x - (T)0.5 * s.x, v[0].y - (T)0.5 * s.y);
-        C<T> r = rot<T>(cscale<T>(d, h), inv);  // -i h d (forward)
-        v[0] = cadd<T>(v[0], s);
-        v[1] = cadd<T>(m, r);
-        v[2] = csub<T>(m, r);
-    }
-};
-
-template <typename T> struct Bfly<T, 4> {
-    static __device__ __forceinline__ void run(C<T>* v, bool inv) {
-        C<T> t0 = cadd<T>(v[0], v[2]);
-        C<T> t1 = csub<T>(v[0], v[2]);
-        C<T> t2 = cadd<T>(v[1], v[3]);
-        C<T> t3 = rot<T>(csub<T>(v[1], v[3]), inv);
-        v[0] = cadd<T>(t0, t2);
-        v[2] = csub<T>(t0, t2);
-        v[1] = cadd<T>(t1, t3);
-        v[3] = csub<T>(t1, t3);
-    }
-};
-
-template <typename T> struct Bfly<T, 8> {
-    static __device__ __forceinline__ void run(C<T>* v, bool inv) {
-        const T r2 = (T)0.70710678118654752440084436210485;  // sqrt(1/2)
-        C<T> e[4] = {v[0], v[2], v[4], v[6]};
-        C<T> o[4] = {v[1], v[3], v[5], v[7]};
-        Bfly<T, 4>::run(e, inv);
-        Bfly<T, 4>::run(o, inv);
-        // o[u] *= exp(-+ 2 pi i u / 8)
-        C<T> o1 = o[1];
-        o[1] = inv ? mk<T>(r2 * (o1.x - o1.y), r2 * (o1.x + o1.y)) : mk<T>(r2 * (o1.x + o1.y), r2 * (o1.y - o1.x));
-        o[2] = rot<T>(o[2], inv);
-        C<T> o3 = o[3];
-        o[3] = inv ? mk<T>(-r2 * (o3.x + o3.y), r2 * (o3.x - o3.y)) : mk<T>(r2 * (o3.y - o3.x), -r2 * (o3.x + o3.y));
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            v[u] = cadd<T>(e[u], o[u]);
-            v[u + 4] = csub<T>(e[u], o[u]);
-        }
-    }
-};
-
-// Division by a workgroup-uniform divisor: shifts for powers of two, otherwise a
-// float-reciprocal quotient corrected to the exact one (x < 2^22), else the
-// integer divide.
-struct FDiv {
-    int d;
-    int sh;
-    float inv;
-    bool p2;
-    __device__ __forceinline__ explicit FDiv(int dd) : d(dd) {
-        p2 = (dd & (dd - 1)) == 0;
-        sh = p2 ? (__ffs(dd) - 1) : 0;
-        inv = 1.0f / (float)dd;
-    }
-    __device__ __forceinline__ int div(int x) const {
-        if (p2) return x >> sh;
-        if (x >= (1 << 22)) return x / d;
-        int q = (int)((float)x * inv);
-        int r = x - q * d;
-        if (r < 0) { q -= 1; r += d; }
-        if (r >= d) { q += 1; }
-        return q;
-    }
-    __device__ __forceinline__ int mod(int x) const { return x - div(x) * d; }
-};
-
-template <typename T> __device__ __forceinline__ C<T> root(const C<T>* __restrict__ tw, int idx, bool inv) {
-    C<T> w = tw[idx];
-    if (inv) w.y = -w.y;
-    return w;
-}
-
-// One Stockham stage with a compile-time radix over nl lines of length N at LDS stride ls.
-template <typename T, int R>
-__device__ void stage_r(const C<T>* __restrict__ X, C<T>* __restrict__ Y, int nl, int ls, int N, int Ns,
-                        const C<T>* __restrict__ tw, int tws, bool inv, const C<T>* __restrict__ post) {
-    const int nb = N / R;
-    const int total = nl * nb;
-    const int tstep = (N / (Ns * R)) * tws;
-    const FDiv fnb(nb), fns(Ns);
-    for (int j = threadIdx.x; j < total; j += blockDim.x) {
-        const int l = fnb.div(j);
-        const int jj = j - l * nb;
-        const C<T>* x = X + l * ls;
-        C<T>* y = Y + l * ls;
-        const int k = fns.mod(jj);
-        C<T> v[R];
-#pragma unroll
-        for (int t = 0; t < R; ++t) v[t] = x[jj + t * nb];
-        if (Ns > 1) {
-#pragma unroll
-            for (int t = 1; t < R; ++t) v[t] = cmul<T>(v[t], root<T>(tw, t * k * tstep, inv));
-        }
-        Bfly<T, R>::run(v, inv);
-        const int base = (jj - k) * R + k;
-        if (post) {
-#pragma unroll
-            for (int t = 0; t < R; ++t) y[base + t * Ns] = cmul<T>(v[t], post[base + t * Ns]);
-        } else {
-#pragma unroll
-            for (int t = 0; t < R; ++t) y[base + t * Ns] = v[t];
-        }
-    }
-}
-
-// Any radix: direct R-point DFT per butterfly, roots from the same table.
-template <typename T>
-__device__ void stage_gen(const C<T>* __restrict__ X, C<T>* __restrict__ Y, int nl, int ls, int N, int Ns,
-                          int R, const C<T>* __restrict__ tw, int tws, bool inv, const C<T>* __restrict__ post) {
-    const int nb = N / R;
-    const int total = nl * nb;
-    const int tstep = (N / (Ns * R)) * tws;
-    const int rstep = nb * tws;
-    for (int j = threadIdx.x; j < total; j += blockDim.x) {
-        const int l = j / nb;
-        const int jj = j - l * nb;
-        const C<T>* x = X + l * ls;
-        C<T>* y = Y + l * ls;
-        const int k = jj % Ns;
-        const int base = (jj / Ns) * Ns * R + k;
-        for (int u = 0; u < R; ++u) {
-            C<T> acc = mk<T>(0, 0);
-            for (int t = 0; t < R; ++t) {
-                C<T> v = x[jj + t * nb];
-                if (Ns > 1 && t > 0) v = cmul<T>(v, root<T>(tw, t * k * tstep, inv));
-                acc = cfma<T>(acc, v, root<T>(tw, ((t * u) % R) * rstep, inv));
-            }
-            y[base + u * Ns] = post ? cmul<T>(acc, post[base + u * Ns]) : acc;
-        }
-    }
-}
-
-// Transform nl lines of length pl.n held in X (stride ls); returns the buffer holding the result.
-// With `post` (a global row of pl.n values) the output is multiplied by it elementwise in the
-// last stage (the chirp of (presB) fused into the forward transform).
-template <typename T>
-__device__ C<T>* lds_fft(C<T>* X, C<T>* Y, int nl, int ls, const RadixPlan& pl, const C<T>* __restrict__ tw,
-                         int tws, bool inv, const C<T>* __restrict__ post = nullptr) {
-    int Ns = 1;
-    const int N = pl.n;
-    if (pl.nst == 0 && post) {
-        for (int e = threadIdx.x; e < nl * N; e += blockDim.x) {
-            const int l = e / N;
-            const int n = e - l * N;
-            X[l * ls + n] = cmul<T>(X[l * ls + n], post[n]);
-        }
-        __syncthreads();
-    }
-    for (int s = 0; s < pl.nst; ++s) {
-        const int R = pl.rad[s];
-        const C<T>* pp = (s + 1 == pl.nst) ? post : nullptr;
-        switch (R) {
-            case 2: stage_r<T, 2>(X, Y, nl, ls, N, Ns, tw, tws, inv, pp); break;
-            case 3: stage_r<T, 3>(X, Y, nl, ls, N, Ns, tw, tws, inv, pp); break;
-            case 4: stage_r<T, 4>(X, Y, nl, ls, N, Ns, tw, tws, inv, pp); break;
-            case 8: stage_r<T, 8>(X, Y, nl, ls, N, Ns, tw, tws, inv, pp); break;
-            default: stage_gen<T>(X, Y, nl, ls, N, Ns, R, tw, tws, inv, pp); break;
-        }
-        __syncthreads();
-        C<T>* t = X;
-        X = Y;
-        Y = t;
-        Ns *= R;
-    }
-    return X;
-}
-
-// Z[l][u] = sum_{c<g} Y[l][u + c P] for nl lines (line stride ls). Several threads share an
-// output when there are few outputs; their partial sums meet in the scratch W (blockDim entries).
-template <typename T>
-__device__ void fold_lines(const C<T>* __restrict__ Y, C<T>* __restrict__ Z, C<T>* __restrict__ W, int nl, int ls,
-                           int P, int g, const FDiv& fP) {
-    const int outs = nl * P;
-    int K = 1;
-    while (K * 2 <= g && outs * K * 2 <= (int)blockDim.x) K *= 2;
-    if (K == 1) {
-        for (int e = threadIdx.x; e < outs; e += blockDim.x) {
-            const int l = fP.div(e);
-            const int u = e - l * P;
-            const C<T>* y = Y + l * ls + u;
-            C<T> acc = mk<T>(0, 0);
-            for (int c = 0; c < g; ++c) acc = cadd<T>(acc, y[c * P]);
-            Z[l * ls + u] = acc;
-        }
-        __syncthreads();
-        return;
-    }
-    const int kb = __ffs(K) - 1;
-    const int t = threadIdx.x;
-    if (t < outs * K) {
-        const int o = t >> kb;
-        const int kk = t & (K - 1);
-        const int l = fP.div(o);
-        const int u = o - l * P;
-        const C<T>* y = Y + l * ls + u;
-        C<T> acc = mk<T>(0, 0);
-        for (int c = kk; c < g; c += K) acc = cadd<T>(acc, y[c * P]);
-        W[t] = acc;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < outs; e += blockDim.x) {
-        const int l = fP.div(e);
-        const int u = e - l * P;
-        C<T> acc = W[e << kb];
-        for (int kk = 1; kk < K; ++kk) acc = cadd<T>(acc, W[(e << kb) + kk]);
-        Z[l * ls + u] = acc;
-    }
-    __syncthreads();
-}
-
-// ------------------------------------------------------------------------------------
-// Tile geometry
-// ------------------------------------------------------------------------------------
-struct Tile {
-    int64_t a0;
-    int64_t s0;
-    int nl;
-};
-
-__device__ __forceinline__ Tile decode_tile(const PassGeom& g, int64_t t) {
-    Tile r;
-    if (g.S == 1) {
-        r.a0 = t * g.TS;
-        r.s0 = 0;
-        r.nl = (int)min((int64_t)g.TS, g.A - r.a0);
-    } else {
-        const int64_t nsc = (g.S + g.TS - 1) / g.TS;
-        r.a0 = t / nsc;
-        r.s0 = (t - r.a0 * nsc) * g.TS;
-        r.nl = (int)min((int64_t)g.TS, g.S - r.s0);
-    }
-    return r;
-}
-
-// Element e of a tile of nl lines of length L -> (line l, position n) and global offset in slice `slice`.
-// `fd` divides by L when the lines are contiguous (S == 1) and by nl otherwise.
-__device__ __forceinline__ int64_t tile_elem(const PassGeom& g, const Tile& tl, int64_t slice, int L,
-                                             const FDiv& fd, int e, int& l, int& n) {
-    if (g.S == 1) {
-        l = fd.div(e);
-        n = e - l * L;
-        return (slice * g.A + tl.a0 + l) * L + n;
-    }
-    n = fd.div(e);
-    l = e - n * tl.nl;
-    return ((slice * g.A + tl.a0) * L + n) * g.S + tl.s0 + l;
-}
-
-__device__ __forceinline__ FDiv tile_div(const PassGeom& g, const Tile& tl, int L) {
-    return FDiv(g.S == 1 ? L : tl.nl);
-}
-
-template <typename T> __device__ __forceinline__ const C<T>* tab(const void* p) { return (const C<T>*)p; }
 
 // Copies the axis' FFT roots into LDS (after the tile buffers) once per workgroup.
 template <typename T>
@@ -365,12 +64,15 @@ __global__ __launch_bounds__(kThreads) void k_E(const C<T>* __restrict__ in, C<T
     const C<T>* tw = stage_roots<T>(B1 + g.TS * M, ax);
     C<T>* Wsc = B1 + g.TS * M + M;  // fold scratch, kThreads entries
     const T scale = (T)ax.scale;
-    const int64_t total = g.Qin * g.qn * g.ntiles;
-    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
-        const int64_t tt = bid % g.ntiles;
-        const int64_t rest = bid / g.ntiles;
-        const int qq = (int)(rest % g.qn);
-        const int64_t qi = rest / g.qn;
+    const int total = (int)(g.Qin * g.qn * g.ntiles);  // < 2^31, checked on the host
+    const FDiv fnt((int)g.ntiles), fqn(g.qn);
+    const bool wm = g.TS >= (int)(blockDim.x >> 6);  // every wave owns at least one line of a full tile
+    for (int bid = blockIdx.x; bid < total; bid += gridDim.x) {
+        const int rest = fnt.div(bid);
+        const int tt = bid - rest * (int)g.ntiles;
+        const int qi32 = fqn.div(rest);
+        const int qq = rest - qi32 * g.qn;
+        const int64_t qi = qi32;
         const int q = g.qb + qq;
         const Tile tl = decode_tile(g, tt);
         const FDiv fdM = tile_div(g, tl, M), fdP = tile_div(g, tl, P);
@@ -381,10 +83,12 @@ __global__ __launch_bounds__(kThreads) void k_E(const C<T>* __restrict__ in, C<T
             B0[l * M + n] = cmul<T>(in[off], TA[q * M + n]);
         }
         __syncthreads();
-        C<T>* Y = lds_fft<T>(B0, B1, nl, M, ax.fm, tw, 1, false, TB + q * M);
+        C<T>* Y = lds_fft<T>(B0, B1, nl, M, ax.fm, tw, 1, false, TB + q * M, wm);
         C<T>* Z = (Y == B0) ? B1 : B0;
-        fold_lines<T>(Y, Z, Wsc, nl, M, P, ax.g, fP);
-        C<T>* Rz = lds_fft<T>(Z, Y, nl, M, ax.fp, tw, ax.g, true);
+        if (wm) fold_lines_wave<T>(Y, Z, nl, M, P, ax.g);
+        else fold_lines<T>(Y, Z, Wsc, nl, M, P, ax.g, fP);
+        C<T>* Rz = lds_fft<T>(Z, Y, nl, M, ax.fp, tw, ax.g, true, nullptr, wm);
+        if (wm) __syncthreads();
         const int64_t qo = qi * g.qn + qq;
         for (int e = threadIdx.x; e < nl * P; e += blockDim.x) {
             int l, u;
@@ -449,10 +153,14 @@ __global__ __launch_bounds__(kThreads) void k_EA(const C<T>* __restrict__ in, C<
     const C<T>* tw = stage_roots<T>(B1 + g.TS * M, ax);
     C<T>* Wsc = B1 + g.TS * M + M;  // fold scratch, kThreads entries
     const T scale = (T)ax.scale;
-    const int64_t total = g.Qin * g.ntiles;
-    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
-        const int64_t tt = bid % g.ntiles;
-        const int64_t qi = bid / g.ntiles;
+    const int total = (int)(g.Qin * g.ntiles);  // < 2^31, checked on the host
+    const FDiv fnt((int)g.ntiles);
+    const bool wm = g.TS >= (int)(blockDim.x >> 6);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+    for (int bid = blockIdx.x; bid < total; bid += gridDim.x) {
+        const int qi32 = fnt.div(bid);
+        const int tt = bid - qi32 * (int)g.ntiles;
+        const int64_t qi = qi32;
         const Tile tl = decode_tile(g, tt);
         const FDiv fdM = tile_div(g, tl, M), fdP = tile_div(g, tl, P);
         const int nl = tl.nl;
@@ -475,15 +183,23 @@ __global__ __launch_bounds__(kThreads) void k_EA(const C<T>* __restrict__ in, C<
         __syncthreads();
         for (int i = 0; i < g.qn; ++i) {
             const int q = g.qb + i;
-            for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-                const int n = fM.mod(e);
-                B0[e] = cmul<T>(RAW[e], TA[q * M + n]);
+            if (wm) {
+                for (int l = wv; l < nl; l += nwv)
+                    for (int n = lane; n < M; n += 64) B0[l * M + n] = cmul<T>(RAW[l * M + n], TA[q * M + n]);
+                wave_sync();
+            } else {
+                for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+                    const int n = fM.mod(e);
+                    B0[e] = cmul<T>(RAW[e], TA[q * M + n]);
+                }
+                __syncthreads();
             }
-            __syncthreads();
-            C<T>* Y = lds_fft<T>(B0, B1, nl, M, ax.fm, tw, 1, false, TB + q * M);
+            C<T>* Y = lds_fft<T>(B0, B1, nl, M, ax.fm, tw, 1, false, TB + q * M, wm);
             C<T>* Z = (Y == B0) ? B1 : B0;
-            fold_lines<T>(Y, Z, Wsc, nl, M, P, ax.g, fP);
-            C<T>* Rz = lds_fft<T>(Z, Y, nl, M, ax.fp, tw, ax.g, true);
+            if (wm) fold_lines_wave<T>(Y, Z, nl, M, P, ax.g);
+            else fold_lines<T>(Y, Z, Wsc, nl, M, P, ax.g, fP);
+            C<T>* Rz = lds_fft<T>(Z, Y, nl, M, ax.fp, tw, ax.g, true, nullptr, wm);
+            if (wm) __syncthreads();
 #pragma unroll
             for (int k = 0; k < ACCN; ++k) {
                 const int e = threadIdx.x + k * kThreads;
@@ -887,6 +603,10 @@ size_t pass_lds_bytes(Kind kind, bool dbl, int TS, int M) {
 
 hipError_t launch_pass(Kind kind, bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g,
                        int accumulate, void* rho, hipStream_t st) {
+    // tile kernels index their tiles with 32-bit integers
+    if (g.Qin * g.qn * g.ntiles >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    if (p2_applicable(kind, ax.M) && g.TS == p2_tile_lines(ax.M))
+        return launch_pass_p2(kind, dbl, in, out, ax, g, accumulate, rho, st);
     return dbl ? launch_T<double>(kind, in, out, ax, g, accumulate, rho, st)
                : launch_T<float>(kind, in, out, ax, g, accumulate, rho, st);
 }

@@ -1,0 +1,129 @@
+"""Summaries of rocprofv3 output for the committed profiles.
+
+    python -m paper_1602_03395_amd.profiling stats <kernel_stats.csv>
+        markdown table of per-kernel call counts and durations
+    python -m paper_1602_03395_amd.profiling counters <counter_collection.csv> <COUNTER>
+        average counter value per dispatch for every kernel name
+    python -m paper_1602_03395_amd.profiling traffic <fetch.csv> <write.csv> <copy_MiB> <calls> <out.json>
+        HBM bytes per dispatch of every pass of the schedule (key 'kind#ordinal', ordinal counted
+        within one expansion call; <calls> = expansion calls in the profiled run) from FETCH_SIZE
+        and WRITE_SIZE (KiB per dispatch), each scaled by the factor that makes the plain copy
+        kernel of known size read (and write) exactly its size; stamped with the kernels' hash
+
+Only the csv files rocprofv3 writes are read; nothing here touches the GPU.
+"""
+
+from __future__ import annotations
+
+import collections
+import csv
+import hashlib
+import json
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def short_name(name: str) -> str:
+    """fx::k_EA<float, 8>(...) -> k_EA<float,8>; other kernels keep a trimmed name."""
+    m = re.search(r"(k_[A-Za-z]+<[^>]*>)", name)
+    if m:
+        return m.group(1).replace(" ", "")
+    return name.split("(")[0][-80:]
+
+
+def stats(path: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    out = ["| kernel | calls | total ms | avg us | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows:
+        out.append("| %s | %s | %.3f | %.2f | %.1f |" % (
+            short_name(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+            float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+    return "\n".join(out)
+
+
+def counters(path: str, counter: str):
+    acc = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name") != counter:
+            continue
+        acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
+
+
+def kernels_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(HERE, "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+PASS_KIND = re.compile(r"fx::k_(EAH|EA|EH|AH|E|A)<")
+
+
+def _pass_dispatches(path: str, counter: str):
+    """[(dispatch_id, kind, value)] of the pass kernels, in dispatch order."""
+    out = []
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name") != counter:
+            continue
+        m = PASS_KIND.search(r["Kernel_Name"])
+        if m:
+            out.append((int(r["Dispatch_Id"]), m.group(1), float(r["Counter_Value"])))
+    out.sort()
+    return out
+
+
+def _per_pass(rows, calls_per_run: int):
+    """Average value per (kind, ordinal within one expansion call); key 'kind#ordinal'."""
+    by_kind = collections.defaultdict(list)
+    for _, kind, v in rows:
+        by_kind[kind].append(v)
+    res = {}
+    for kind, vals in by_kind.items():
+        per_call = max(1, len(vals) // max(1, calls_per_run))
+        for i, v in enumerate(vals):
+            key = f"{kind}#{i % per_call}"
+            res.setdefault(key, []).append(v)
+    return {k: (sum(v) / len(v), len(v)) for k, v in res.items()}
+
+
+def traffic(fetch_csv: str, write_csv: str, copy_mib: float, calls: int, out_json: str):
+    f_avg, _ = counters(fetch_csv, "FETCH_SIZE")
+    w_avg, _ = counters(write_csv, "WRITE_SIZE")
+    copy_kib = copy_mib * 1024.0
+    copies = [k for k in f_avg if "copy" in k.lower()]
+    if not copies:
+        raise SystemExit("no copy kernel found in the counter file")
+    ck = max(copies, key=lambda k: f_avg[k])
+    f_scale = copy_kib / f_avg[ck]
+    w_scale = copy_kib / w_avg[ck] if w_avg.get(ck) else 1.0
+    fp = _per_pass(_pass_dispatches(fetch_csv, "FETCH_SIZE"), calls)
+    wp = _per_pass(_pass_dispatches(write_csv, "WRITE_SIZE"), calls)
+    res = {"kernels_hash": kernels_hash(), "copy_kernel": short_name(ck), "copy_MiB": copy_mib,
+           "copy_fetch_KiB_counter": f_avg[ck], "copy_write_KiB_counter": w_avg.get(ck),
+           "fetch_scale": f_scale, "write_scale": w_scale, "passes": {}}
+    for key, (fv, n) in fp.items():
+        fb = fv * 1024.0 * f_scale
+        wb = wp.get(key, (0.0, 0))[0] * 1024.0 * w_scale
+        res["passes"][key] = {"dispatches": n, "fetch_bytes": fb, "write_bytes": wb,
+                              "hbm_bytes_per_launch": fb + wb}
+    json.dump(res, open(out_json, "w"), indent=1)
+    return res
+
+
+if __name__ == "__main__":
+    cmd = sys.argv[1]
+    if cmd == "stats":
+        print(stats(sys.argv[2]))
+    elif cmd == "counters":
+        avg, n = counters(sys.argv[2], sys.argv[3])
+        for k in sorted(avg, key=lambda x: -avg[x]):
+            print(f"{short_name(k):40s} dispatches {n[k]:5d}  avg {avg[k]:.4g}")
+    elif cmd == "traffic":
+        print(json.dumps(traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), int(sys.argv[5]), sys.argv[6]),
+                         indent=1))
+    else:
+        raise SystemExit(__doc__)
