@@ -175,6 +175,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--members", type=int, default=768, help="c4 only: number of realizations")
+    ap.add_argument("--member", type=int, default=None,
+                    help="c4 only: expand this single realization through one plan (per-pass timing)")
     ap.add_argument("--dtype", default=None, choices=[None, "c64", "c128"])
     ap.add_argument("--schedule", default="paper", choices=["paper", "axis_factorised"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -199,10 +201,13 @@ def main():
         print(json.dumps({"error": "no GPU visible"}), flush=True)
         sys.exit(3)
 
-    if args.config == "c4":
+    if args.config == "c4" and args.member is None:
         return bench_batch(args)
 
-    wl = workloads.make_workload(args.config)
+    if args.config == "c4":
+        wl = workloads.make_c4(members=[args.member])
+    else:
+        wl = workloads.make_workload(args.config)
     if args.config == "c5":
         wl.fields = wl.fields[:1]
     dtype_name = args.dtype or wl.dtype

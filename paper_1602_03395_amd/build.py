@@ -17,7 +17,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfx.so")
-SOURCES = ["fx.cpp", "tables.cpp", "batch.cpp", "kernels.hip", "kernels_p2.hip"]
+SOURCES = ["fx.cpp", "tables.cpp", "batch.cpp", "kernels.hip", "kernels_p2.hip", "kernels_ct.hip"]
 
 
 def hipcc() -> str:
@@ -28,23 +28,38 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = True, arch: str = "gfx950") -> str:
+    """Compiles every source to an object (in parallel) and links libfx.so."""
+    import concurrent.futures as cf
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    common = [hipcc(), f"--offload-arch={arch}", "-O3", "-std=c++17", "-fPIC",
+              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+              "-Wno-unused-command-line-argument", "-I", os.path.join(HERE, "..", "include")]
+
+    def compile_one(src):
+        obj = os.path.join(objdir, src + ".o")
+        cmd = common + ["-c", "-o", obj, os.path.join(CSRC, src)]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        return src, obj, cmd, res
+
+    objs = []
+    workers = min(len(SOURCES), max(1, os.cpu_count() or 1))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        for src, obj, cmd, res in ex.map(compile_one, SOURCES):
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            if res.returncode != 0:
+                sys.stderr.write(res.stdout + res.stderr)
+                raise RuntimeError(f"hipcc failed on {src}")
+            objs.append(obj)
     out_tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={arch}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-command-line-argument",
-           "-I", os.path.join(HERE, "..", "include"),
-           "-o", out_tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+    link = [hipcc(), f"--offload-arch={arch}", "-shared", "-fPIC", "-o", out_tmp] + objs
     if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
+        print(" ".join(link), flush=True)
+    res = subprocess.run(link, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed")
-    if verbose and res.stderr.strip():
-        # keep warnings visible but short
-        lines = [ln for ln in res.stderr.splitlines() if "packed-fp32-ops" not in ln]
-        if lines:
-            sys.stderr.write("\n".join(lines[:40]) + "\n")
+        raise RuntimeError("link failed")
     os.replace(out_tmp, LIB)
     return LIB
 

@@ -111,6 +111,8 @@ size_t csize(const fx_plan* p) { return p->dbl ? 16 : 8; }
 int choose_ts(const fx_plan* p, Kind kind, int M, int64_t A, int64_t S) {
     if (p->use_p2 && p2_applicable(kind, M) && (int64_t)p2_lds_bytes(kind, p->dbl, M) <= lds_limit_bytes())
         return p2_tile_lines(M);
+    if (p->use_p2 && ct_applicable(kind, M) && (int64_t)ct_lds_bytes(kind, p->dbl, M) <= lds_limit_bytes())
+        return ct_tile_lines(M);
     int ts = std::max(1, p->ts_target / std::max(1, M));
     ts = std::min(ts, std::max(1, kMaxTilePoints / M));
     if (S == 1) ts = (int)std::min<int64_t>(ts, A);

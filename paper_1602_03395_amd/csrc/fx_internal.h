@@ -84,6 +84,13 @@ int p2_tile_lines(int M);
 size_t p2_lds_bytes(Kind kind, bool dbl, int M);
 hipError_t launch_pass_p2(Kind kind, bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g,
                           int accumulate, void* rho, hipStream_t st);
+// Compile-time E / EA kernels for axis lengths 3 * 2^k, 12..1536 (kernels_ct.hip), tiles of
+// ct_tile_lines(M) lines.
+bool ct_applicable(Kind kind, int M);
+int ct_tile_lines(int M);
+size_t ct_lds_bytes(Kind kind, bool dbl, int M);
+hipError_t launch_pass_ct(Kind kind, bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g,
+                          int accumulate, void* rho, hipStream_t st);
 int lds_limit_bytes();
 
 // Host-built FP64 tables (tables.cpp).

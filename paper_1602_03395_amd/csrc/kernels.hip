@@ -607,6 +607,8 @@ hipError_t launch_pass(Kind kind, bool dbl, const void* in, void* out, const Axi
     if (g.Qin * g.qn * g.ntiles >= (int64_t(1) << 31)) return hipErrorInvalidValue;
     if (p2_applicable(kind, ax.M) && g.TS == p2_tile_lines(ax.M))
         return launch_pass_p2(kind, dbl, in, out, ax, g, accumulate, rho, st);
+    if (ct_applicable(kind, ax.M) && g.TS == ct_tile_lines(ax.M))
+        return launch_pass_ct(kind, dbl, in, out, ax, g, accumulate, rho, st);
     return dbl ? launch_T<double>(kind, in, out, ax, g, accumulate, rho, st)
                : launch_T<float>(kind, in, out, ax, g, accumulate, rho, st);
 }

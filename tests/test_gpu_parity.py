@@ -58,6 +58,8 @@ CASES = [
     ((1, 8), (3, 2), (1.0, 1.0), 3.0, 1.0, 0.0),
     ((16, 384), (2, 3), (1.0, 1.0), 50.0, 1.0, 0.0),
     ((3,), (1,), (1.0,), 1.0, 1.0, 0.0),
+    ((12, 24, 48), (2, 3, 4), (1.0, 1.0, 1.0), 7.0, 1.0, 0.1),
+    ((96,), (6,), (1.0,), 30.0, 1.0, 0.0),
 ]
 
 
