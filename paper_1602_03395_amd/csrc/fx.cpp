@@ -447,6 +447,7 @@ fx_status fx_plan_create(const fx_problem* prob, fx_plan** out) {
         ad.scale = 1.0 / (double)ap.M;
         ad.fm = make_radix_plan(ad.M);
         ad.fp = make_radix_plan(ad.P);
+        ad.fg = make_radix_plan(ad.g);
         tabs[pa] = build_axis_tables(ap);
         if (!(ap.M == 1 && ap.lam == 1)) p->act[p->nact++] = pa;
     }

@@ -46,6 +46,7 @@ struct AxisDev {
     double scale = 1; // 1 / M
     RadixPlan fm;     // radix plan of length M
     RadixPlan fp;     // radix plan of length P
+    RadixPlan fg;     // radix plan of length g (structured accumulate)
 };
 
 // Geometry of one pass along an axis of a tensor laid out as [Qin][A][L][S].
@@ -61,6 +62,10 @@ struct PassGeom {
 };
 
 enum class Kind { E, A, EA, EH, AH, EAH };
+
+// Groups per tile of the structured accumulate (A via a g-point transform over q mod g).
+int as_tile_groups(int g);
+size_t as_lds_bytes(bool dbl, int g, int M);
 
 struct KernelCfg {
     int ts_target = 2048;  // preferred TS*L points per tile

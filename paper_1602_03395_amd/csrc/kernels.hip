@@ -30,6 +30,7 @@
 // (S > 1) they walk across the TS adjacent lines.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 #include <set>
 
@@ -131,6 +132,81 @@ __global__ __launch_bounds__(kThreads) void k_A(const C<T>* __restrict__ in, C<T
             dst[e] = acc;
             if (rdst) rdst[e] = acc.x * acc.x + acc.y * acc.y;
         }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// AS: the same sum as A, organised by the n'' sample. The g output points nb = n0 + P c
+// (c < g) read the same input value for every q, and Tf[q][n0 + P c] equals
+// Tf[q][n0] exp(2 pi i q c / g) exactly (the twiddle (presf) advances by q/g cycles per step
+// P), so
+//   out[n0 + P c] = sum_{q' < g} exp(2 pi i q' c / g) H[q'],
+//   H[q'] = sum_{q = q' mod g} Tf[q][n0] in_q[r(n0)],
+// i.e. one pass over the inputs and a g-point inverse transform per (n0, s) group.
+// Groups are numbered row-major over (qo, a, n0, s); a tile holds TSL groups.
+// ------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_AS(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
+                                                 PassGeom g, int accumulate, T* __restrict__ rho, int TSL) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int M = ax.M, P = ax.P, G = ax.g;
+    const int S = (int)g.S;
+    const int PS = P * S;
+    C<T>* H0 = (C<T>*)smem;
+    C<T>* H1 = H0 + TSL * G;
+    C<T>* tw = H1 + TSL * G;
+    const C<T>* twg = (const C<T>*)ax.tw;
+    for (int i = threadIdx.x; i < M; i += blockDim.x) tw[i] = twg[i];
+    __syncthreads();
+    const C<T>* Tf = (const C<T>*)ax.Tf;
+    const int ngroups = (int)(g.Qin * g.A * PS);  // < 2^31, checked on the host
+    const int ntile = (ngroups + TSL - 1) / TSL;
+    const FDiv fPS(PS), fS(S), fP(P), fA((int)g.A), fG(G);
+    const int64_t step = g.A * (int64_t)PS;  // one magnification slice of the input
+    const int q0r = fG.mod(g.qb);
+    for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
+        const int base = t * TSL;
+        const int nt = min(TSL, ngroups - base);
+        // work items (residue qr, group p): consecutive threads take consecutive groups
+        const FDiv fnt(nt);
+        for (int it = threadIdx.x; it < nt * G; it += blockDim.x) {
+            const int qr = fnt.div(it);
+            const int p = it - qr * nt;
+            const int gi = base + p;
+            const int row = fPS.div(gi);
+            const int rem = gi - row * PS;
+            const int n0 = fS.div(rem);
+            const int s = rem - n0 * S;
+            const int qo = fA.div(row);
+            const int a = row - qo * (int)g.A;
+            const int r = fP.mod(n0 * ax.lg);
+            const C<T>* src = in + (((int64_t)qo * g.qn) * g.A + a) * (int64_t)PS + r * S + s;
+            const C<T>* tf = Tf + g.qb * M + n0;
+            int i0 = qr - q0r;  // first i with (qb + i) mod G == qr
+            if (i0 < 0) i0 += G;
+            C<T> acc = mk<T>(0, 0);
+            for (int i = i0; i < g.qn; i += G) acc = cfma<T>(acc, tf[i * M], src[i * step]);
+            H0[p * G + qr] = acc;
+        }
+        for (int p = nt + threadIdx.x; p < TSL; p += blockDim.x)
+            for (int qr = 0; qr < G; ++qr) H0[p * G + qr] = mk<T>(0, 0);
+        __syncthreads();
+        C<T>* R = lds_fft<T>(H0, H1, TSL, G, ax.fg, tw, M / G, true);
+        for (int e = threadIdx.x; e < nt * G; e += blockDim.x) {
+            const int c = fnt.div(e);
+            const int p = e - c * nt;
+            const int gi = base + p;
+            const int row = fPS.div(gi);
+            const int rem = gi - row * PS;
+            const int n0 = fS.div(rem);
+            const int s = rem - n0 * S;
+            const int64_t o = ((int64_t)row * M + n0 + P * c) * S + s;
+            C<T> v = R[p * G + c];
+            if (accumulate) v = cadd<T>(v, out[o]);
+            out[o] = v;
+            if (rho) rho[o] = v.x * v.x + v.y * v.y;
+        }
+        __syncthreads();
     }
 }
 
@@ -566,6 +642,20 @@ hipError_t launch_T(Kind kind, const void* in, void* out, const AxisDev& ax, con
             return hipGetLastError();
         }
         case Kind::A: {
+            if (ax.g >= 4 && g.Qin * g.A * (int64_t)ax.P * g.S < (int64_t(1) << 31)) {
+                const int TSL = as_tile_groups(ax.g);
+                const size_t lds = as_lds_bytes(sizeof(T) == 8, ax.g, ax.M);
+                auto k = k_AS<T>;
+                hipError_t err = prep_lds(k, lds);
+                if (err != hipSuccess) return err;
+                const int64_t ngroups = g.Qin * g.A * (int64_t)ax.P * g.S;
+                int64_t blocks = (ngroups + TSL - 1) / TSL;
+                if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = g.max_blocks;
+                blocks = std::min<int64_t>(std::max<int64_t>(blocks, 1), 1 << 22);
+                hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kThreads), lds, st, (const C<T>*)in, (C<T>*)out,
+                                   ax, g, accumulate, (T*)rho, TSL);
+                return hipGetLastError();
+            }
             const dim3 grid = plane_grid((int64_t)ax.M * g.S, g.Qin * g.A);
             hipLaunchKernelGGL(k_A<T>, grid, dim3(kThreads), 0, st, (const C<T>*)in, (C<T>*)out, ax, g,
                                accumulate, (T*)rho);
@@ -589,6 +679,13 @@ hipError_t launch_T(Kind kind, const void* in, void* out, const AxisDev& ax, con
 }
 
 }  // namespace
+
+int as_tile_groups(int g) { return std::max(1, 512 / std::max(1, g)); }
+
+size_t as_lds_bytes(bool dbl, int g, int M) {
+    const size_t c = dbl ? 16 : 8;
+    return (2 * (size_t)as_tile_groups(g) * g + (size_t)M) * c;
+}
 
 size_t pass_lds_bytes(Kind kind, bool dbl, int TS, int M) {
     const size_t c = dbl ? 16 : 8;

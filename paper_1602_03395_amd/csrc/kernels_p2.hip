@@ -22,11 +22,15 @@ namespace {
 
 constexpr int kTilePoints2 = 2048;  // points per tile of the specialised kernels
 
-// LDS tiles are padded by one element per 256-byte bank row (32 complex64 / 16 complex128),
-// which turns the strided Stockham stores into (nearly) conflict-free ones.
-template <typename T> struct PadP { static constexpr int sh = sizeof(T) == 8 ? 4 : 5; };
-template <typename T> __device__ __forceinline__ int px(int i) { return i + (i >> PadP<T>::sh); }
-__host__ __device__ constexpr int padded_tile(bool dbl) { return kTilePoints2 + (kTilePoints2 >> (dbl ? 4 : 5)) + 2; }
+// FP32 tiles are padded by one element per 256-byte bank row (32 complex64), which turns the
+// strided Stockham stores into (nearly) conflict-free ones. FP64 tiles are not padded: there
+// the extra address arithmetic and registers cost more than the conflicts (measured).
+template <typename T> struct PadP { static constexpr bool on = sizeof(T) == 4; };
+template <typename T> __device__ __forceinline__ int px(int i) {
+    if constexpr (PadP<T>::on) return i + (i >> 5);
+    else return i;
+}
+__host__ __device__ constexpr int padded_tile(bool dbl) { return dbl ? kTilePoints2 : kTilePoints2 + (kTilePoints2 >> 5) + 2; }
 
 // Stage structure of a length-2^LM transform: the short radix (2 or 4) first, then radix 8.
 template <int LM> struct Plan2 {
