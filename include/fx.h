@@ -117,6 +117,25 @@ fx_status fx_problem_init(fx_problem* p);
  */
 fx_status fx_plan_create(const fx_problem* prob, fx_plan** out);
 
+/*
+ * Other spectra (section 7.4, generalisations): as fx_plan_create, but the free
+ * evolution factor exp(-i hbar t k^2 / 2m) of eq. (free0) is replaced on every
+ * axis j with phase[j] != NULL by exp(-i phase[j][i]), for a dispersion that is
+ * a sum over axes, omega_k = sum_j omega_j(k_j). Only the chirp (presB) and the
+ * final twiddle (presf) change; the vacuum assumption (eq. (vacuum)) still holds.
+ *
+ * phase[j] (host, read during the call only, not retained) holds lambda[j] *
+ * shape[j] doubles: phase[j][i] = t * omega_j(kappa) in radians at the fine wave
+ * number kappa = 2 pi l / (lambda[j] shape[j] dx[j]), l = i - floor(lambda[j]
+ * shape[j] / 2) (ascending, the Nyquist value, for an even count, first).
+ * phase has ndim entries; an entry NULL keeps the free-particle phase of
+ * m_over_hbar and t_flight on that axis. The phases are reduced modulo 2 pi in
+ * FP64, so their absolute accuracy is that of the caller's doubles.
+ * Errors: as fx_plan_create; FX_EINVAL also for phase == NULL or a non-finite
+ * table value.
+ */
+fx_status fx_plan_create_spectrum(const fx_problem* prob, const double* const* phase, fx_plan** out);
+
 /* Releases the plan, its tables and any workspace it allocated itself. NULL is a no-op. */
 fx_status fx_plan_destroy(fx_plan* plan);
 

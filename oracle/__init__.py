@@ -26,6 +26,10 @@ from .propagator import (  # noqa: F401
     direct_nd,
     expand,
     expand_adjoint,
+    expand_dispersion,
+    expand_dispersion_adjoint,
+    fine_wavenumbers,
+    gtable_phase,
     expand_points,
     gtable,
     gtable_longdouble,

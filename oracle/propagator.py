@@ -261,3 +261,88 @@ def direct_nd(psi: np.ndarray, dx, m_over_hbar: float, t: float, lam, a=None, ab
             im += np.longdouble(v.real) * s_ + np.longdouble(v.imag) * c
         out[nbar] = complex(re / Ntot, im / Ntot)
     return out
+
+
+# ----------------------------------------------------------------------------------------
+# Other spectra (section 7.4, generalisations): exp(-i t omega_k) in place of the
+# free-particle phase, for a dispersion that is a sum over axes, omega_k = sum_j omega_j(k_j).
+# ----------------------------------------------------------------------------------------
+
+def fine_wavenumbers(M: int, lam: int, dx: float) -> np.ndarray:
+    """kappa_l = 2 pi l / (lam M dx) for the lam M fine wave numbers l, ascending from -floor(lam M / 2)."""
+    N = int(lam) * int(M)
+    l = np.arange(-(N // 2), -(N // 2) + N, dtype=np.float64)
+    return 2.0 * np.pi * l / (N * float(dx))
+
+
+def gtable_phase(M: int, lam: int, delta: float, phase: np.ndarray, s_min: int, count: int) -> np.ndarray:
+    """G(s) = 1/(lam M) sum_l exp(2 pi i l (s + delta) / (lam M) - i phase_l), s = s_min + i.
+
+    ``phase[i]`` is t * omega(kappa_l) in radians for l = i - floor(lam M / 2).
+    The integer part of l (s + delta) is reduced exactly modulo lam M in int64,
+    the rest of the phase is accumulated in long double.
+    """
+    N = int(lam) * int(M)
+    phase = np.asarray(phase, dtype=np.float64)
+    if phase.shape != (N,):
+        raise ValueError(f"phase must hold lam*M = {N} values")
+    l = np.arange(-(N // 2), -(N // 2) + N, dtype=np.int64)
+    pi = np.arccos(np.longdouble(-1))
+    di = int(np.rint(delta))
+    df = np.longdouble(delta) - np.longdouble(di)
+    rest = l.astype(np.longdouble) * df / np.longdouble(N) - phase.astype(np.longdouble) / (2 * pi)
+    out = np.empty(count, dtype=np.complex128)
+    for i in range(count):
+        s = s_min + i + di
+        k = np.mod(np.mod(l, N) * (s % N), N)
+        ph = k.astype(np.longdouble) / np.longdouble(N) + rest
+        ph = ph - np.rint(ph)
+        ang = 2 * pi * ph
+        out[i] = complex(np.cos(ang).sum() / N, np.sin(ang).sum() / N)
+    return out
+
+
+def axis_matrix_phase(M: int, lam: int, dx: float, a: float, abar: float, phase: np.ndarray) -> np.ndarray:
+    """Dense M x M matrix G[nbar, n] = G(lam*nbar - n) of one axis for a tabulated spectrum."""
+    delta = (abar - a) / dx
+    s_min = -(M - 1)
+    count = (lam + 1) * (M - 1) + 1
+    tab = gtable_phase(M, lam, delta, phase, s_min, count)
+    nbar = np.arange(M)[:, None]
+    n = np.arange(M)[None, :]
+    return tab[lam * nbar - n - s_min]
+
+
+def _matrices_phase(shape, dx, lam, t, m_over_hbar, a, abar, phases):
+    a, abar = default_offsets(shape, dx, lam, a, abar)
+    mats = []
+    for j in range(len(shape)):
+        if phases is None or phases[j] is None:
+            mats.append(axis_matrix(shape[j], lam[j], dx[j], a[j], abar[j], t, m_over_hbar))
+        else:
+            mats.append(axis_matrix_phase(shape[j], lam[j], dx[j], a[j], abar[j], phases[j]))
+    return mats
+
+
+def expand_dispersion(psi: np.ndarray, dx, lam, phases, m_over_hbar: float = 1.0, t: float = 0.0,
+                      a=None, abar=None) -> np.ndarray:
+    """Expansion with the spectrum t*omega_j tabulated per axis (``phases[j]``, see ``gtable_phase``).
+
+    An axis whose entry is None keeps the free-particle phase hbar t k^2 / 2m.
+    """
+    psi = np.asarray(psi).astype(np.complex128)
+    d = psi.ndim
+    dx = tuple(float(v) for v in np.broadcast_to(dx, (d,)))
+    lam = tuple(int(v) for v in np.broadcast_to(lam, (d,)))
+    return _apply(_matrices_phase(psi.shape, dx, lam, t, m_over_hbar, a, abar, phases), psi)
+
+
+def expand_dispersion_adjoint(y: np.ndarray, dx, lam, phases, m_over_hbar: float = 1.0, t: float = 0.0,
+                              a=None, abar=None) -> np.ndarray:
+    """Hermitian adjoint of ``expand_dispersion``."""
+    y = np.asarray(y).astype(np.complex128)
+    d = y.ndim
+    dx = tuple(float(v) for v in np.broadcast_to(dx, (d,)))
+    lam = tuple(int(v) for v in np.broadcast_to(lam, (d,)))
+    mats = [G.conj().T for G in _matrices_phase(y.shape, dx, lam, t, m_over_hbar, a, abar, phases)]
+    return _apply(mats, y)

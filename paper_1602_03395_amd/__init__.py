@@ -16,7 +16,9 @@ from .api import (  # noqa: F401
     expand_adjoint,
     expand_batch,
     expand_density,
+    fine_wavenumbers,
     get_plan,
 )
 
-__all__ = ["Plan", "Batch", "expand_batch", "expand", "expand_adjoint", "expand_density", "ExpandDensity", "column_density", "get_plan"]
+__all__ = ["Plan", "Batch", "expand_batch", "expand", "expand_adjoint", "expand_density", "ExpandDensity", "column_density", "get_plan",
+           "fine_wavenumbers"]

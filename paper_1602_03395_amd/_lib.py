@@ -70,6 +70,7 @@ def _load():
     sigs = {
         "fx_problem_init": (ctypes.c_int, [P(fx_problem)]),
         "fx_plan_create": (ctypes.c_int, [P(fx_problem), P(vp)]),
+        "fx_plan_create_spectrum": (ctypes.c_int, [P(fx_problem), P(P(ctypes.c_double)), P(vp)]),
         "fx_plan_destroy": (ctypes.c_int, [vp]),
         "fx_plan_num_terms": (ctypes.c_int, [vp, P(ctypes.c_int64)]),
         "fx_plan_workspace_size": (ctypes.c_int, [vp, P(ctypes.c_size_t)]),

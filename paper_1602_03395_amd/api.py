@@ -14,6 +14,7 @@ import ctypes
 import threading
 from typing import Optional, Sequence, Tuple
 
+import numpy as np
 import torch
 
 from . import _lib as L
@@ -54,14 +55,35 @@ class Plan:
     """Owns one ``fx_plan`` (tables on the device, tiling, schedule)."""
 
     def __init__(self, shape, dx, m_over_hbar, t, lam, a=None, abar=None, dtype=torch.complex128,
-                 schedule: str = "paper"):
+                 schedule: str = "paper", spectrum=None):
+        """``spectrum``: optional per-axis list of t * omega_j in radians on the fine wave
+        numbers (``fine_wavenumbers``), None entries keeping the free-particle phase."""
         self.shape = tuple(int(s) for s in shape)
         self.dtype = dtype
         sched = {"paper": L.FX_SCHED_PAPER, "axis_factorised": L.FX_SCHED_AXIS_FACTORISED}[schedule]
         prob = L.make_problem(self.shape, dx, lam, m_over_hbar, t, a, abar, precision_of(dtype), sched)
         self.problem = prob
         h = ctypes.c_void_p()
-        L.check(L.lib.fx_plan_create(ctypes.byref(prob), ctypes.byref(h)), "fx_plan_create")
+        if spectrum is None:
+            L.check(L.lib.fx_plan_create(ctypes.byref(prob), ctypes.byref(h)), "fx_plan_create")
+        else:
+            d = len(self.shape)
+            if len(spectrum) != d:
+                raise ValueError(f"spectrum needs one entry per axis ({d})")
+            DP = ctypes.POINTER(ctypes.c_double)
+            keep = []
+            arr = (DP * 3)()
+            for j, ph in enumerate(spectrum):
+                if ph is None:
+                    continue
+                ph = np.ascontiguousarray(np.asarray(ph, dtype=np.float64))
+                n = int(prob.lambda_[j]) * self.shape[j]
+                if ph.shape != (n,):
+                    raise ValueError(f"spectrum[{j}] must hold lam*M = {n} values")
+                keep.append(ph)
+                arr[j] = ph.ctypes.data_as(DP)
+            L.check(L.lib.fx_plan_create_spectrum(ctypes.byref(prob), arr, ctypes.byref(h)),
+                    "fx_plan_create_spectrum")
         self._h = h
         self._ws = None
 
@@ -198,18 +220,34 @@ def get_plan(shape, dx, m_over_hbar, t, lam, a=None, abar=None, dtype=torch.comp
     return plan
 
 
+def fine_wavenumbers(M: int, lam: int, dx: float) -> np.ndarray:
+    """The lam*M fine wave numbers 2 pi l / (lam M dx), ascending from l = -floor(lam M / 2):
+    the points at which a ``spectrum`` table samples t * omega."""
+    N = int(lam) * int(M)
+    return 2.0 * np.pi * np.arange(-(N // 2), -(N // 2) + N, dtype=np.float64) / (N * float(dx))
+
+
+def _plan_for(x, dx, m_over_hbar, t, lam, a, abar, schedule, spectrum):
+    if spectrum is None:
+        return get_plan(x.shape, dx, m_over_hbar, t, lam, a, abar, x.dtype, schedule)
+    return Plan(x.shape, dx, m_over_hbar, t, lam, a, abar, x.dtype, schedule, spectrum=spectrum)
+
+
 def expand(psi0: torch.Tensor, dx, m_over_hbar: float, t: float, lam, a=None, abar=None,
-           want_psi: bool = True, schedule: str = "paper") -> Tuple[Optional[torch.Tensor], torch.Tensor]:
-    """Free flight of ``psi0`` for time t onto the lattice magnified by ``lam``: returns (psi, rho)."""
+           want_psi: bool = True, schedule: str = "paper",
+           spectrum=None) -> Tuple[Optional[torch.Tensor], torch.Tensor]:
+    """Free flight of ``psi0`` for time t onto the lattice magnified by ``lam``: returns (psi, rho).
+
+    ``spectrum`` (optional) replaces the free-particle phase per axis, see ``Plan``."""
     _check_field(psi0, "psi0")
-    plan = get_plan(psi0.shape, dx, m_over_hbar, t, lam, a, abar, psi0.dtype, schedule)
+    plan = _plan_for(psi0, dx, m_over_hbar, t, lam, a, abar, schedule, spectrum)
     return plan.expand(psi0, want_psi=want_psi, want_rho=True)
 
 
 def expand_adjoint(grad_out: torch.Tensor, dx, m_over_hbar: float, t: float, lam, a=None, abar=None,
-                   schedule: str = "paper") -> torch.Tensor:
+                   schedule: str = "paper", spectrum=None) -> torch.Tensor:
     _check_field(grad_out, "grad_psi_out")
-    plan = get_plan(grad_out.shape, dx, m_over_hbar, t, lam, a, abar, grad_out.dtype, schedule)
+    plan = _plan_for(grad_out, dx, m_over_hbar, t, lam, a, abar, schedule, spectrum)
     return plan.expand_adjoint(grad_out)
 
 

@@ -404,7 +404,9 @@ fx_status fx_problem_init(fx_problem* p) {
     return FX_OK;
 }
 
-fx_status fx_plan_create(const fx_problem* prob, fx_plan** out) {
+namespace fx {
+
+fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_plan** out) {
     if (!out) { set_error("out is NULL"); return FX_EINVAL; }
     fx_status s = validate(prob);
     if (s != FX_OK) return s;
@@ -435,6 +437,10 @@ fx_status fx_plan_create(const fx_problem* prob, fx_plan** out) {
         }
         ap.t = prob->t_flight;
         ap.m_over_hbar = prob->m_over_hbar;
+        if (phase && pa >= off) {
+            ap.phase = phase[pa - off];
+            p->spectrum[pa] = (ap.phase != nullptr);
+        }
         p->par[pa] = ap;
         p->len[pa] = ap.M;
         AxisDev& ad = p->ax[pa];
@@ -449,6 +455,7 @@ fx_status fx_plan_create(const fx_problem* prob, fx_plan** out) {
         ad.fp = make_radix_plan(ad.P);
         ad.fg = make_radix_plan(ad.g);
         tabs[pa] = build_axis_tables(ap);
+        p->par[pa].phase = nullptr;  // the caller's table is not kept
         if (!(ap.M == 1 && ap.lam == 1)) p->act[p->nact++] = pa;
     }
     p->M = p->len[0] * p->len[1] * p->len[2];
@@ -513,6 +520,29 @@ fx_status fx_plan_create(const fx_problem* prob, fx_plan** out) {
     plan_setup_workspace(p, 1);
     *out = p;
     return FX_OK;
+}
+
+}  // namespace fx
+
+fx_status fx_plan_create(const fx_problem* prob, fx_plan** out) { return create_plan(prob, nullptr, out); }
+
+fx_status fx_plan_create_spectrum(const fx_problem* prob, const double* const* phase, fx_plan** out) {
+    if (!phase) { set_error("phase is NULL"); return FX_EINVAL; }
+    fx_status s = validate(prob);
+    if (s != FX_OK) return s;
+    {
+        for (int j = 0; j < prob->ndim; ++j) {
+            if (!phase[j]) continue;
+            const int64_t n = (int64_t)prob->lambda[j] * prob->shape[j];
+            for (int64_t i = 0; i < n; ++i) {
+                if (!std::isfinite(phase[j][i])) {
+                    set_error("phase table holds a non-finite value");
+                    return FX_EINVAL;
+                }
+            }
+        }
+    }
+    return create_plan(prob, phase, out);
 }
 
 fx_status fx_plan_destroy(fx_plan* p) {
@@ -734,7 +764,12 @@ fx_status fx_plan_describe(const fx_plan* p, char* buf, size_t len) {
     s += "\",\"precision\":\"";
     s += p->dbl ? "c128" : "c64_phase64";
     s += "\",\"terms\":" + std::to_string(p->Q) + ",\"outer_block\":" + std::to_string(p->nb_outer) +
-         ",\"workspace_bytes\":" + std::to_string(p->ws_need) + ",\"passes\":[";
+         ",\"workspace_bytes\":" + std::to_string(p->ws_need) + ",\"spectrum\":[";
+    for (int j = 0; j < p->ndim; ++j) {
+        s += j ? "," : "";
+        s += p->spectrum[3 - p->ndim + j] ? "\"table\"" : "\"free\"";
+    }
+    s += "],\"passes\":[";
     static const char* names[] = {"E", "A", "EA", "EH", "AH", "EAH"};
     for (size_t i = 0; i < ops.size(); ++i) {
         const Op& o = ops[i];

@@ -107,6 +107,9 @@ struct AxisParams {
     int lam = 1;
     double dx = 1, a = 0, abar = 0;
     double t = 0, m_over_hbar = 1;
+    // Optional spectrum: phase[i] = t * omega(kappa_l) in radians for the fine wave
+    // number l = i - floor(lam M / 2); NULL keeps hbar t kappa^2 / 2m.
+    const double* phase = nullptr;
 };
 AxisTables build_axis_tables(const AxisParams& p);
 

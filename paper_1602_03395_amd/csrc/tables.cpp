@@ -18,6 +18,10 @@
 //   Tf[q][nb]  : alpha_q (xbar - a) - alpha_q^2 ht/2m    = q (delta + lam nb) / (lam M) - beta q^2
 // For odd M the largest positive coarse wave number is folded to the negative
 // side when q >= lam/2 (the umklapp rule stated after (FF)).
+//
+// Other spectra (section 7.4): with exp(-i t omega_k) in place of the free-particle
+// factor, the quadratic parts become -(phi(ell) - phi(q)) in TB and -phi(q) in Tf,
+// phi = t omega / (2 pi) in cycles, read from a caller table over the fine wave numbers.
 #include <cmath>
 #include <cstdint>
 
@@ -79,7 +83,10 @@ AxisTables build_axis_tables(const AxisParams& p) {
     const int64_t di = (int64_t)di_d;
     const double df = delta - di_d;
 
+    const double inv2pi = 1.0 / kTwoPi;
+    const int64_t l0 = N / 2;  // table index of the fine wave number 0
     for (int64_t q = 0; q < lam; ++q) {
+        const double phq = p.phase ? p.phase[l0 + q] * inv2pi : 0.0;
         for (int64_t n = 0; n < M; ++n) {
             const size_t i = (size_t)(q * M + n);
             // TA: -(q n)/(lam M)
@@ -89,12 +96,13 @@ AxisTables build_axis_tables(const AxisParams& p) {
             if ((M % 2 == 1) && (2 * n == M - 1) && (2 * q >= lam)) lt -= M;
             const int64_t ell = lam * lt + q;
             const int64_t I = ell * ell - q * q;
-            const double tb = rational_cycles(lt * di, M) + (double)lt * df / (double)M
-                              - beta_cycles(beta, I);
+            const double chirp = p.phase ? reduce_cycles(p.phase[l0 + ell] * inv2pi - phq)
+                                         : beta_cycles(beta, I);
+            const double tb = rational_cycles(lt * di, M) + (double)lt * df / (double)M - chirp;
             put(t.TB, i, tb, 1.0);
             // Tf: q (delta + lam nb)/(lam M) - beta q^2, amplitude 1/lam.
             const double tf = rational_cycles(q * (di + lam * n), N) + (double)q * df / (double)N
-                              - beta_cycles(beta, q * q);
+                              - (p.phase ? reduce_cycles(phq) : beta_cycles(beta, q * q));
             put(t.Tf, i, tf, 1.0 / (double)lam);
         }
     }

@@ -109,3 +109,34 @@ def test_python_wrappers_reject_host_tensors():
         fx.expand(torch.zeros(8, dtype=torch.complex128), 1.0, 1.0, 1.0, 2)
     with pytest.raises(ValueError):
         fx.expand(torch.zeros(8, dtype=torch.float64), 1.0, 1.0, 1.0, 2)
+
+
+def test_spectrum_plan_rejects_bad_tables_on_host():
+    L = _lib()
+    import numpy as np
+    DP = ctypes.POINTER(ctypes.c_double)
+    p = L.make_problem((16,), 1.0, 3, 1.0, 2.0)
+    h = ctypes.c_void_p()
+    assert L.lib.fx_plan_create_spectrum(ctypes.byref(p), None, ctypes.byref(h)) == L.FX_EINVAL
+    bad = np.zeros(48)
+    bad[17] = math.nan
+    arr = (DP * 3)()
+    arr[0] = bad.ctypes.data_as(DP)
+    st = L.lib.fx_plan_create_spectrum(ctypes.byref(p), arr, ctypes.byref(h))
+    assert st == L.FX_EINVAL and b"non-finite" in L.lib.fx_last_error()
+    # an invalid problem is rejected before the table is read
+    p.lambda_[0] = 0
+    assert L.lib.fx_plan_create_spectrum(ctypes.byref(p), arr, ctypes.byref(h)) == L.FX_EINVAL
+    assert not h.value
+
+
+def test_spectrum_wrapper_checks_table_length():
+    torch = pytest.importorskip("torch")
+    import numpy as np
+    import paper_1602_03395_amd as fx
+    with pytest.raises(ValueError):
+        fx.Plan((16,), 1.0, 1.0, 2.0, 3, spectrum=[np.zeros(47)])
+    with pytest.raises(ValueError):
+        fx.Plan((16, 4), 1.0, 1.0, 2.0, 3, spectrum=[np.zeros(48)])
+    k = fx.fine_wavenumbers(16, 3, 0.5)
+    assert k.shape == (48,) and k[0] < 0 and abs(k[24]) == 0.0
