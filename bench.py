@@ -17,7 +17,6 @@ baseline.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -58,13 +57,13 @@ def pass_cost(p: dict, csize: int, outer_chunks: int = 1):
 
 
 def kernels_hash() -> str:
-    h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1602_03395_amd", "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
-    return h.hexdigest()[:16]
+    from paper_1602_03395_amd.profiling import kernels_hash as kh
+    return kh()
 
 
-def load_traffic(kernel_key: str):
+def load_traffic(tag: str, kernel_key: str):
+    """HBM bytes per launch of one pass from the committed counter summary, or None when it
+    was taken on other kernel sources or another workload."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(path):
         return None
@@ -74,7 +73,7 @@ def load_traffic(kernel_key: str):
         return None
     if d.get("kernels_hash") != kernels_hash():
         return None
-    ent = d.get("passes", {}).get(kernel_key)
+    ent = d.get("workloads", {}).get(tag, {}).get("passes", {}).get(kernel_key)
     if not ent:
         return None
     return ent.get("hbm_bytes_per_launch")
@@ -285,7 +284,7 @@ def main():
             roofline = {"bound": "hbm", "achieved": dom["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                         "frac": dom["gbs"] / PEAK_HBM_GBS}
         roofline["kernel"] = dom["pass"]
-        roofline["traffic"] = load_traffic(dom["key"])
+        roofline["traffic"] = load_traffic(f"{wl.name}/{dtype_name}/{args.schedule}", dom["key"])
 
     result = {
         "metric": "expanded lattice pts/s + HBM roofline %, FP32/FP64-phase vs FP64 at 1e-5 err",

@@ -195,6 +195,30 @@ fx_status fx_column_density(fx_plan* plan, const void* rho, int axis, void* imag
 fx_status fx_expand_adjoint(fx_plan* plan, const void* grad_psi_out, void* grad_psi0, void* stream);
 
 /*
+ * Positive-P pairs (section 7.4, generalisations): the two independent fields
+ * psi and psi^+ that stand for the annihilation and creation operators are
+ * expanded together, as two slices of one run of the plan's passes. psi follows
+ * the free evolution of the plan (Psibar = U psi), psi^+ the complex-conjugate
+ * one (Psibar^+ = conj(U conj(psi^+)), i.e. the elementwise conjugate kernel),
+ * and n = Psibar^+ * Psibar is the density estimator on the magnified grid
+ * (complex; its real part estimates the mean density).
+ *
+ * psi, psi_plus: device, the plan's shape and complex type, read only.
+ * psi_out, psi_plus_out, n_out: device, same shape and type; any may be NULL
+ * but not all three. Needs fx_plan_pair_workspace_size() bytes of workspace
+ * (allocated by the plan on first use unless the caller set a workspace, which
+ * must then be at least that large: FX_ENOMEM otherwise). Works with either
+ * schedule and with plans from fx_plan_create_spectrum (psi^+ then takes the
+ * conjugate of that kernel too). Asynchronous on `stream`.
+ * Errors: FX_EINVAL (NULL plan or input, all outputs NULL), FX_ENOMEM, FX_EDEVICE.
+ */
+fx_status fx_expand_pair(fx_plan* plan, const void* psi, const void* psi_plus, void* psi_out,
+                         void* psi_plus_out, void* n_out, void* stream);
+
+/* Device bytes of workspace fx_expand_pair needs (two slices plus input staging). */
+fx_status fx_plan_pair_workspace_size(const fx_plan* plan, size_t* bytes);
+
+/*
  * Ragged batch of problems (ensembles of realizations, section 1): problems
  * with equal shape, spacing, offsets, magnification, flight and precision
  * share one plan and run as one batched pass sequence; different shape

@@ -27,6 +27,7 @@ from .propagator import (  # noqa: F401
     expand,
     expand_adjoint,
     expand_dispersion,
+    expand_pair,
     expand_dispersion_adjoint,
     fine_wavenumbers,
     gtable_phase,

@@ -346,3 +346,29 @@ def expand_dispersion_adjoint(y: np.ndarray, dx, lam, phases, m_over_hbar: float
     lam = tuple(int(v) for v in np.broadcast_to(lam, (d,)))
     mats = [G.conj().T for G in _matrices_phase(y.shape, dx, lam, t, m_over_hbar, a, abar, phases)]
     return _apply(mats, y)
+
+
+# ----------------------------------------------------------------------------------------
+# Two fields (section 7.4, generalisations): positive-P pairs psi, psi^+.
+# ----------------------------------------------------------------------------------------
+
+def expand_pair(psi: np.ndarray, psi_plus: np.ndarray, dx, m_over_hbar: float, t: float, lam,
+                a=None, abar=None):
+    """Free flight of a positive-P pair onto the magnified grid.
+
+    psi follows the free Schroedinger equation (kernel G), psi^+ the conjugate one
+    (kernel conj(G), elementwise), as the fields standing for the annihilation and
+    creation operators do. Returns (psibar, psibar_plus, n) with the density
+    estimator n = psibar_plus * psibar (complex).
+    """
+    psi = np.asarray(psi).astype(np.complex128)
+    psi_plus = np.asarray(psi_plus).astype(np.complex128)
+    if psi.shape != psi_plus.shape:
+        raise ValueError("psi and psi_plus must have the same shape")
+    d = psi.ndim
+    dx = tuple(float(v) for v in np.broadcast_to(dx, (d,)))
+    lam = tuple(int(v) for v in np.broadcast_to(lam, (d,)))
+    mats = _matrices(psi.shape, dx, lam, t, m_over_hbar, a, abar)
+    pb = _apply(mats, psi)
+    pbp = _apply([G.conj() for G in mats], psi_plus)
+    return pb, pbp, pbp * pb

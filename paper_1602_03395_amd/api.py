@@ -187,6 +187,24 @@ class Plan:
                 "fx_expand_adjoint")
         return grad_in
 
+    def pair_workspace_size(self) -> int:
+        b = ctypes.c_size_t()
+        L.check(L.lib.fx_plan_pair_workspace_size(self._h, ctypes.byref(b)), "fx_plan_pair_workspace_size")
+        return b.value
+
+    def expand_pair(self, psi: torch.Tensor, psi_plus: torch.Tensor):
+        """Positive-P pair: returns (Psibar, Psibar^+, n = Psibar^+ * Psibar), see ``fx_expand_pair``."""
+        _check_field(psi, "psi")
+        _check_field(psi_plus, "psi_plus")
+        self._check_shape(psi)
+        self._check_shape(psi_plus)
+        out = torch.empty_like(psi)
+        out_plus = torch.empty_like(psi)
+        n = torch.empty_like(psi)
+        L.check(L.lib.fx_expand_pair(self._h, _ptr(psi), _ptr(psi_plus), _ptr(out), _ptr(out_plus), _ptr(n),
+                                     _stream_ptr()), "fx_expand_pair")
+        return out, out_plus, n
+
     def _check_shape(self, x: torch.Tensor):
         if tuple(x.shape) != self.shape:
             raise ValueError(f"tensor shape {tuple(x.shape)} does not match the plan's {self.shape}")

@@ -262,8 +262,7 @@ void to_prec(const std::vector<double>& src, std::vector<unsigned char>& dst, si
     for (size_t i = 0; i < src.size(); ++i) d[i] = (T)src[i];
 }
 
-fx_status plan_setup_workspace(fx_plan* p, int64_t slices) {
-    p->slices = slices;
+void workspace_layout(const fx_plan* p, int64_t slices, int64_t* nb_out, int64_t* buf_out, size_t* need_out) {
     const int k = p->nact;
     int qb[3] = {0, 0, 0}, qn[3];
     for (int i = 0; i < 3; ++i) qn[i] = p->ax[i].lam;
@@ -282,16 +281,22 @@ fx_status plan_setup_workspace(fx_plan* p, int64_t slices) {
         else
             while (nb > 1 && (size_t)need(nb) * 2 * cs > p->budget) nb = (nb + 1) / 2;
     }
-    p->nb_outer = std::max<int64_t>(1, nb);
-    p->buf_elems = need(p->nb_outer);
-    p->ws_need = (size_t)(2 * p->buf_elems + slices * p->M) * cs + 1024;
+    *nb_out = std::max<int64_t>(1, nb);
+    *buf_out = need(*nb_out);
+    *need_out = (size_t)(2 * *buf_out + slices * p->M) * cs + 1024;
+}
+
+fx_status plan_setup_workspace(fx_plan* p, int64_t slices) {
+    p->slices = slices;
+    workspace_layout(p, slices, &p->nb_outer, &p->buf_elems, &p->ws_need);
     return FX_OK;
 }
 
 fx_status ensure_workspace(fx_plan* p) {
     if (p->ws && p->ws_bytes >= p->ws_need) return FX_OK;
     if (p->ws && !p->ws_owned) {
-        set_error("caller workspace smaller than fx_plan_workspace_size()");
+        set_error("caller workspace smaller than this call needs (fx_plan_workspace_size, "
+                  "fx_plan_pair_workspace_size for pairs)");
         return FX_ENOMEM;
     }
     if (p->ws_owned && p->ws) {
@@ -567,7 +572,8 @@ fx_status fx_plan_num_terms(const fx_plan* p, int64_t* q) {
 
 fx_status fx_plan_workspace_size(const fx_plan* p, size_t* bytes) {
     if (!p || !bytes) { set_error("NULL argument"); return FX_EINVAL; }
-    *bytes = p->ws_need;
+    int64_t nb = 0, buf = 0;
+    workspace_layout(p, 1, &nb, &buf, bytes);
     return FX_OK;
 }
 
@@ -579,7 +585,9 @@ fx_status fx_plan_set_workspace(fx_plan* p, void* dev_ptr, size_t bytes) {
     }
     if (!dev_ptr) { set_error("workspace pointer is NULL"); return FX_EINVAL; }
     if (((uintptr_t)dev_ptr) % 256 != 0) { set_error("workspace must be 256-byte aligned"); return FX_EINVAL; }
-    if (bytes < p->ws_need) { set_error("workspace smaller than fx_plan_workspace_size()"); return FX_ENOMEM; }
+    size_t need = 0;
+    (void)fx_plan_workspace_size(p, &need);
+    if (bytes < need) { set_error("workspace smaller than fx_plan_workspace_size()"); return FX_ENOMEM; }
     if (p->ws_owned && p->ws) (void)hipFree(p->ws);
     p->ws = dev_ptr;
     p->ws_bytes = bytes;

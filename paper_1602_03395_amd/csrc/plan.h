@@ -73,6 +73,8 @@ size_t csize(const fx_plan* p);
 std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], int64_t slices0, bool adjoint);
 int64_t max_intermediate(const std::vector<Op>& ops);
 fx_status validate(const fx_problem* pr);
+// Outer block, ping-pong buffer elements and workspace bytes for `slices` leading slices.
+void workspace_layout(const fx_plan* p, int64_t slices, int64_t* nb, int64_t* buf, size_t* need);
 fx_status plan_setup_workspace(fx_plan* p, int64_t slices);
 fx_status ensure_workspace(fx_plan* p);
 fx_status run_ops(fx_plan* p, const std::vector<Op>& ops, const void* src, void* dst, int accumulate, void* rho,

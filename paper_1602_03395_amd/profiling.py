@@ -4,11 +4,12 @@
         markdown table of per-kernel call counts and durations
     python -m paper_1602_03395_amd.profiling counters <counter_collection.csv> <COUNTER>
         average counter value per dispatch for every kernel name
-    python -m paper_1602_03395_amd.profiling traffic <fetch.csv> <write.csv> <copy_MiB> <calls> <out.json>
+    python -m paper_1602_03395_amd.profiling traffic <fetch.csv> <write.csv> <copy_MiB> <calls> <out.json> <tag>
         HBM bytes per dispatch of every pass of the schedule (key 'kind#ordinal', ordinal counted
         within one expansion call; <calls> = expansion calls in the profiled run) from FETCH_SIZE
         and WRITE_SIZE (KiB per dispatch), each scaled by the factor that makes the plain copy
-        kernel of known size read (and write) exactly its size; stamped with the kernels' hash
+        kernel of known size read (and write) exactly its size; stored under <tag>
+        (workload/dtype/schedule) and stamped with the hash of the kernel sources
 
 Only the csv files rocprofv3 writes are read; nothing here touches the GPU.
 """
@@ -53,14 +54,19 @@ def counters(path: str, counter: str):
     return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
 
 
+KERNEL_SOURCES = ("kernels.hip", "kernels_p2.hip", "kernels_ct.hip", "device_common.h", "fx_internal.h")
+
+
 def kernels_hash() -> str:
     h = hashlib.sha256()
-    with open(os.path.join(HERE, "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
-PASS_KIND = re.compile(r"fx::k_(EAH|EA|EH|AH|E|A)<")
+# pass kernels: k_E, k_E2 (power-of-two), k_Ect (3*2^k), k_EA*, k_A, k_AS (structured), adjoints
+PASS_KIND = re.compile(r"fx::k_(EAH|EA|EH|AH|E|A)(?:2|ct|S)?<")
 
 
 def _pass_dispatches(path: str, counter: str):
@@ -90,7 +96,7 @@ def _per_pass(rows, calls_per_run: int):
     return {k: (sum(v) / len(v), len(v)) for k, v in res.items()}
 
 
-def traffic(fetch_csv: str, write_csv: str, copy_mib: float, calls: int, out_json: str):
+def traffic(fetch_csv: str, write_csv: str, copy_mib: float, calls: int, out_json: str, tag: str):
     f_avg, _ = counters(fetch_csv, "FETCH_SIZE")
     w_avg, _ = counters(write_csv, "WRITE_SIZE")
     copy_kib = copy_mib * 1024.0
@@ -102,7 +108,7 @@ def traffic(fetch_csv: str, write_csv: str, copy_mib: float, calls: int, out_jso
     w_scale = copy_kib / w_avg[ck] if w_avg.get(ck) else 1.0
     fp = _per_pass(_pass_dispatches(fetch_csv, "FETCH_SIZE"), calls)
     wp = _per_pass(_pass_dispatches(write_csv, "WRITE_SIZE"), calls)
-    res = {"kernels_hash": kernels_hash(), "copy_kernel": short_name(ck), "copy_MiB": copy_mib,
+    res = {"copy_kernel": short_name(ck), "copy_MiB": copy_mib,
            "copy_fetch_KiB_counter": f_avg[ck], "copy_write_KiB_counter": w_avg.get(ck),
            "fetch_scale": f_scale, "write_scale": w_scale, "passes": {}}
     for key, (fv, n) in fp.items():
@@ -110,7 +116,16 @@ def traffic(fetch_csv: str, write_csv: str, copy_mib: float, calls: int, out_jso
         wb = wp.get(key, (0.0, 0))[0] * 1024.0 * w_scale
         res["passes"][key] = {"dispatches": n, "fetch_bytes": fb, "write_bytes": wb,
                               "hbm_bytes_per_launch": fb + wb}
-    json.dump(res, open(out_json, "w"), indent=1)
+    doc = {}
+    if os.path.exists(out_json):
+        try:
+            doc = json.load(open(out_json))
+        except ValueError:
+            doc = {}
+    if doc.get("kernels_hash") != kernels_hash():
+        doc = {"kernels_hash": kernels_hash(), "workloads": {}}
+    doc.setdefault("workloads", {})[tag] = res
+    json.dump(doc, open(out_json, "w"), indent=1)
     return res
 
 
@@ -123,7 +138,7 @@ if __name__ == "__main__":
         for k in sorted(avg, key=lambda x: -avg[x]):
             print(f"{short_name(k):40s} dispatches {n[k]:5d}  avg {avg[k]:.4g}")
     elif cmd == "traffic":
-        print(json.dumps(traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), int(sys.argv[5]), sys.argv[6]),
-                         indent=1))
+        print(json.dumps(traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), int(sys.argv[5]), sys.argv[6],
+                                 sys.argv[7]), indent=1))
     else:
         raise SystemExit(__doc__)

@@ -140,3 +140,9 @@ def test_spectrum_wrapper_checks_table_length():
         fx.Plan((16, 4), 1.0, 1.0, 2.0, 3, spectrum=[np.zeros(48)])
     k = fx.fine_wavenumbers(16, 3, 0.5)
     assert k.shape == (48,) and k[0] < 0 and abs(k[24]) == 0.0
+
+
+def test_pair_entry_rejects_null_arguments():
+    L = _lib()
+    assert L.lib.fx_expand_pair(None, None, None, None, None, None, None) == L.FX_EINVAL
+    assert L.lib.fx_plan_pair_workspace_size(None, None) == L.FX_EINVAL
