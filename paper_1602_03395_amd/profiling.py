@@ -29,7 +29,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def short_name(name: str) -> str:
     """fx::k_EA<float, 8>(...) -> k_EA<float,8>; other kernels keep a trimmed name."""
-    m = re.search(r"(k_[A-Za-z]+<[^>]*>)", name)
+    m = re.search(r"(k_[A-Za-z0-9]+<[^>]*>)", name)
     if m:
         return m.group(1).replace(" ", "")
     return name.split("(")[0][-80:]
@@ -66,7 +66,7 @@ def kernels_hash() -> str:
 
 
 # pass kernels: k_E, k_E2 (power-of-two), k_Ect (3*2^k), k_EA*, k_A, k_AS (structured), adjoints
-PASS_KIND = re.compile(r"fx::k_(EAH|EA|EH|AH|E|A)(?:2|ct|S)?<")
+PASS_KIND = re.compile(r"\bk_(EAH|EA|EH|AH|E|A)(?:2|ct|S)?<")
 
 
 def _pass_dispatches(path: str, counter: str):
