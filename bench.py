@@ -178,6 +178,9 @@ def main():
                     help="c4 only: expand this single realization through one plan (per-pass timing)")
     ap.add_argument("--dtype", default=None, choices=[None, "c64", "c128"])
     ap.add_argument("--schedule", default="paper", choices=["paper", "axis_factorised"])
+    ap.add_argument("--variant", default="free", choices=["free", "spectrum", "pair"],
+                    help="free: free flight (the paper's case); spectrum: a tabulated non-quadratic "
+                         "axis-additive spectrum of the same size; pair: positive-P pair psi, psi^+")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -225,14 +228,33 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     psi = torch.from_numpy(field).to(dev)
-    plan = fx.Plan(psi.shape, dx, wl.m_over_hbar, t, lam, dtype=dtype, schedule=args.schedule)
-    desc = json.loads(plan.describe())
+    spectrum = None
+    if args.variant == "spectrum":
+        # per-axis Bogoliubov-like spectrum omega = sqrt(eps (eps + 2 mu)), eps = k^2 / 2m
+        mu = 0.1
+        spectrum = []
+        for j in range(len(lam)):
+            k = fx.fine_wavenumbers(psi.shape[j], lam[j], dx[j])
+            eps = k * k / (2.0 * wl.m_over_hbar)
+            spectrum.append(t * np.sqrt(eps * (eps + 2.0 * mu)))
+    plan = fx.Plan(psi.shape, dx, wl.m_over_hbar, t, lam, dtype=dtype, schedule=args.schedule, spectrum=spectrum)
     out = torch.empty_like(psi)
     rho = torch.empty(psi.shape, dtype=torch.float32 if dtype == torch.complex64 else torch.float64, device=dev)
+    if args.variant == "pair":
+        rng = np.random.default_rng(np.random.SeedSequence(11))
+        noise = 0.05 * (rng.standard_normal(field.shape) + 1j * rng.standard_normal(field.shape))
+        psi_plus = torch.from_numpy((field.conj() + noise).astype(field.dtype)).to(dev)
+
+        def step():
+            return plan.expand_pair(psi, psi_plus)
+    else:
+        def step():
+            return plan.expand(psi, psi_out=out, rho_out=rho)
 
     for _ in range(args.warmup):
-        plan.expand(psi, psi_out=out, rho_out=rho)
+        step()
     torch.cuda.synchronize()
+    desc = json.loads(plan.describe())
 
     stream = torch.cuda.current_stream()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -241,7 +263,7 @@ def main():
     w0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
-        plan.expand(psi, psi_out=out, rho_out=rho)
+        step()
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
@@ -256,7 +278,7 @@ def main():
         plan.set_timing(True)
         plan.pass_times()  # clear
         for _ in range(args.steps):
-            plan.expand(psi, psi_out=out, rho_out=rho)
+            step()
         torch.cuda.synchronize()
         passes = plan.pass_times()
         plan.set_timing(False)
@@ -292,7 +314,8 @@ def main():
             roofline = {"bound": "hbm", "achieved": dom["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                         "frac": dom["gbs"] / PEAK_HBM_GBS}
         roofline["kernel"] = dom["pass"]
-        roofline["traffic"] = load_traffic(f"{wl.name}/{dtype_name}/{args.schedule}", dom["key"])
+        tag = f"{wl.name}/{dtype_name}/{args.schedule}" + ("" if args.variant == "free" else f"/{args.variant}")
+        roofline["traffic"] = load_traffic(tag, dom["key"])
 
     result = {
         "metric": "expanded lattice pts/s + HBM roofline %, FP32/FP64-phase vs FP64 at 1e-5 err",
@@ -309,7 +332,7 @@ def main():
         "dtype": "f32" if dtype == torch.complex64 else "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "shape": list(psi.shape), "lam": list(lam), "dx": list(dx), "t": t,
-                   "terms": terms, "schedule": args.schedule,
+                   "terms": terms, "schedule": args.schedule, "variant": args.variant,
                    "precision": "c64_phase64" if dtype == torch.complex64 else "c128",
                    "outer_block": desc["outer_block"]},
         "q_term_pts_per_s": npts * terms / (ms_per_step * 1e-3),
@@ -317,7 +340,7 @@ def main():
         "passes": pass_rows,
     }
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.variant == "free":
         ref, ref_rho, cb = cpu_baseline(wl, field, lam, dx, t)
         result["cpu_baseline"] = cb
         got = rho.cpu().numpy().astype(np.float64)

@@ -108,6 +108,11 @@ namespace fx {
 
 size_t csize(const fx_plan* p) { return p->dbl ? 16 : 8; }
 
+bool use_cfp(const fx_plan* p, Kind kind, const AxisDev& a) {
+    return p->use_cfp && a.HT != nullptr && cfp_applicable(kind, p->dbl, a.M, a.g) &&
+           (int64_t)cfp_lds_bytes(p->dbl, a.M, a.g) <= lds_limit_bytes();
+}
+
 int choose_ts(const fx_plan* p, Kind kind, int M, int64_t A, int64_t S) {
     if (p->use_p2 && p2_applicable(kind, M) && (int64_t)p2_lds_bytes(kind, p->dbl, M) <= lds_limit_bytes())
         return p2_tile_lines(M);
@@ -153,10 +158,20 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
         g.Qin = qin;
         g.qb = qb[ax];
         g.qn = qn[ax];
-        g.TS = choose_ts(p, kind, p->ax[ax].M, g.A, g.S);
+        const bool reg = use_cfp(p, kind, p->ax[ax]);
+        g.TS = reg ? cfp_tile_lines(p->ax[ax].g) : choose_ts(p, kind, p->ax[ax].M, g.A, g.S);
         if (g.S == 1) g.ntiles = (g.A + g.TS - 1) / g.TS;
         else g.ntiles = g.A * ((g.S + g.TS - 1) / g.TS);
         g.max_blocks = p->persist > 0 ? p->persist * num_cus() : 0;
+        g.reg_a = (kind == Kind::A) && p->use_asr && asr_applicable(p->ax[ax].g);
+        if (reg && kind == Kind::EA) {
+            g.qc = g.qn;  // the fused pass sums every magnification index inside the workgroup
+        } else if (reg) {
+            // magnification indices per workgroup: as many as keep >= cfp_blocks workgroups
+            const int64_t base = g.Qin * g.ntiles;
+            const int64_t want = std::max<int64_t>(1, (int64_t)p->cfp_blocks);
+            g.qc = (int)std::max<int64_t>(1, std::min<int64_t>(g.qn, (base * g.qn) / want));
+        }
         return g;
     };
     auto vol = [&]() { return slices * lens[0] * lens[1] * lens[2]; };
@@ -459,6 +474,8 @@ fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_pla
         ad.fm = make_radix_plan(ad.M);
         ad.fp = make_radix_plan(ad.P);
         ad.fg = make_radix_plan(ad.g);
+        ap.want_ht = cfp_applicable(Kind::E, p->dbl, (int)ap.M, ad.g) &&
+                     ap.lam * ap.M * (int64_t)ad.g <= (int64_t(1) << 26);
         tabs[pa] = build_axis_tables(ap);
         p->par[pa].phase = nullptr;  // the caller's table is not kept
         if (!(ap.M == 1 && ap.lam == 1)) p->act[p->nact++] = pa;
@@ -477,19 +494,19 @@ fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_pla
     // Upload all tables in one allocation: per axis TA | TB | Tf | tw.
     const size_t cs = csize(p);
     size_t total = 0;
-    size_t offs[3][4];
+    size_t offs[3][5];
     for (int pa = 0; pa < 3; ++pa) {
         const size_t lm = (size_t)p->ax[pa].lam * p->ax[pa].M;
-        const size_t sz[4] = {lm, lm, lm, (size_t)p->ax[pa].M};
-        for (int t = 0; t < 4; ++t) {
+        const size_t sz[5] = {lm, lm, lm, (size_t)p->ax[pa].M, tabs[pa].HT.size() / 2};
+        for (int t = 0; t < 5; ++t) {
             offs[pa][t] = total;
             total += ((sz[t] * cs + 255) / 256) * 256;
         }
     }
     std::vector<unsigned char> host(total, 0);
     for (int pa = 0; pa < 3; ++pa) {
-        const std::vector<double>* src[4] = {&tabs[pa].TA, &tabs[pa].TB, &tabs[pa].Tf, &tabs[pa].tw};
-        for (int t = 0; t < 4; ++t) {
+        const std::vector<double>* src[5] = {&tabs[pa].TA, &tabs[pa].TB, &tabs[pa].Tf, &tabs[pa].tw, &tabs[pa].HT};
+        for (int t = 0; t < 5; ++t) {
             if (p->dbl) to_prec<double>(*src[t], host, offs[pa][t]);
             else to_prec<float>(*src[t], host, offs[pa][t]);
         }
@@ -513,6 +530,7 @@ fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_pla
         p->ax[pa].TB = b + offs[pa][1];
         p->ax[pa].Tf = b + offs[pa][2];
         p->ax[pa].tw = b + offs[pa][3];
+        p->ax[pa].HT = tabs[pa].HT.empty() ? nullptr : b + offs[pa][4];
     }
     size_t budget = (size_t)8 << 30;
     if (const char* e = std::getenv("FX_WORKSPACE_MB")) budget = (size_t)std::max(1L, std::atol(e)) << 20;
@@ -522,6 +540,10 @@ fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_pla
     if (const char* e = std::getenv("FX_TILE_POINTS")) p->ts_target = std::max(1, std::atoi(e));
     if (const char* e = std::getenv("FX_NO_SPLIT")) p->allow_split = (e[0] != '1');
     if (const char* e = std::getenv("FX_NO_P2")) p->use_p2 = (e[0] != '1');
+    if (const char* e = std::getenv("FX_NO_CFP")) p->use_cfp = (e[0] != '1');
+    if (const char* e = std::getenv("FX_NO_ASR")) p->use_asr = (e[0] != '1');
+    p->cfp_blocks = 2 * num_cus();
+    if (const char* e = std::getenv("FX_CFP_BLOCKS")) p->cfp_blocks = std::max(1, std::atoi(e));
     plan_setup_workspace(p, 1);
     *out = p;
     return FX_OK;

@@ -37,6 +37,7 @@ struct AxisDev {
     const void* TB = nullptr;
     const void* Tf = nullptr;
     const void* tw = nullptr;
+    const void* HT = nullptr;  // [lam][g][P] chirp-folded table of the register E kernel (or null)
     int M = 1;        // axis length
     int P = 1;        // M / g: number of distinct n'' values (output-pruned length)
     int g = 1;        // gcd(lam, M)
@@ -59,6 +60,8 @@ struct PassGeom {
     int TS = 1;        // lines per workgroup tile
     int64_t ntiles = 1;  // tiles per (slice, q)
     int max_blocks = 0;  // persistent grid: cap on workgroups (0 = one per tile)
+    int qc = 0;        // > 0: register E kernel, magnification indices per workgroup
+    bool reg_a = false;  // A pass: register structured accumulate
 };
 
 enum class Kind { E, A, EA, EH, AH, EAH };
@@ -101,6 +104,7 @@ int lds_limit_bytes();
 // Host-built FP64 tables (tables.cpp).
 struct AxisTables {
     std::vector<double> TA, TB, Tf, tw;  // interleaved re,im; [lam][M] for TA/TB/Tf, [M] for tw
+    std::vector<double> HT;              // [lam][g][P] when requested, else empty
 };
 struct AxisParams {
     int64_t M = 1;
@@ -110,8 +114,20 @@ struct AxisParams {
     // Optional spectrum: phase[i] = t * omega(kappa_l) in radians for the fine wave
     // number l = i - floor(lam M / 2); NULL keeps hbar t kappa^2 / 2m.
     const double* phase = nullptr;
+    bool want_ht = false;  // also build the chirp-folded table HT
 };
 AxisTables build_axis_tables(const AxisParams& p);
+
+// Register E kernel (output-pruned transform with the chirp folded into HT, kernels_cfp.hip).
+bool cfp_applicable(Kind kind, bool dbl, int M, int g);
+int cfp_tile_lines(int g);
+size_t cfp_lds_bytes(bool dbl, int M, int g);
+hipError_t launch_pass_cfp(Kind kind, bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g,
+                           int accumulate, void* rho, hipStream_t st);
+// Structured accumulate (A) with one thread per output group and register accumulators (g <= 32).
+bool asr_applicable(int g);
+hipError_t launch_pass_asr(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
+                           void* rho, hipStream_t st);
 
 void set_error(const std::string& msg);
 

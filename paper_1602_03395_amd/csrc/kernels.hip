@@ -702,6 +702,8 @@ hipError_t launch_pass(Kind kind, bool dbl, const void* in, void* out, const Axi
                        int accumulate, void* rho, hipStream_t st) {
     // tile kernels index their tiles with 32-bit integers
     if (g.Qin * g.qn * g.ntiles >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    if (g.qc > 0) return launch_pass_cfp(kind, dbl, in, out, ax, g, accumulate, rho, st);
+    if (kind == Kind::A && g.reg_a) return launch_pass_asr(dbl, in, out, ax, g, accumulate, rho, st);
     if (p2_applicable(kind, ax.M) && g.TS == p2_tile_lines(ax.M))
         return launch_pass_p2(kind, dbl, in, out, ax, g, accumulate, rho, st);
     if (ct_applicable(kind, ax.M) && g.TS == ct_tile_lines(ax.M))

@@ -1,0 +1,664 @@
+// Register form of the E and EA passes for short pruned lengths (P = M / g in {1, 2, 3, 4, 6, 8, 12,
+// 16}, g a power of two <= 64).
+//
+// The E pass of one axis maps a line x[0..M) to, for every magnification index q, the P values
+//   E_q[u] = (1/M) sum_r exp(2 pi i r u / P) sum_c (TB_q FFT_M(TA_q x))[r + P c]      (FF), (FFaux)
+// With n = g n1 + n2 the forward transform splits into P-point transforms of the g stride-g
+// subsequences, and the chirp, the alias fold over c and the remaining g-point stage fold into
+// one table HT_q[n2][r] (built on the host in FP64, see tables.cpp):
+//   E_q[u] = sum_n2 IDFT_P( HT_q[n2] * DFT_P( x[g n1 + n2] * TA_q[g n1] ) )[u].
+// One thread owns one (line, n2): its P inputs stay in registers for every q of the workgroup,
+// the two P-point transforms run in registers with constant twiddles, and the sum over n2 is a
+// butterfly reduction across the g lanes of the line (a line never straddles a wavefront).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <set>
+
+#include "fx_internal.h"
+#include "device_common.h"
+
+namespace fx {
+namespace {
+
+constexpr int kWave = 64;
+
+// cos(2 pi e / 32) for e = 0..8; the other 32nd roots follow by symmetry
+constexpr double kQ32[9] = {1.0,
+                            0.980785280403230449126182236134,
+                            0.923879532511286756128183189397,
+                            0.831469612302545237078788377618,
+                            0.707106781186547524400844362105,
+                            0.555570233019602224742830813949,
+                            0.382683432365089771728459984030,
+                            0.195090322016128267848284868477,
+                            0.0};
+constexpr double cos32(int e) {
+    e &= 31;
+    return e <= 8 ? kQ32[e] : e <= 16 ? -kQ32[16 - e] : e <= 24 ? -kQ32[e - 16] : kQ32[32 - e];
+}
+constexpr double sin32(int e) { return cos32(e + 24); }  // sin x = cos(x - pi/2)
+
+// a * exp(-+2 pi i e / 32) (forward sign -, inverse +), e a compile-time constant
+template <typename T, bool INV, int E>
+__device__ __forceinline__ C<T> tw32(C<T> a) {
+    constexpr int e = E & 31;
+    if constexpr (e == 0) return a;
+    else if constexpr (e == 8) return rot<T>(a, INV);
+    else if constexpr (e == 16) return mk<T>(-a.x, -a.y);
+    else if constexpr (e == 24) return rot<T>(a, !INV);
+    else {
+        constexpr double cd = cos32(e), sd = sin32(e);
+        const T c = (T)cd;
+        const T s = INV ? (T)sd : (T)-sd;
+        return mk<T>(a.x * c - a.y * s, a.x * s + a.y * c);
+    }
+}
+template <typename T, bool INV, int E>
+__device__ __forceinline__ C<T> tw16(C<T> a) { return tw32<T, INV, 2 * E>(a); }
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(C<T>& a, C<T>& b) {
+    const C<T> t = a;
+    a = cadd<T>(t, b);
+    b = csub<T>(t, b);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(C<T>& a0, C<T>& a1, C<T>& a2, C<T>& a3) {
+    const C<T> t0 = cadd<T>(a0, a2), t1 = csub<T>(a0, a2);
+    const C<T> t2 = cadd<T>(a1, a3), t3 = rot<T>(csub<T>(a1, a3), INV);
+    a0 = cadd<T>(t0, t2);
+    a2 = csub<T>(t0, t2);
+    a1 = cadd<T>(t1, t3);
+    a3 = csub<T>(t1, t3);
+}
+
+// In-register DFT of N points, natural order in and out.
+template <typename T, int N, bool INV> struct RegDFT;
+
+template <typename T, bool INV> struct RegDFT<T, 1, INV> {
+    __device__ __forceinline__ static void run(C<T>*) {}
+};
+template <typename T, bool INV> struct RegDFT<T, 2, INV> {
+    __device__ __forceinline__ static void run(C<T>* v) { dft2<T, INV>(v[0], v[1]); }
+};
+template <typename T, bool INV> struct RegDFT<T, 4, INV> {
+    __device__ __forceinline__ static void run(C<T>* v) { dft4<T, INV>(v[0], v[1], v[2], v[3]); }
+};
+template <typename T, bool INV> struct RegDFT<T, 8, INV> {
+    // radix 2 over two 4-point transforms of the even and odd samples
+    __device__ __forceinline__ static void run(C<T>* v) {
+        C<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+        C<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+        dft4<T, INV>(e0, e1, e2, e3);
+        dft4<T, INV>(o0, o1, o2, o3);
+        o1 = tw16<T, INV, 2>(o1);
+        o2 = tw16<T, INV, 4>(o2);
+        o3 = tw16<T, INV, 6>(o3);
+        v[0] = cadd<T>(e0, o0); v[4] = csub<T>(e0, o0);
+        v[1] = cadd<T>(e1, o1); v[5] = csub<T>(e1, o1);
+        v[2] = cadd<T>(e2, o2); v[6] = csub<T>(e2, o2);
+        v[3] = cadd<T>(e3, o3); v[7] = csub<T>(e3, o3);
+    }
+};
+template <typename T, bool INV> struct RegDFT<T, 16, INV> {
+    // 4 x 4: B[k1][j2] = DFT4 over n2 of v[k1 + 4 n2], times w16^(k1 j2), then DFT4 over k1.
+    __device__ __forceinline__ static void run(C<T>* v) {
+        dft4<T, INV>(v[0], v[4], v[8], v[12]);
+        dft4<T, INV>(v[1], v[5], v[9], v[13]);
+        dft4<T, INV>(v[2], v[6], v[10], v[14]);
+        dft4<T, INV>(v[3], v[7], v[11], v[15]);
+        v[5] = tw16<T, INV, 1>(v[5]);
+        v[9] = tw16<T, INV, 2>(v[9]);
+        v[13] = tw16<T, INV, 3>(v[13]);
+        v[6] = tw16<T, INV, 2>(v[6]);
+        v[10] = tw16<T, INV, 4>(v[10]);
+        v[14] = tw16<T, INV, 6>(v[14]);
+        v[7] = tw16<T, INV, 3>(v[7]);
+        v[11] = tw16<T, INV, 6>(v[11]);
+        v[15] = tw16<T, INV, 9>(v[15]);
+        // after the first pass v[k1 + 4 j2] holds B[k1][j2]; y[j2 + 4 j1] = DFT4 over k1
+        C<T> y[16];
+#pragma unroll
+        for (int j2 = 0; j2 < 4; ++j2) {
+            C<T> b0 = v[0 + 4 * j2], b1 = v[1 + 4 * j2], b2 = v[2 + 4 * j2], b3 = v[3 + 4 * j2];
+            dft4<T, INV>(b0, b1, b2, b3);
+            y[j2] = b0;
+            y[j2 + 4] = b1;
+            y[j2 + 8] = b2;
+            y[j2 + 12] = b3;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = y[i];
+    }
+};
+
+template <typename T, bool INV> struct RegDFT<T, 32, INV> {
+    // radix 2 over two 16-point transforms of the even and odd samples
+    __device__ __forceinline__ static void run(C<T>* v) {
+        C<T> e[16], o[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            e[i] = v[2 * i];
+            o[i] = v[2 * i + 1];
+        }
+        RegDFT<T, 16, INV>::run(e);
+        RegDFT<T, 16, INV>::run(o);
+        twiddle_odd<0>(o);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            v[k] = cadd<T>(e[k], o[k]);
+            v[k + 16] = csub<T>(e[k], o[k]);
+        }
+    }
+    template <int K>
+    __device__ __forceinline__ static void twiddle_odd(C<T>* o) {
+        if constexpr (K < 16) {
+            o[K] = tw32<T, INV, K>(o[K]);
+            twiddle_odd<K + 1>(o);
+        }
+    }
+};
+
+constexpr double kH3 = 0.866025403784438646763723170753;  // sin(pi/3)
+
+// a * exp(-+2 pi i k / 12) (forward sign -, inverse +), k a compile-time constant
+template <typename T, bool INV, int K>
+__device__ __forceinline__ C<T> tw12(C<T> a) {
+    constexpr int k = K % 12;
+    constexpr double ct[12] = {1.0, kH3, 0.5, 0.0, -0.5, -kH3, -1.0, -kH3, -0.5, 0.0, 0.5, kH3};
+    constexpr double st[12] = {0.0, 0.5, kH3, 1.0, kH3, 0.5, 0.0, -0.5, -kH3, -1.0, -kH3, -0.5};
+    if constexpr (k == 0) return a;
+    else if constexpr (k == 3) return rot<T>(a, INV);
+    else if constexpr (k == 6) return mk<T>(-a.x, -a.y);
+    else if constexpr (k == 9) return rot<T>(a, !INV);
+    else {
+        const T c = (T)ct[k];
+        const T sn = INV ? (T)st[k] : (T)-st[k];
+        return mk<T>(a.x * c - a.y * sn, a.x * sn + a.y * c);
+    }
+}
+
+template <typename T, bool INV> struct RegDFT<T, 3, INV> {
+    __device__ __forceinline__ static void run(C<T>* v) {
+        const C<T> t1 = cadd<T>(v[1], v[2]);
+        const C<T> t2 = csub<T>(v[1], v[2]);
+        const C<T> m = mk<T>(v[0].x - (T)0.5 * t1.x, v[0].y - (T)0.5 * t1.y);
+        const C<T> n = rot<T>(mk<T>((T)kH3 * t2.x, (T)kH3 * t2.y), INV);
+        v[0] = cadd<T>(v[0], t1);
+        v[1] = cadd<T>(m, n);
+        v[2] = csub<T>(m, n);
+    }
+};
+
+// radix 2 over two N/2-point transforms of the even and odd samples, N = 6 or 12
+template <typename T, bool INV, int N>
+struct RegDFT2x {
+    __device__ __forceinline__ static void run(C<T>* v) {
+        constexpr int H = N / 2;
+        C<T> e[H], o[H];
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            e[i] = v[2 * i];
+            o[i] = v[2 * i + 1];
+        }
+        RegDFT<T, H, INV>::run(e);
+        RegDFT<T, H, INV>::run(o);
+        twiddle<1>(o);
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            v[k] = cadd<T>(e[k], o[k]);
+            v[k + H] = csub<T>(e[k], o[k]);
+        }
+    }
+    template <int K>
+    __device__ __forceinline__ static void twiddle(C<T>* o) {
+        if constexpr (K < N / 2) {
+            o[K] = tw12<T, INV, K * (12 / N)>(o[K]);
+            twiddle<K + 1>(o);
+        }
+    }
+};
+template <typename T, bool INV> struct RegDFT<T, 6, INV> {
+    __device__ __forceinline__ static void run(C<T>* v) { RegDFT2x<T, INV, 6>::run(v); }
+};
+template <typename T, bool INV> struct RegDFT<T, 12, INV> {
+    __device__ __forceinline__ static void run(C<T>* v) { RegDFT2x<T, INV, 12>::run(v); }
+};
+
+template <typename T>
+__device__ __forceinline__ C<T> shfl_xor_c(C<T> a, int m) {
+    return mk<T>(__shfl_xor(a.x, m, kWave), __shfl_xor(a.y, m, kWave));
+}
+
+// Sum over the G = 2^lgG lanes of a line of each lane's P values. Reduce-scatter over the low
+// log2 P lane bits (each step keeps half of the values: the upper half when the lane bit is set),
+// then all-reduce over the remaining lane bits. Afterwards the lane holds P >> min(lgP, lgG)
+// consecutive values starting at base(n2) = sum_s bit_s(n2) * (P >> (s + 1)).
+template <typename T, int P, int S>
+__device__ __forceinline__ void reduce_step(C<T>* v, int n2, int lgG) {
+    if constexpr ((1 << S) < P) {
+        if (S < lgG) {
+            constexpr int half = (P >> S) >> 1;
+            const bool hi = (n2 >> S) & 1;
+#pragma unroll
+            for (int i = 0; i < half; ++i) {
+                const C<T> keep = hi ? v[i + half] : v[i];
+                const C<T> send = hi ? v[i] : v[i + half];
+                v[i] = cadd<T>(keep, shfl_xor_c<T>(send, 1 << S));
+            }
+            reduce_step<T, P, S + 1>(v, n2, lgG);
+        }
+    }
+}
+
+// Every lane of a line ends with all P sums over the G = 2^lgG lanes (any P).
+template <typename T, int P>
+__device__ __forceinline__ void reduce_all(C<T>* v, int lgG) {
+    for (int s = 0; s < lgG; ++s) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) v[i] = cadd<T>(v[i], shfl_xor_c<T>(v[i], 1 << s));
+    }
+}
+
+template <int P> constexpr bool kPow2 = (P & (P - 1)) == 0;
+
+template <typename T, int P>
+__global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
+                                                 PassGeom g, int lgG, const C<T>* __restrict__ TA,
+                                                 const C<T>* __restrict__ HT) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int LP = (P >= 32) ? 5 : (P >= 16) ? 4 : (P >= 8) ? 3 : (P >= 4) ? 2 : (P >= 2) ? 1 : 0;
+    C<T>* B = (C<T>*)smem;  // tile: TS lines x M points
+    const int M = ax.M;
+    const int G = 1 << lgG;
+    const int l = (int)threadIdx.x >> lgG;
+    const int n2 = (int)threadIdx.x & (G - 1);
+    const int qc = g.qc;
+    const int nqc = (g.qn + qc - 1) / qc;
+    const int64_t per_slice = g.ntiles * nqc;
+    const int64_t total = g.Qin * per_slice;
+    const int lk = (lgG < LP) ? lgG : LP;     // reduce-scatter steps
+    const int cnt = P >> lk;                  // values a lane holds afterwards
+    int base = 0;
+    for (int s = 0; s < lk; ++s) base += ((n2 >> s) & 1) * ((P >> s) >> 1);
+    const bool writer = (n2 >> lk) == 0 || lgG <= LP;
+    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
+        const int64_t qi = bid / per_slice;
+        const int64_t rest = bid - qi * per_slice;
+        const int64_t tt = rest / nqc;
+        const int ci = (int)(rest - tt * nqc);
+        const Tile tl = decode_tile(g, tt);
+        const FDiv fdM = tile_div(g, tl, M);
+        for (int e = threadIdx.x; e < tl.nl * M; e += kThreads) {
+            int ll, n;
+            const int64_t off = tile_elem(g, tl, qi, M, fdM, e, ll, n);
+            B[ll * M + n] = in[off];
+        }
+        __syncthreads();
+        const bool live = l < tl.nl;
+        const C<T>* x = B + l * M + n2;  // the line stays in LDS for every q (rows past nl are unused)
+        const int qlo = g.qb + ci * qc;
+        const int qhi = min(qlo + qc, g.qb + g.qn);
+        for (int q = qlo; q < qhi; ++q) {
+            const C<T>* ta = TA + (int64_t)q * M;
+            const C<T>* h = HT + ((int64_t)q * G + n2) * P;
+            C<T> v[P];
+#pragma unroll
+            for (int i = 0; i < P; ++i) v[i] = cmul<T>(x[i << lgG], ta[i << lgG]);
+            RegDFT<T, P, false>::run(v);
+#pragma unroll
+            for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r]);
+            RegDFT<T, P, true>::run(v);
+            if constexpr (!kPow2<P>) {
+                // all-reduce; lane n2 writes the values u = n2 mod G
+                reduce_all<T, P>(v, lgG);
+                if (live) {
+                    const int64_t qo = qi * g.qn + (q - g.qb);
+#pragma unroll
+                    for (int u = 0; u < P; ++u) {
+                        if ((u & (G - 1)) == n2) {
+                            const int64_t off = (g.S == 1) ? ((qo * g.A + tl.a0 + l) * P + u)
+                                                           : (((qo * g.A + tl.a0) * P + u) * g.S + tl.s0 + l);
+                            out[off] = v[u];
+                        }
+                    }
+                }
+                continue;
+            }
+            reduce_step<T, P, 0>(v, n2, lgG);
+            C<T> s0 = v[0];
+            for (int s = LP; s < lgG; ++s) s0 = cadd<T>(s0, shfl_xor_c<T>(s0, 1 << s));
+            v[0] = s0;
+            if (live && writer) {
+                const int64_t qo = qi * g.qn + (q - g.qb);
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    if (i < cnt) {
+                        const int u = base + i;
+                        const int64_t off = (g.S == 1) ? ((qo * g.A + tl.a0 + l) * P + u)
+                                                       : (((qo * g.A + tl.a0) * P + u) * g.S + tl.s0 + l);
+                        out[off] = v[i];
+                    }
+                }
+            }
+        }
+        __syncthreads();  // the next tile overwrites the buffer the q loop reads
+    }
+}
+
+// EA in register form: the E values of every q are combined at once into the lane's M / G = P
+// outputs nbar = n2 + G k (the accumulate of (FFpsi) along this axis):
+//   out[nbar] = sum_q Tf_q[nbar] E_q[r(nbar)],  r(nbar) = (nbar lg) mod P.
+// For a power-of-two P with G >= P, r(nbar) = (n2 lg) mod P is one value per lane, read with one
+// cross-lane shuffle from the lane that holds it after the reduce-scatter; otherwise every lane
+// keeps all P sums and picks r(nbar) per output.
+template <typename T, int P>
+__global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
+                                                  PassGeom g, int accumulate, T* __restrict__ rho, int lgG,
+                                                  const C<T>* __restrict__ TA, const C<T>* __restrict__ Tf,
+                                                  const C<T>* __restrict__ HT) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int LP = (P >= 32) ? 5 : (P >= 16) ? 4 : (P >= 8) ? 3 : (P >= 4) ? 2 : (P >= 2) ? 1 : 0;
+    C<T>* B = (C<T>*)smem;
+    const int M = ax.M;
+    const int G = 1 << lgG;
+    const int l = (int)threadIdx.x >> lgG;
+    const int n2 = (int)threadIdx.x & (G - 1);
+    const int64_t total = g.Qin * g.ntiles;
+    // after the reduction lane n2' holds E[bitrev_LP(n2' mod P)]; this lane needs u = (n2 lg) mod P
+    const int u_need = (int)(((int64_t)n2 * ax.lg) % P);
+    int src = 0;
+    for (int s = 0; s < LP; ++s) src |= ((u_need >> s) & 1) << (LP - 1 - s);
+    const int lane = (int)threadIdx.x & (kWave - 1);
+    const int src_lane = lane - n2 + src;
+    // power-of-two P with G >= P: reduce-scatter and one shuffle; otherwise all-reduce and pick
+    const bool scatter = kPow2<P> && G >= P;
+    // r(nbar) of the lane's outputs nbar = n2 + G k is r0 + k d (mod P)
+    const int r0 = (int)(((int64_t)n2 * ax.lg) % P);
+    const int rd = (int)(((int64_t)G * ax.lg) % P);
+    // power-of-two P with G < P: after the reduce-scatter the lane holds cnt values from base
+    const int lk = (lgG < LP) ? lgG : LP;
+    const int cnt = P >> lk;
+    int base = 0;
+    for (int s = 0; s < lk; ++s) base += ((n2 >> s) & 1) * ((P >> s) >> 1);
+    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
+        const int64_t qi = bid / g.ntiles;
+        const int64_t tt = bid - qi * g.ntiles;
+        const Tile tl = decode_tile(g, tt);
+        const FDiv fdM = tile_div(g, tl, M);
+        for (int e = threadIdx.x; e < tl.nl * M; e += kThreads) {
+            int ll, n;
+            const int64_t off = tile_elem(g, tl, qi, M, fdM, e, ll, n);
+            B[ll * M + n] = in[off];
+        }
+        __syncthreads();
+        const bool live = l < tl.nl;
+        C<T> x[P], acc[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            x[i] = live ? B[l * M + (i << lgG) + n2] : mk<T>(0, 0);
+            acc[i] = mk<T>(0, 0);
+        }
+        __syncthreads();
+        for (int q = g.qb; q < g.qb + g.qn; ++q) {
+            const C<T>* ta = TA + (int64_t)q * M;
+            const C<T>* h = HT + ((int64_t)q * G + n2) * P;
+            const C<T>* tf = Tf + (int64_t)q * M + n2;
+            C<T> v[P];
+#pragma unroll
+            for (int i = 0; i < P; ++i) v[i] = cmul<T>(x[i], ta[i << lgG]);
+            RegDFT<T, P, false>::run(v);
+#pragma unroll
+            for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r]);
+            RegDFT<T, P, true>::run(v);
+            if (scatter) {
+                reduce_step<T, P, 0>(v, n2, lgG);
+                C<T> s0 = v[0];
+                for (int s = LP; s < lgG; ++s) s0 = cadd<T>(s0, shfl_xor_c<T>(s0, 1 << s));
+                const C<T> e = mk<T>(__shfl(s0.x, src_lane, kWave), __shfl(s0.y, src_lane, kWave));
+#pragma unroll
+                for (int k = 0; k < P; ++k) acc[k] = cfma<T>(acc[k], tf[k << lgG], e);
+            } else {
+                // the line's P sums go through LDS (the tile buffer is free during the q loop)
+                C<T>* El = B + l * P;
+                if constexpr (kPow2<P>) {
+                    reduce_step<T, P, 0>(v, n2, lgG);  // G < P: the lane holds P / G values from base
+#pragma unroll
+                    for (int i = 0; i < P; ++i)
+                        if (i < cnt) El[base + i] = v[i];
+                } else {
+                    reduce_all<T, P>(v, lgG);
+#pragma unroll
+                    for (int u = 0; u < P; ++u)
+                        if ((u & (G - 1)) == n2) El[u] = v[u];
+                }
+                wave_sync();
+                int rk = r0;
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    acc[k] = cfma<T>(acc[k], tf[k << lgG], El[rk]);
+                    rk += rd;
+                    if (rk >= P) rk -= P;
+                }
+                wave_sync();
+            }
+        }
+        if (live) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const int nb = n2 + (k << lgG);
+                const int64_t off = (g.S == 1) ? ((qi * g.A + tl.a0 + l) * M + nb)
+                                               : (((qi * g.A + tl.a0) * M + nb) * g.S + tl.s0 + l);
+                C<T> v = acc[k];
+                if (accumulate) v = cadd<T>(v, out[off]);
+                out[off] = v;
+                if (rho) rho[off] = v.x * v.x + v.y * v.y;
+            }
+        }
+        __syncthreads();  // the next tile overwrites the buffer the q loop used
+    }
+}
+
+// Structured accumulate in registers: one thread per group (qo, a, n0, s). For the outputs
+// nbar = n0 + P c (c < g) every term reads the same input sample r(n0), and the twiddle (presf)
+// satisfies Tf_q[n0 + P c] = Tf_q[n0] exp(2 pi i q c / g), so with j = (q - qb) mod g
+//   out[n0 + P c] = exp(2 pi i qb c / g) sum_j exp(2 pi i j c / g) H[j],
+//   H[j] = sum_{q - qb = j mod g} Tf_q[n0] in_q[r(n0)],
+// a g-point inverse transform of register accumulators per group.
+template <typename T, int G>
+__global__ __launch_bounds__(kThreads) void k_ASR(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
+                                                  PassGeom g, int accumulate, T* __restrict__ rho) {
+    const int M = ax.M, P = ax.P;
+    const int64_t S = g.S;
+    const int64_t PS = (int64_t)P * S;
+    const int64_t ngroups = g.Qin * g.A * PS;
+    const int64_t step = g.A * PS;  // one magnification slice of the input
+    const C<T>* Tf = (const C<T>*)ax.Tf;
+    const C<T>* twg = (const C<T>*)ax.tw;
+    const int qbr = g.qb % G;
+    for (int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < ngroups;
+         gi += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = gi / PS;  // (qo, a)
+        const int64_t rem = gi - row * PS;
+        const int n0 = (int)(rem / S);
+        const int64_t s = rem - (int64_t)n0 * S;
+        const int64_t qo = row / g.A;
+        const int64_t a = row - qo * g.A;
+        const int r = (int)(((int64_t)n0 * ax.lg) % P);
+        const C<T>* src = in + (qo * g.qn * g.A + a) * PS + (int64_t)r * S + s;
+        const C<T>* tf = Tf + (int64_t)g.qb * M + n0;
+        C<T> h[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) h[j] = mk<T>(0, 0);
+        // whole blocks of G terms: every load of a block is issued before the first product
+        int i0 = 0;
+        for (; i0 + G <= g.qn; i0 += G) {
+            C<T> a[G], b[G];
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                a[j] = tf[(int64_t)(i0 + j) * M];
+                b[j] = src[(int64_t)(i0 + j) * step];
+            }
+#pragma unroll
+            for (int j = 0; j < G; ++j) h[j] = cfma<T>(h[j], a[j], b[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if (i0 + j < g.qn) h[j] = cfma<T>(h[j], tf[(int64_t)(i0 + j) * M], src[(int64_t)(i0 + j) * step]);
+        RegDFT<T, G, true>::run(h);
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+            C<T> v = h[c];
+            if (qbr != 0) v = cmulc<T>(v, twg[((qbr * c) % G) * P]);  // exp(+2 pi i qb c / g)
+            const int64_t o = (row * M + n0 + (int64_t)P * c) * S + s;
+            if (accumulate) v = cadd<T>(v, out[o]);
+            out[o] = v;
+            if (rho) rho[o] = v.x * v.x + v.y * v.y;
+        }
+    }
+}
+
+hipError_t prep_lds(const void* k, size_t lds) {
+    static std::mutex mu;
+    static std::set<const void*> done;
+    std::lock_guard<std::mutex> lk(mu);
+    if (lds > 65536 && !done.count(k)) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        done.insert(k);
+    }
+    return hipSuccess;
+}
+
+int ilog2i(int v) {
+    int r = 0;
+    while ((1 << r) < v) ++r;
+    return r;
+}
+
+template <typename T, int P>
+hipError_t launch_er(const void* in, void* out, const AxisDev& ax, const PassGeom& g, hipStream_t st) {
+    const size_t lds = cfp_lds_bytes(sizeof(T) == 8, ax.M, ax.g);
+    auto k = k_ER<T, P>;
+    hipError_t e = prep_lds((const void*)k, lds);
+    if (e != hipSuccess) return e;
+    const int nqc = (g.qn + g.qc - 1) / g.qc;
+    int64_t blocks = g.Qin * g.ntiles * nqc;
+    if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = g.max_blocks;
+    if (blocks > (1 << 22)) blocks = 1 << 22;
+    hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), lds, st, (const C<T>*)in,
+                       (C<T>*)out, ax, g, ilog2i(ax.g), (const C<T>*)ax.TA, (const C<T>*)ax.HT);
+    return hipGetLastError();
+}
+
+template <typename T, int P>
+hipError_t launch_ear(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
+                      hipStream_t st) {
+    const size_t lds = cfp_lds_bytes(sizeof(T) == 8, ax.M, ax.g);
+    auto k = k_EAR<T, P>;
+    hipError_t e = prep_lds((const void*)k, lds);
+    if (e != hipSuccess) return e;
+    int64_t blocks = g.Qin * g.ntiles;
+    if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = g.max_blocks;
+    if (blocks > (1 << 22)) blocks = 1 << 22;
+    hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), lds, st, (const C<T>*)in,
+                       (C<T>*)out, ax, g, accumulate, (T*)rho, ilog2i(ax.g), (const C<T>*)ax.TA,
+                       (const C<T>*)ax.Tf, (const C<T>*)ax.HT);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_er_T(Kind kind, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
+                       void* rho, hipStream_t st) {
+    if (kind == Kind::EA) {
+        switch (ax.P) {
+            case 1: return launch_ear<T, 1>(in, out, ax, g, accumulate, rho, st);
+            case 2: return launch_ear<T, 2>(in, out, ax, g, accumulate, rho, st);
+            case 4: return launch_ear<T, 4>(in, out, ax, g, accumulate, rho, st);
+            case 8: return launch_ear<T, 8>(in, out, ax, g, accumulate, rho, st);
+            case 16: return launch_ear<T, 16>(in, out, ax, g, accumulate, rho, st);
+            case 3: return launch_ear<T, 3>(in, out, ax, g, accumulate, rho, st);
+            case 6: return launch_ear<T, 6>(in, out, ax, g, accumulate, rho, st);
+            case 12: return launch_ear<T, 12>(in, out, ax, g, accumulate, rho, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (ax.P) {
+        case 1: return launch_er<T, 1>(in, out, ax, g, st);
+        case 2: return launch_er<T, 2>(in, out, ax, g, st);
+        case 4: return launch_er<T, 4>(in, out, ax, g, st);
+        case 8: return launch_er<T, 8>(in, out, ax, g, st);
+        case 16: return launch_er<T, 16>(in, out, ax, g, st);
+        case 3: return launch_er<T, 3>(in, out, ax, g, st);
+        case 6: return launch_er<T, 6>(in, out, ax, g, st);
+        case 12: return launch_er<T, 12>(in, out, ax, g, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int G>
+hipError_t launch_asr(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
+                      hipStream_t st) {
+    const int64_t ngroups = g.Qin * g.A * (int64_t)ax.P * g.S;
+    int64_t blocks = (ngroups + kThreads - 1) / kThreads;
+    if (blocks > (1 << 20)) blocks = 1 << 20;
+    hipLaunchKernelGGL((k_ASR<T, G>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), 0, st,
+                       (const C<T>*)in, (C<T>*)out, ax, g, accumulate, (T*)rho);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_asr_T(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
+                        hipStream_t st) {
+    switch (ax.g) {
+        case 1: return launch_asr<T, 1>(in, out, ax, g, accumulate, rho, st);
+        case 2: return launch_asr<T, 2>(in, out, ax, g, accumulate, rho, st);
+        case 4: return launch_asr<T, 4>(in, out, ax, g, accumulate, rho, st);
+        case 8: return launch_asr<T, 8>(in, out, ax, g, accumulate, rho, st);
+        case 16: return launch_asr<T, 16>(in, out, ax, g, accumulate, rho, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+// g = 32 keeps 32 complex accumulators per thread and leaves too few threads in flight; the
+// LDS-transform form (k_AS) is faster there.
+bool asr_applicable(int g) { return g == 1 || g == 2 || g == 4 || g == 8 || g == 16; }
+
+hipError_t launch_pass_asr(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
+                           void* rho, hipStream_t st) {
+    if (!asr_applicable(ax.g)) return hipErrorInvalidValue;
+    return dbl ? launch_asr_T<double>(in, out, ax, g, accumulate, rho, st)
+               : launch_asr_T<float>(in, out, ax, g, accumulate, rho, st);
+}
+
+bool cfp_applicable(Kind kind, bool dbl, int M, int g) {
+    if (kind != Kind::E && kind != Kind::EA) return false;
+    if (g < 1 || g > kWave || (g & (g - 1)) != 0) return false;
+    if (M % g != 0) return false;
+    const int P = M / g;
+    (void)dbl;
+    return P == 1 || P == 2 || P == 4 || P == 8 || P == 16 || P == 3 || P == 6 || P == 12;
+}
+
+int cfp_tile_lines(int g) { return kThreads / std::max(1, g); }
+
+size_t cfp_lds_bytes(bool dbl, int M, int g) {
+    // TS lines of M points with TS = kThreads / g, i.e. kThreads * P points
+    return (size_t)kThreads * (size_t)(M / std::max(1, g)) * (dbl ? 16 : 8);
+}
+
+hipError_t launch_pass_cfp(Kind kind, bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g,
+                           int accumulate, void* rho, hipStream_t st) {
+    if (!cfp_applicable(kind, dbl, ax.M, ax.g) || !ax.HT || g.TS != cfp_tile_lines(ax.g) || g.qc < 1)
+        return hipErrorInvalidValue;
+    if (g.Qin * g.ntiles * ((g.qn + g.qc - 1) / g.qc) >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    return dbl ? launch_er_T<double>(kind, in, out, ax, g, accumulate, rho, st)
+               : launch_er_T<float>(kind, in, out, ax, g, accumulate, rho, st);
+}
+
+}  // namespace fx

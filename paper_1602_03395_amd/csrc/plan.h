@@ -55,6 +55,9 @@ struct fx_plan {
     int ts_target = 2048;
     bool allow_split = true;       // split a starved fused EA pass into E + A
     bool spectrum[3] = {false, false, false};  // axis built from a caller spectrum table
+    bool use_cfp = true;           // register E kernel where the pruned length allows it
+    bool use_asr = true;           // register structured accumulate for g <= 32
+    int cfp_blocks = 1024;         // register E kernel: target workgroups per launch
     bool use_p2 = true;            // compile-time specialised kernels for power-of-two axes
     int persist = 0;               // >0: tile passes run as persistent grids of persist x CUs workgroups
     size_t budget = 0;

@@ -58,6 +58,44 @@ inline void put(std::vector<double>& v, size_t i, double cycles, double amp) {
     v[2 * i + 1] = amp * std::sin(ang);
 }
 
+// Chirp-folded table of the register E kernel. With g = gcd(lam, M), P = M / g, input index
+// n = g n1 + n2 and spectral index m = r + P c (n1, r < P; n2, c < g), the forward DFT factors as
+//   Y[r + P c] = sum_n2 w_g^(n2 c) w_M^(n2 r) V[n2][r],  V[n2][r] = sum_n1 w_P^(n1 r) y[g n1 + n2],
+// so the chirp (presB) and the fold over c of the pruned inverse collapse into
+//   W[r] = sum_c TB[r + P c] Y[r + P c] = sum_n2 HT[n2][r] V[n2][r],
+//   HT[n2][r] = w_M^(n2 r) TA'[n2] sum_c TB[r + P c] w_g^(n2 c) / M,
+// where the n2 part of (presA), TA'[n2] = exp(-2 pi i q n2 / (lam M)), and the 1/M of the inverse
+// are folded in as well. Layout [q][n2][r], FP64 complex.
+void build_ht(AxisTables& t, int64_t M, int64_t lam) {
+    int64_t g = lam, b = M;
+    while (b) { const int64_t r = g % b; g = b; b = r; }
+    const int64_t P = M / g;
+    const int64_t N = lam * M;
+    t.HT.assign(2 * (size_t)(lam * M), 0.0);
+    std::vector<double> rg(2 * (size_t)g);  // exp(-2 pi i k / g)
+    for (int64_t k = 0; k < g; ++k) put(rg, (size_t)k, -rational_cycles(k, g), 1.0);
+    for (int64_t q = 0; q < lam; ++q) {
+        const double* tb = &t.TB[2 * (size_t)(q * M)];
+        for (int64_t n2 = 0; n2 < g; ++n2) {
+            for (int64_t r = 0; r < P; ++r) {
+                double sr = 0.0, si = 0.0;
+                for (int64_t c = 0; c < g; ++c) {
+                    const double* z = tb + 2 * (r + P * c);
+                    const double* w = &rg[2 * (size_t)((n2 * c) % g)];
+                    sr += z[0] * w[0] - z[1] * w[1];
+                    si += z[0] * w[1] + z[1] * w[0];
+                }
+                // exp(-2 pi i (n2 r lam + q n2) / (lam M)) / M
+                const double ang = -kTwoPi * rational_cycles(n2 * r * lam + q * n2, N);
+                const double er = std::cos(ang) / (double)M, ei = std::sin(ang) / (double)M;
+                const size_t i = 2 * (size_t)((q * g + n2) * P + r);
+                t.HT[i] = sr * er - si * ei;
+                t.HT[i + 1] = sr * ei + si * er;
+            }
+        }
+    }
+}
+
 }  // namespace
 
 AxisTables build_axis_tables(const AxisParams& p) {
@@ -107,6 +145,7 @@ AxisTables build_axis_tables(const AxisParams& p) {
         }
     }
     for (int64_t k = 0; k < M; ++k) put(t.tw, (size_t)k, -rational_cycles(k, M), 1.0);
+    if (p.want_ht) build_ht(t, M, lam);
     return t;
 }
 

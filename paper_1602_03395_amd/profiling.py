@@ -54,7 +54,8 @@ def counters(path: str, counter: str):
     return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
 
 
-KERNEL_SOURCES = ("kernels.hip", "kernels_p2.hip", "kernels_ct.hip", "device_common.h", "fx_internal.h")
+KERNEL_SOURCES = ("kernels.hip", "kernels_p2.hip", "kernels_ct.hip", "kernels_cfp.hip", "device_common.h",
+                  "fx_internal.h")
 
 
 def kernels_hash() -> str:
@@ -66,7 +67,7 @@ def kernels_hash() -> str:
 
 
 # pass kernels: k_E, k_E2 (power-of-two), k_Ect (3*2^k), k_EA*, k_A, k_AS (structured), adjoints
-PASS_KIND = re.compile(r"\bk_(EAH|EA|EH|AH|E|A)(?:2|ct|S)?<")
+PASS_KIND = re.compile(r"\bk_(EAH|EA|EH|AH|E|A)(?:2|ct|S|R)?<")
 
 
 def _pass_dispatches(path: str, counter: str):

@@ -60,6 +60,14 @@ CASES = [
     ((3,), (1,), (1.0,), 1.0, 1.0, 0.0),
     ((12, 24, 48), (2, 3, 4), (1.0, 1.0, 1.0), 7.0, 1.0, 0.1),
     ((96,), (6,), (1.0,), 30.0, 1.0, 0.0),
+    # register-form passes: pruned lengths 3, 6, 12, 16, 2, 1 with 2..64 lanes per line
+    ((24,), (8,), (1.0,), 10.0, 1.0, 0.0),
+    ((32, 48), (2, 8), (1.0, 1.0), 20.0, 1.0, 0.3),
+    ((64, 32), (32, 64), (1.0, 1.0), 300.0, 1.0, 0.0),
+    ((1024,), (64,), (1.0,), 400.0, 1.0, 0.0),
+    ((8, 96), (4, 8), (1.0, 0.5), 25.0, 1.0, 0.2),
+    ((40, 12, 48), (8, 2, 4), (1.0, 1.0, 1.0), 15.0, 1.0, 0.0),
+    ((64, 64), (2, 6), (1.0, 1.0), 40.0, 1.0, 0.1),     # 32 points per lane (FP32 register form)
 ]
 
 
