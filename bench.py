@@ -178,9 +178,10 @@ def main():
                     help="c4 only: expand this single realization through one plan (per-pass timing)")
     ap.add_argument("--dtype", default=None, choices=[None, "c64", "c128"])
     ap.add_argument("--schedule", default="paper", choices=["paper", "axis_factorised"])
-    ap.add_argument("--variant", default="free", choices=["free", "spectrum", "pair"],
+    ap.add_argument("--variant", default="free", choices=["free", "spectrum", "pair", "far_field"],
                     help="free: free flight (the paper's case); spectrum: a tabulated non-quadratic "
-                         "axis-additive spectrum of the same size; pair: positive-P pair psi, psi^+")
+                         "axis-additive spectrum of the same size; pair: positive-P pair psi, psi^+; "
+                         "far_field: the far-field estimate (comparator) on the same output lattice")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -247,6 +248,9 @@ def main():
 
         def step():
             return plan.expand_pair(psi, psi_plus)
+    elif args.variant == "far_field":
+        def step():
+            return plan.far_field(psi)
     else:
         def step():
             return plan.expand(psi, psi_out=out, rho_out=rho)

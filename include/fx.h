@@ -219,6 +219,21 @@ fx_status fx_expand_pair(fx_plan* plan, const void* psi, const void* psi_plus, v
 fx_status fx_plan_pair_workspace_size(const fx_plan* plan, size_t* bytes);
 
 /*
+ * Far-field estimate (section 2.2, eq. (farfieldk)) on the plan's magnified output
+ * lattice, the comparator the finite-time expansion replaces:
+ *   amp[nbar] = (m / hbar t)^(d/2) Psi~(m xbar(nbar) / hbar t),   rho_ff = |amp|^2,
+ * with Psi~ the norm-preserving transform of eq. (FT) summed over the input lattice as
+ * in eq. (Psiwtm) but evaluated at the off-grid wave vectors m xbar / (hbar t). The
+ * estimate carries no further phase information. Each axis is a dense complex matrix
+ * (built on the host in FP64 on first use, kept by the plan) applied as a batched GEMM.
+ * psi0: device input of the plan's shape and type; amp_out (complex) and rho_out (real)
+ * are device outputs of the same shape, either may be NULL but not both.
+ * Errors: FX_EINVAL (NULL plan or input, both outputs NULL, t_flight == 0),
+ * FX_EUNSUPPORTED (a plan built with a caller spectrum), FX_ENOMEM, FX_EDEVICE.
+ */
+fx_status fx_far_field(fx_plan* plan, const void* psi0, void* amp_out, void* rho_out, void* stream);
+
+/*
  * Ragged batch of problems (ensembles of realizations, section 1): problems
  * with equal shape, spacing, offsets, magnification, flight and precision
  * share one plan and run as one batched pass sequence; different shape

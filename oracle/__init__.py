@@ -32,6 +32,7 @@ from .propagator import (  # noqa: F401
     fine_wavenumbers,
     gtable_phase,
     expand_points,
+    far_field,
     gtable,
     gtable_longdouble,
     loss_and_grad,

@@ -372,3 +372,41 @@ def expand_pair(psi: np.ndarray, psi_plus: np.ndarray, dx, m_over_hbar: float, t
     pb = _apply(mats, psi)
     pbp = _apply([G.conj() for G in mats], psi_plus)
     return pb, pbp, pbp * pb
+
+
+# ----------------------------------------------------------------------------------------
+# Far-field estimate (section 2.2, eqs. (farfieldk), (FT), (Psiwtm)): the comparator the
+# finite-time expansion replaces.
+# ----------------------------------------------------------------------------------------
+
+def far_field(psi: np.ndarray, dx, m_over_hbar: float, t: float, lam, a=None, abar=None):
+    """Far-field amplitude and density on the magnified output lattice.
+
+    rho_ff(r) = (m / hbar t)^d |Psi~(m r / hbar t)|^2 (eq. (farfieldk)) with the norm-preserving
+    transform of eq. (FT) evaluated directly (not on the DFT grid) at kappa = m r / (hbar t) from the
+    lattice sum of eq. (Psiwtm): Psi~(kappa) = dV / (2 pi)^(d/2) sum_n Psi_n exp(-i kappa . x_n).
+    r runs over the output points xbar_j = abar_j + nbar_j lam_j dx_j. Returns (amp, rho) with
+    amp = (m / hbar t)^(d/2) Psi~(m r / hbar t) (the estimate carries no phase information beyond
+    this), rho = |amp|^2. Phases are accumulated in long double before one exponential.
+    """
+    psi = np.asarray(psi).astype(np.complex128)
+    d = psi.ndim
+    if t == 0:
+        raise ValueError("the far-field estimate needs t != 0")
+    dx = np.broadcast_to(np.asarray(dx, dtype=np.float64), (d,))
+    lam = np.broadcast_to(np.asarray(lam, dtype=np.int64), (d,))
+    a, abar = default_offsets(psi.shape, dx, lam, a, abar)
+    scale = np.longdouble(m_over_hbar) / np.longdouble(t)
+    mats = []
+    for j in range(d):
+        M = psi.shape[j]
+        x = np.longdouble(a[j]) + np.arange(M, dtype=np.longdouble) * np.longdouble(dx[j])
+        xb = np.longdouble(abar[j]) + np.arange(M, dtype=np.longdouble) * np.longdouble(lam[j] * dx[j])
+        ph = -(scale * xb)[:, None] * x[None, :]
+        two_pi = 2 * np.arccos(np.longdouble(-1))
+        ph = ph - two_pi * np.rint(ph / two_pi)
+        mats.append((np.cos(ph) + 1j * np.sin(ph)).astype(np.complex128))
+    amp = _apply(mats, psi)
+    dV = float(np.prod(dx))
+    amp = amp * (float(abs(scale)) ** (d / 2.0)) * dV / (2.0 * np.pi) ** (d / 2.0)
+    return amp, density(amp)

@@ -205,6 +205,15 @@ class Plan:
                                      _stream_ptr()), "fx_expand_pair")
         return out, out_plus, n
 
+    def far_field(self, psi0: torch.Tensor, want_amp: bool = True):
+        """Far-field estimate on the magnified lattice: returns (amp or None, rho_ff), see ``fx_far_field``."""
+        _check_field(psi0, "psi0")
+        self._check_shape(psi0)
+        amp = torch.empty_like(psi0) if want_amp else None
+        rho = torch.empty(psi0.shape, dtype=real_dtype(psi0.dtype), device=psi0.device)
+        L.check(L.lib.fx_far_field(self._h, _ptr(psi0), _ptr(amp), _ptr(rho), _stream_ptr()), "fx_far_field")
+        return amp, rho
+
     def _check_shape(self, x: torch.Tensor):
         if tuple(x.shape) != self.shape:
             raise ValueError(f"tensor shape {tuple(x.shape)} does not match the plan's {self.shape}")

@@ -582,6 +582,8 @@ fx_status fx_plan_destroy(fx_plan* p) {
     for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
     if (p->ws_owned && p->ws) (void)hipFree(p->ws);
     if (p->dtab) (void)hipFree(p->dtab);
+    if (p->ff_tab) (void)hipFree(p->ff_tab);
+    if (p->ff_buf) (void)hipFree(p->ff_buf);
     delete p;
     return FX_OK;
 }

@@ -55,6 +55,9 @@ struct fx_plan {
     int ts_target = 2048;
     bool allow_split = true;       // split a starved fused EA pass into E + A
     bool spectrum[3] = {false, false, false};  // axis built from a caller spectrum table
+    void* ff_tab = nullptr;        // far-field comparator: per-axis dense matrices (built on first use)
+    void* ff_buf = nullptr;        // far-field comparator: two M-point buffers
+    size_t ff_off[3] = {0, 0, 0};
     bool use_cfp = true;           // register E kernel where the pruned length allows it
     bool use_asr = true;           // register structured accumulate for g <= 32
     int cfp_blocks = 1024;         // register E kernel: target workgroups per launch

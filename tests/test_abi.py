@@ -146,3 +146,8 @@ def test_pair_entry_rejects_null_arguments():
     L = _lib()
     assert L.lib.fx_expand_pair(None, None, None, None, None, None, None) == L.FX_EINVAL
     assert L.lib.fx_plan_pair_workspace_size(None, None) == L.FX_EINVAL
+
+
+def test_far_field_entry_rejects_null_arguments():
+    L = _lib()
+    assert L.lib.fx_far_field(None, None, None, None, None) == L.FX_EINVAL
