@@ -163,7 +163,7 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
         if (g.S == 1) g.ntiles = (g.A + g.TS - 1) / g.TS;
         else g.ntiles = g.A * ((g.S + g.TS - 1) / g.TS);
         g.max_blocks = p->persist > 0 ? p->persist * num_cus() : 0;
-        g.reg_a = (kind == Kind::A) && p->use_asr && asr_applicable(p->ax[ax].g);
+        g.reg_a = (kind == Kind::A) && p->use_asr && asr_applicable(p->ax[ax].g, p->asr_max_g);
         if (reg && kind == Kind::EA) {
             g.qc = g.qn;  // the fused pass sums every magnification index inside the workgroup
         } else if (reg) {
@@ -542,6 +542,7 @@ fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_pla
     if (const char* e = std::getenv("FX_NO_P2")) p->use_p2 = (e[0] != '1');
     if (const char* e = std::getenv("FX_NO_CFP")) p->use_cfp = (e[0] != '1');
     if (const char* e = std::getenv("FX_NO_ASR")) p->use_asr = (e[0] != '1');
+    if (const char* e = std::getenv("FX_ASR_MAXG")) p->asr_max_g = std::max(1, std::atoi(e));
     p->cfp_blocks = 2 * num_cus();
     if (const char* e = std::getenv("FX_CFP_BLOCKS")) p->cfp_blocks = std::max(1, std::atoi(e));
     plan_setup_workspace(p, 1);

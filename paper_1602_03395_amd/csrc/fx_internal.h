@@ -125,7 +125,7 @@ size_t cfp_lds_bytes(bool dbl, int M, int g);
 hipError_t launch_pass_cfp(Kind kind, bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g,
                            int accumulate, void* rho, hipStream_t st);
 // Structured accumulate (A) with one thread per output group and register accumulators (g <= 32).
-bool asr_applicable(int g);
+bool asr_applicable(int g, int max_g);
 hipError_t launch_pass_asr(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
                            void* rho, hipStream_t st);
 

@@ -265,7 +265,35 @@ __device__ __forceinline__ void reduce_all(C<T>* v, int lgG) {
 
 template <int P> constexpr bool kPow2 = (P & (P - 1)) == 0;
 
-template <typename T, int P>
+// wst[s] = exp(+2 pi i (n2 mod 2^s) / 2^(s+1)) = conj(tw[(n2 mod 2^s) M / 2^(s+1)]), tw[k] = exp(-2 pi i k / M)
+template <typename T, int LP>
+__device__ __forceinline__ void lane_twiddles(C<T>* wst, int n2, const C<T>* tw, int M) {
+#pragma unroll
+    for (int s = 0; s < LP; ++s) {
+        const C<T> w = tw[(n2 & ((1 << s) - 1)) * (M >> (s + 1))];
+        wst[s] = mk<T>(w.x, -w.y);
+    }
+}
+
+// Inverse P-point DFT across the first P lanes of a line (power-of-two P <= G). On entry lane n2
+// holds W[bitrev(n2 mod P)], the order the reduce-scatter leaves; radix-2 decimation in time on
+// bit-reversed input yields natural order, so on exit lane n2 holds sum_r W[r] exp(2 pi i r u / P)
+// for u = n2 mod P. wst[s] = exp(2 pi i (n2 mod 2^s) / 2^(s+1)) is the lane's twiddle of stage s.
+template <typename T, int LP>
+__device__ __forceinline__ C<T> lane_idft(C<T> a, int n2, const C<T>* wst) {
+#pragma unroll
+    for (int s = 0; s < LP; ++s) {
+        const int h = 1 << s;
+        const C<T> b = shfl_xor_c<T>(a, h);
+        const bool upper = (n2 & h) != 0;
+        // lower lane: a + w b; upper lane: b - w a (b is then the lower value)
+        const C<T> wx = cmul<T>(wst[s], upper ? a : b);
+        a = upper ? csub<T>(b, wx) : cadd<T>(a, wx);
+    }
+    return a;
+}
+
+template <typename T, int P, bool LANEINV>
 __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
                                                  PassGeom g, int lgG, const C<T>* __restrict__ TA,
                                                  const C<T>* __restrict__ HT) {
@@ -285,6 +313,8 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
     int base = 0;
     for (int s = 0; s < lk; ++s) base += ((n2 >> s) & 1) * ((P >> s) >> 1);
     const bool writer = (n2 >> lk) == 0 || lgG <= LP;
+    C<T> wst[LP > 0 ? LP : 1];
+    lane_twiddles<T, LP>(wst, n2, (const C<T>*)ax.tw, M);
     for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
         const int64_t qi = bid / per_slice;
         const int64_t rest = bid - qi * per_slice;
@@ -311,6 +341,23 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
             RegDFT<T, P, false>::run(v);
 #pragma unroll
             for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r]);
+            if constexpr (LANEINV) {
+                {
+                    // sum over the lanes first, then one inverse transform across the P lanes
+                    reduce_step<T, P, 0>(v, n2, lgG);
+                    C<T> s0 = v[0];
+                    for (int s = LP; s < lgG; ++s) s0 = cadd<T>(s0, shfl_xor_c<T>(s0, 1 << s));
+                    s0 = lane_idft<T, LP>(s0, n2, wst);
+                    if (live && n2 < P) {
+                        const int64_t qo = qi * g.qn + (q - g.qb);
+                        const int64_t off = (g.S == 1) ? ((qo * g.A + tl.a0 + l) * P + n2)
+                                                       : (((qo * g.A + tl.a0) * P + n2) * g.S + tl.s0 + l);
+                        out[off] = s0;
+                    }
+                    continue;
+                }
+            }
+            if constexpr (!LANEINV) {
             RegDFT<T, P, true>::run(v);
             if constexpr (!kPow2<P>) {
                 // all-reduce; lane n2 writes the values u = n2 mod G
@@ -344,6 +391,7 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
                     }
                 }
             }
+            }
         }
         __syncthreads();  // the next tile overwrites the buffer the q loop reads
     }
@@ -368,12 +416,13 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
     const int l = (int)threadIdx.x >> lgG;
     const int n2 = (int)threadIdx.x & (G - 1);
     const int64_t total = g.Qin * g.ntiles;
-    // after the reduction lane n2' holds E[bitrev_LP(n2' mod P)]; this lane needs u = (n2 lg) mod P
+    // after the reduction and the cross-lane inverse transform lane u holds E[u]; this lane
+    // needs u = (n2 lg) mod P
     const int u_need = (int)(((int64_t)n2 * ax.lg) % P);
-    int src = 0;
-    for (int s = 0; s < LP; ++s) src |= ((u_need >> s) & 1) << (LP - 1 - s);
     const int lane = (int)threadIdx.x & (kWave - 1);
-    const int src_lane = lane - n2 + src;
+    const int src_lane = lane - n2 + u_need;
+    C<T> wst[LP > 0 ? LP : 1];
+    lane_twiddles<T, LP>(wst, n2, (const C<T>*)ax.tw, M);
     // power-of-two P with G >= P: reduce-scatter and one shuffle; otherwise all-reduce and pick
     const bool scatter = kPow2<P> && G >= P;
     // r(nbar) of the lane's outputs nbar = n2 + G k is r0 + k d (mod P)
@@ -413,15 +462,16 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
             RegDFT<T, P, false>::run(v);
 #pragma unroll
             for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r]);
-            RegDFT<T, P, true>::run(v);
             if (scatter) {
                 reduce_step<T, P, 0>(v, n2, lgG);
                 C<T> s0 = v[0];
                 for (int s = LP; s < lgG; ++s) s0 = cadd<T>(s0, shfl_xor_c<T>(s0, 1 << s));
+                s0 = lane_idft<T, LP>(s0, n2, wst);  // lane n2 < P now holds E[n2]
                 const C<T> e = mk<T>(__shfl(s0.x, src_lane, kWave), __shfl(s0.y, src_lane, kWave));
 #pragma unroll
                 for (int k = 0; k < P; ++k) acc[k] = cfma<T>(acc[k], tf[k << lgG], e);
             } else {
+                RegDFT<T, P, true>::run(v);
                 // the line's P sums go through LDS (the tile buffer is free during the q loop)
                 C<T>* El = B + l * P;
                 if constexpr (kPow2<P>) {
@@ -542,7 +592,9 @@ int ilog2i(int v) {
 template <typename T, int P>
 hipError_t launch_er(const void* in, void* out, const AxisDev& ax, const PassGeom& g, hipStream_t st) {
     const size_t lds = cfp_lds_bytes(sizeof(T) == 8, ax.M, ax.g);
-    auto k = k_ER<T, P>;
+    // power-of-two P with at least P lanes per line: reduce first, inverse transform across lanes
+    constexpr bool pow2 = kPow2<P>;
+    auto k = (pow2 && ax.g >= P) ? k_ER<T, P, pow2> : k_ER<T, P, false>;
     hipError_t e = prep_lds((const void*)k, lds);
     if (e != hipSuccess) return e;
     const int nqc = (g.qn + g.qc - 1) / g.qc;
@@ -619,19 +671,22 @@ hipError_t launch_asr_T(const void* in, void* out, const AxisDev& ax, const Pass
         case 4: return launch_asr<T, 4>(in, out, ax, g, accumulate, rho, st);
         case 8: return launch_asr<T, 8>(in, out, ax, g, accumulate, rho, st);
         case 16: return launch_asr<T, 16>(in, out, ax, g, accumulate, rho, st);
+        case 32: return launch_asr<T, 32>(in, out, ax, g, accumulate, rho, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-// g = 32 keeps 32 complex accumulators per thread and leaves too few threads in flight; the
-// LDS-transform form (k_AS) is faster there.
-bool asr_applicable(int g) { return g == 1 || g == 2 || g == 4 || g == 8 || g == 16; }
+// By default (plan asr_max_g = 16) g = 32 uses the LDS-transform form (k_AS): 32 complex
+// accumulators per thread leave too few threads in flight for the small group counts of 2-D cases.
+bool asr_applicable(int g, int max_g) {
+    return (g == 1 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32) && g <= max_g;
+}
 
 hipError_t launch_pass_asr(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
                            void* rho, hipStream_t st) {
-    if (!asr_applicable(ax.g)) return hipErrorInvalidValue;
+    if (!asr_applicable(ax.g, 32)) return hipErrorInvalidValue;
     return dbl ? launch_asr_T<double>(in, out, ax, g, accumulate, rho, st)
                : launch_asr_T<float>(in, out, ax, g, accumulate, rho, st);
 }

@@ -59,7 +59,8 @@ struct fx_plan {
     void* ff_buf = nullptr;        // far-field comparator: two M-point buffers
     size_t ff_off[3] = {0, 0, 0};
     bool use_cfp = true;           // register E kernel where the pruned length allows it
-    bool use_asr = true;           // register structured accumulate for g <= 32
+    bool use_asr = true;           // register structured accumulate (k_ASR) for g <= asr_max_g
+    int asr_max_g = 16;            // above this the LDS-transform form (k_AS) is used
     int cfp_blocks = 1024;         // register E kernel: target workgroups per launch
     bool use_p2 = true;            // compile-time specialised kernels for power-of-two axes
     int persist = 0;               // >0: tile passes run as persistent grids of persist x CUs workgroups
