@@ -178,10 +178,11 @@ def main():
                     help="c4 only: expand this single realization through one plan (per-pass timing)")
     ap.add_argument("--dtype", default=None, choices=[None, "c64", "c128"])
     ap.add_argument("--schedule", default="paper", choices=["paper", "axis_factorised"])
-    ap.add_argument("--variant", default="free", choices=["free", "spectrum", "pair", "far_field"],
+    ap.add_argument("--variant", default="free", choices=["free", "spectrum", "pair", "far_field", "brute_force"],
                     help="free: free flight (the paper's case); spectrum: a tabulated non-quadratic "
                          "axis-additive spectrum of the same size; pair: positive-P pair psi, psi^+; "
-                         "far_field: the far-field estimate (comparator) on the same output lattice")
+                         "far_field: the far-field estimate (comparator) on the same output lattice; "
+                         "brute_force: the padded-lattice propagation (comparator), same result")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -251,6 +252,9 @@ def main():
     elif args.variant == "far_field":
         def step():
             return plan.far_field(psi)
+    elif args.variant == "brute_force":
+        def step():
+            return plan.brute_force(psi)
     else:
         def step():
             return plan.expand(psi, psi_out=out, rho_out=rho)

@@ -234,6 +234,24 @@ fx_status fx_plan_pair_workspace_size(const fx_plan* plan, size_t* bytes);
 fx_status fx_far_field(fx_plan* plan, const void* psi0, void* amp_out, void* rho_out, void* stream);
 
 /*
+ * Brute-force comparator (the padded-lattice propagation of section 3 that the method
+ * avoids, eq. (Psin) on the vacuum-padded lattice): per axis the field is zero-padded to
+ * N_j = lam_j M_j points (eq. (vacuum)), transformed, multiplied by
+ * exp(i k (abar - a) - i hbar t k^2 / 2m) for the N_j wave numbers of the padded lattice,
+ * transformed back and sampled at every lam_j-th point. By the separability of the free
+ * propagator this equals the full d-dimensional padded-lattice propagation; the result is
+ * the same Psibar as fx_expand up to rounding. Padded lines longer than one workgroup's LDS
+ * take two transform passes each way through a padded buffer of prod(shape) * lam_j
+ * elements. Tables and buffers are built on first use and kept by the plan.
+ * psi0: device input; psi_out (complex) and rho_out (real): device outputs of the same
+ * shape, either may be NULL but not both.
+ * Errors: FX_EINVAL (NULL plan or input, both outputs NULL), FX_EUNSUPPORTED (a plan
+ * built with a caller spectrum, or a padded length with no factorisation into
+ * workgroup-sized transforms), FX_ENOMEM, FX_EDEVICE.
+ */
+fx_status fx_brute_force(fx_plan* plan, const void* psi0, void* psi_out, void* rho_out, void* stream);
+
+/*
  * Ragged batch of problems (ensembles of realizations, section 1): problems
  * with equal shape, spacing, offsets, magnification, flight and precision
  * share one plan and run as one batched pass sequence; different shape

@@ -83,6 +83,7 @@ def _load():
         "fx_expand_pair": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "fx_plan_pair_workspace_size": (ctypes.c_int, [vp, P(ctypes.c_size_t)]),
         "fx_far_field": (ctypes.c_int, [vp, vp, vp, vp, vp]),
+        "fx_brute_force": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "fx_batch_create": (ctypes.c_int, [P(fx_problem), ctypes.c_int32, P(vp)]),
         "fx_batch_destroy": (ctypes.c_int, [vp]),
         "fx_batch_run": (ctypes.c_int, [vp, P(vp), P(vp), P(vp), vp]),

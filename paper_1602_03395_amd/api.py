@@ -214,6 +214,15 @@ class Plan:
         L.check(L.lib.fx_far_field(self._h, _ptr(psi0), _ptr(amp), _ptr(rho), _stream_ptr()), "fx_far_field")
         return amp, rho
 
+    def brute_force(self, psi0: torch.Tensor, want_psi: bool = True):
+        """Padded-lattice propagation (comparator): returns (psi or None, rho), see ``fx_brute_force``."""
+        _check_field(psi0, "psi0")
+        self._check_shape(psi0)
+        out = torch.empty_like(psi0) if want_psi else None
+        rho = torch.empty(psi0.shape, dtype=real_dtype(psi0.dtype), device=psi0.device)
+        L.check(L.lib.fx_brute_force(self._h, _ptr(psi0), _ptr(out), _ptr(rho), _stream_ptr()), "fx_brute_force")
+        return out, rho
+
     def _check_shape(self, x: torch.Tensor):
         if tuple(x.shape) != self.shape:
             raise ValueError(f"tensor shape {tuple(x.shape)} does not match the plan's {self.shape}")

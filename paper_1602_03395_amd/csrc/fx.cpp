@@ -585,6 +585,7 @@ fx_status fx_plan_destroy(fx_plan* p) {
     if (p->dtab) (void)hipFree(p->dtab);
     if (p->ff_tab) (void)hipFree(p->ff_tab);
     if (p->ff_buf) (void)hipFree(p->ff_buf);
+    bf_release(p);
     delete p;
     return FX_OK;
 }

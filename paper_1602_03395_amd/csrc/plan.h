@@ -58,6 +58,7 @@ struct fx_plan {
     void* ff_tab = nullptr;        // far-field comparator: per-axis dense matrices (built on first use)
     void* ff_buf = nullptr;        // far-field comparator: two M-point buffers
     size_t ff_off[3] = {0, 0, 0};
+    void* bf_state = nullptr;      // brute-force comparator: tables and buffers (built on first use)
     bool use_cfp = true;           // register E kernel where the pruned length allows it
     bool use_asr = true;           // register structured accumulate (k_ASR) for g <= asr_max_g
     int asr_max_g = 16;            // above this the LDS-transform form (k_AS) is used
@@ -89,5 +90,6 @@ fx_status run_ops(fx_plan* p, const std::vector<Op>& ops, const void* src, void*
 fx_status run_box(fx_plan* p, const int qb[3], const int qn[3], const void* src, void* dst, int accumulate,
                   void* rho, bool adjoint, hipStream_t st);
 fx_status check_ptr(const void* ptr, const char* what);
+void bf_release(fx_plan* p);
 
 }  // namespace fx
