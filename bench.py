@@ -36,19 +36,34 @@ def pass_cost(p: dict, csize: int, outer_chunks: int = 1):
     """Algorithmic flops and unique bytes of one launch of a pass (roofline model).
 
     Counting convention: complex multiply 6 flops, complex add 2, complex
-    multiply-add 8, a length-N transform 5 N log2 N.
+    multiply-add 8, a length-N transform 5 N log2 N. Per line and magnification index:
+      transform form of E:  6M (premultiply) + 5M log2 M + 6M (chirp) + 2(M - P) (fold)
+                            + 5P log2 P (pruned inverse) + 2P
+      register form of E:   6M (premultiply) + 5M log2 P (g transforms of P points) + 6M (folded
+                            chirp table) + 2M (sum over the g subsequences) + 5P log2 P (inverse)
+      EA adds 8M (the twiddle multiply-accumulate of every output point).
+    A: 8 flops per output and term; AA (two fused accumulates): 16 per input sample plus a
+    g_u x g_v inverse transform per output group.
     """
     kind, M, P, lam = p["kind"], p["M"], p["P"], p["lam"]
     qn = p.get("qn", lam)
     lines = p["Qin"] * p["A"] * p["S"]
     lg = lambda n: math.log2(n) if n > 1 else 0.0
-    e_line = 6 * M + 5 * M * lg(M) + 6 * M + 2 * (M - P) + 5 * P * lg(P) + 2 * P
+    if p.get("reg") and kind in ("E", "EA"):
+        e_line = 6 * M + 5 * M * lg(P) + 6 * M + 2 * M + 5 * P * lg(P)
+    else:
+        e_line = 6 * M + 5 * M * lg(M) + 6 * M + 2 * (M - P) + 5 * P * lg(P) + 2 * P
     if kind in ("E", "EH"):
         flops = lines * qn * e_line
         byts = (lines * M + lines * qn * P) * csize
     elif kind in ("EA", "EAH"):
         flops = lines * qn * (e_line + 8 * M) + lines * M * 2
         byts = 2 * lines * M * csize
+    elif kind == "AA":
+        nin = p["O"] * p["qn2"] * qn * p["X"] * P * p["Y"] * p["P2"] * p["Z"]
+        nout = p["O"] * p["X"] * M * p["Y"] * p["M2"] * p["Z"]
+        flops = nin * 16 + nout * 5 * lg(p["g"] * p["g2"])
+        byts = (nin + nout) * csize
     else:  # A, AH
         outs = p["Qin"] * p["A"] * M * p["S"]
         flops = outs * 8 * qn

@@ -234,6 +234,35 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
         for (int i = k - 1; i >= 1; --i) do_E(p->act[i]);
         do_EA(p->act[0]);
         for (int i = 1; i < k; ++i) do_A(p->act[i]);
+        // fuse the last two accumulate passes (axes u < v) into one 2-D structured accumulate
+        const size_t n = ops.size();
+        if (p->use_aa && n >= 2 && ops[n - 2].kind == Kind::A && ops[n - 1].kind == Kind::A) {
+            const Op& ou = ops[n - 2];
+            const Op& ov = ops[n - 1];
+            const int u = ou.axis, v = ov.axis;
+            const AxisDev& au = p->ax[u];
+            const AxisDev& av = p->ax[v];
+            if (u < v && aa_applicable(p->dbl, au.g, av.g) &&
+                (int64_t)aa_lds_bytes(p->dbl, au.g, av.g) <= lds_limit_bytes()) {
+                Op f = ou;
+                f.kind = Kind::AA;
+                f.axis2 = v;
+                f.out_elems = ov.out_elems;
+                AAGeom& a = f.aa;
+                a.O = ov.g.Qin;
+                a.qn_u = ou.g.qn;
+                a.qb_u = ou.g.qb;
+                a.qn_v = ov.g.qn;
+                a.qb_v = ov.g.qb;
+                // lengths of the other axes as the fused pass sees them (u and v excluded)
+                a.X = ou.g.A;                               // axes before u
+                a.Z = ov.g.S;                               // axes after v
+                a.Y = ou.g.S / ((int64_t)av.P * a.Z);       // axes between u and v
+                a.tsg = aa_tile_groups(au.g, av.g);
+                ops.pop_back();
+                ops.back() = f;
+            }
+        }
     } else {
         for (int i = k - 1; i >= 1; --i) do_AH(p->act[i]);
         do_EAH(p->act[0]);
@@ -348,8 +377,11 @@ fx_status run_ops(fx_plan* p, const std::vector<Op>& ops, const void* src, void*
             }
             FX_TRY_HIP(hipEventRecord(ea, st));
         }
-        hipError_t e = launch_pass(o.kind, p->dbl, cur, out, p->ax[o.axis], o.g, last ? accumulate : 0,
-                                   last ? rho : nullptr, st);
+        hipError_t e = (o.kind == Kind::AA)
+                           ? launch_pass_aa(p->dbl, cur, out, p->ax[o.axis], p->ax[o.axis2], o.aa,
+                                            last ? accumulate : 0, last ? rho : nullptr, st)
+                           : launch_pass(o.kind, p->dbl, cur, out, p->ax[o.axis], o.g, last ? accumulate : 0,
+                                         last ? rho : nullptr, st);
         if (p->timing) {
             FX_TRY_HIP(hipEventRecord(eb, st));
             p->pending.push_back({(int)i, ea, eb});
@@ -542,6 +574,7 @@ fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_pla
     if (const char* e = std::getenv("FX_NO_P2")) p->use_p2 = (e[0] != '1');
     if (const char* e = std::getenv("FX_NO_CFP")) p->use_cfp = (e[0] != '1');
     if (const char* e = std::getenv("FX_NO_ASR")) p->use_asr = (e[0] != '1');
+    if (const char* e = std::getenv("FX_AA")) p->use_aa = (e[0] == '1');
     if (const char* e = std::getenv("FX_ASR_MAXG")) p->asr_max_g = std::max(1, std::atoi(e));
     p->cfp_blocks = 2 * num_cus();
     if (const char* e = std::getenv("FX_CFP_BLOCKS")) p->cfp_blocks = std::max(1, std::atoi(e));
@@ -804,17 +837,28 @@ fx_status fx_plan_describe(const fx_plan* p, char* buf, size_t len) {
         s += p->spectrum[3 - p->ndim + j] ? "\"table\"" : "\"free\"";
     }
     s += "],\"passes\":[";
-    static const char* names[] = {"E", "A", "EA", "EH", "AH", "EAH"};
+    static const char* names[] = {"E", "A", "EA", "EH", "AH", "EAH", "AA"};
     for (size_t i = 0; i < ops.size(); ++i) {
         const Op& o = ops[i];
         const AxisDev& a = p->ax[o.axis];
         char tmp[256];
         std::snprintf(tmp, sizeof(tmp),
                       "%s{\"kind\":\"%s\",\"axis\":%d,\"M\":%d,\"P\":%d,\"lam\":%d,\"qn\":%d,\"Qin\":%lld,"
-                      "\"A\":%lld,\"S\":%lld,\"TS\":%d}",
+                      "\"A\":%lld,\"S\":%lld,\"TS\":%d,\"reg\":%d",
                       i ? "," : "", names[(int)o.kind], o.axis - (3 - p->ndim), a.M, a.P, a.lam, o.g.qn,
-                      (long long)o.g.Qin, (long long)o.g.A, (long long)o.g.S, o.g.TS);
+                      (long long)o.g.Qin, (long long)o.g.A, (long long)o.g.S, o.g.TS,
+                      (o.g.qc > 0 || o.g.reg_a) ? 1 : 0);
         s += tmp;
+        if (o.kind == Kind::AA) {
+            const AxisDev& b = p->ax[o.axis2];
+            std::snprintf(tmp, sizeof(tmp),
+                          ",\"axis2\":%d,\"M2\":%d,\"P2\":%d,\"lam2\":%d,\"qn2\":%d,\"O\":%lld,\"X\":%lld,"
+                          "\"Y\":%lld,\"Z\":%lld,\"g\":%d,\"g2\":%d",
+                          o.axis2 - (3 - p->ndim), b.M, b.P, b.lam, o.aa.qn_v, (long long)o.aa.O,
+                          (long long)o.aa.X, (long long)o.aa.Y, (long long)o.aa.Z, a.g, b.g);
+            s += tmp;
+        }
+        s += "}";
     }
     s += "]}";
     std::snprintf(buf, len, "%s", s.c_str());

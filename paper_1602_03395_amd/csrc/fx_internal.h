@@ -64,7 +64,7 @@ struct PassGeom {
     bool reg_a = false;  // A pass: register structured accumulate
 };
 
-enum class Kind { E, A, EA, EH, AH, EAH };
+enum class Kind { E, A, EA, EH, AH, EAH, AA };
 
 // Groups per tile of the structured accumulate (A via a g-point transform over q mod g).
 int as_tile_groups(int g);
@@ -124,6 +124,18 @@ int cfp_tile_lines(int g);
 size_t cfp_lds_bytes(bool dbl, int M, int g);
 hipError_t launch_pass_cfp(Kind kind, bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g,
                            int accumulate, void* rho, hipStream_t st);
+// The last two accumulate passes of the paper schedule fused (axes u < v): input
+// [O][qn_v][qn_u][X][P_u][Y][P_v][Z] -> output [O][X][M_u][Y][M_v][Z].
+struct AAGeom {
+    int64_t O = 1, X = 1, Y = 1, Z = 1;
+    int qn_u = 1, qb_u = 0, qn_v = 1, qb_v = 0;
+    int tsg = 1;  // groups per workgroup
+};
+bool aa_applicable(bool dbl, int gu, int gv);
+int aa_tile_groups(int gu, int gv);
+size_t aa_lds_bytes(bool dbl, int gu, int gv);
+hipError_t launch_pass_aa(bool dbl, const void* in, void* out, const AxisDev& au, const AxisDev& av, const AAGeom& g,
+                          int accumulate, void* rho, hipStream_t st);
 // Structured accumulate (A) with one thread per output group and register accumulators (g <= 32).
 bool asr_applicable(int g, int max_g);
 hipError_t launch_pass_asr(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,

@@ -571,6 +571,98 @@ __global__ __launch_bounds__(kThreads) void k_ASR(const C<T>* __restrict__ in, C
     }
 }
 
+// The last two accumulate passes (axes u < v) in one: for the group (o, x, n0_u, y, n0_v, z) the
+// outputs nbar_u = n0_u + P_u c_u, nbar_v = n0_v + P_v c_v read one input sample per (q_u, q_v),
+// and the twiddles (presf) of both axes advance by q c / g per step P, so
+//   out[.., nbar_u, .., nbar_v, ..] = sum_{j_u, j_v} exp(2 pi i (q_u c_u / g_u + q_v c_v / g_v)) H[j_u][j_v],
+//   H[j_u][j_v] = sum_{q_u = j_u, q_v = j_v mod g} Tf_u[q_u][n0_u] Tf_v[q_v][n0_v] in[q_v][q_u][r_u][r_v],
+// a g_u x g_v inverse transform per group, done in LDS: rows over j_u, a transpose, rows over j_v.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_AA(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev au,
+                                                 AxisDev av, AAGeom g, int accumulate, T* __restrict__ rho) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int gu = au.g, gv = av.g, Pu = au.P, Pv = av.P, Mu = au.M, Mv = av.M;
+    const int GG = gu * gv;
+    const int TSG = g.tsg;
+    C<T>* H0 = (C<T>*)smem;
+    C<T>* H1 = H0 + TSG * GG;
+    C<T>* twu = H1 + TSG * GG;  // exp(-2 pi i k / g_u)
+    C<T>* twv = twu + gu;       // exp(-2 pi i k / g_v)
+    const C<T>* tu = (const C<T>*)au.tw;
+    const C<T>* tv = (const C<T>*)av.tw;
+    for (int k = threadIdx.x; k < gu; k += blockDim.x) twu[k] = tu[k * Pu];
+    for (int k = threadIdx.x; k < gv; k += blockDim.x) twv[k] = tv[k * Pv];
+    __syncthreads();
+    const C<T>* Tfu = (const C<T>*)au.Tf;
+    const C<T>* Tfv = (const C<T>*)av.Tf;
+    const int64_t X = g.X, Y = g.Y, Z = g.Z;
+    const int64_t ngroups = g.O * X * Pu * Y * Pv * Z;
+    const int64_t ntiles = (ngroups + TSG - 1) / TSG;
+    const int qru = g.qb_u % gu, qrv = g.qb_v % gv;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t base = t * TSG;
+        const int nt = (int)min((int64_t)TSG, ngroups - base);
+        for (int it = threadIdx.x; it < nt * GG; it += blockDim.x) {
+            const int p = it % nt;
+            const int rest = it / nt;
+            const int ju = rest % gu, jv = rest / gu;
+            int64_t gi = base + p;
+            const int64_t z = gi % Z; gi /= Z;
+            const int n0v = (int)(gi % Pv); gi /= Pv;
+            const int64_t y = gi % Y; gi /= Y;
+            const int n0u = (int)(gi % Pu); gi /= Pu;
+            const int64_t x = gi % X;
+            const int64_t o = gi / X;
+            const int ru = (int)(((int64_t)n0u * au.lg) % Pu);
+            const int rv = (int)(((int64_t)n0v * av.lg) % Pv);
+            C<T> acc = mk<T>(0, 0);
+            for (int iv = jv; iv < g.qn_v; iv += gv) {
+                const int qv = g.qb_v + iv;
+                const C<T> fv = Tfv[(int64_t)qv * Mv + n0v];
+                C<T> su = mk<T>(0, 0);
+                for (int iu = ju; iu < g.qn_u; iu += gu) {
+                    const int qu = g.qb_u + iu;
+                    const int64_t slice = (o * g.qn_v + iv) * g.qn_u + iu;
+                    const int64_t a = ((((slice * X + x) * Pu + ru) * Y + y) * Pv + rv) * Z + z;
+                    su = cfma<T>(su, Tfu[(int64_t)qu * Mu + n0u], in[a]);
+                }
+                acc = cfma<T>(acc, fv, su);
+            }
+            H0[(p * gv + jv) * gu + ju] = acc;
+        }
+        __syncthreads();
+        C<T>* R1 = lds_fft<T>(H0, H1, nt * gv, gu, au.fg, twu, 1, true);  // rows over j_u
+        C<T>* Tb = (R1 == H0) ? H1 : H0;
+        for (int e = threadIdx.x; e < nt * GG; e += blockDim.x) {
+            const int cu = e % gu, r = e / gu;  // r = p * gv + jv
+            const int jv = r % gv, p = r / gv;
+            Tb[(p * gu + cu) * gv + jv] = R1[e];
+        }
+        __syncthreads();
+        C<T>* R2 = lds_fft<T>(Tb, R1, nt * gu, gv, av.fg, twv, 1, true);  // rows over j_v
+        for (int e = threadIdx.x; e < nt * GG; e += blockDim.x) {
+            const int p = e % nt;
+            const int rest = e / nt;
+            const int cv = rest % gv, cu = rest / gv;
+            int64_t gi = base + p;
+            const int64_t z = gi % Z; gi /= Z;
+            const int n0v = (int)(gi % Pv); gi /= Pv;
+            const int64_t y = gi % Y; gi /= Y;
+            const int n0u = (int)(gi % Pu); gi /= Pu;
+            const int64_t x = gi % X;
+            const int64_t o = gi / X;
+            C<T> v = R2[(p * gu + cu) * gv + cv];
+            if (qru != 0) v = cmulc<T>(v, tu[((qru * cu) % gu) * Pu]);  // exp(+2 pi i qb_u c_u / g_u)
+            if (qrv != 0) v = cmulc<T>(v, tv[((qrv * cv) % gv) * Pv]);  // exp(+2 pi i qb_v c_v / g_v)
+            const int64_t oa = ((((o * X + x) * Mu + n0u + (int64_t)Pu * cu) * Y + y) * Mv + n0v + (int64_t)Pv * cv) * Z + z;
+            if (accumulate) v = cadd<T>(v, out[oa]);
+            out[oa] = v;
+            if (rho) rho[oa] = v.x * v.x + v.y * v.y;
+        }
+        __syncthreads();
+    }
+}
+
 hipError_t prep_lds(const void* k, size_t lds) {
     static std::mutex mu;
     static std::set<const void*> done;
@@ -689,6 +781,34 @@ hipError_t launch_pass_asr(bool dbl, const void* in, void* out, const AxisDev& a
     if (!asr_applicable(ax.g, 32)) return hipErrorInvalidValue;
     return dbl ? launch_asr_T<double>(in, out, ax, g, accumulate, rho, st)
                : launch_asr_T<float>(in, out, ax, g, accumulate, rho, st);
+}
+
+bool aa_applicable(bool dbl, int gu, int gv) {
+    (void)dbl;
+    return gu >= 1 && gv >= 1 && gu * gv <= 1024;
+}
+
+int aa_tile_groups(int gu, int gv) { return std::max(1, 1024 / (gu * gv)); }
+
+size_t aa_lds_bytes(bool dbl, int gu, int gv) {
+    const size_t tsg = (size_t)aa_tile_groups(gu, gv);
+    return (2 * tsg * gu * gv + gu + gv) * (dbl ? 16 : 8);
+}
+
+hipError_t launch_pass_aa(bool dbl, const void* in, void* out, const AxisDev& au, const AxisDev& av, const AAGeom& g,
+                          int accumulate, void* rho, hipStream_t st) {
+    if (!aa_applicable(dbl, au.g, av.g) || g.tsg != aa_tile_groups(au.g, av.g)) return hipErrorInvalidValue;
+    const int64_t ngroups = g.O * g.X * au.P * g.Y * av.P * g.Z;
+    const int64_t tiles = (ngroups + g.tsg - 1) / g.tsg;
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, 1 << 20));
+    const size_t lds = aa_lds_bytes(dbl, au.g, av.g);
+    if (dbl)
+        hipLaunchKernelGGL(k_AA<double>, dim3(blocks), dim3(kThreads), lds, st, (const double2*)in, (double2*)out, au,
+                           av, g, accumulate, (double*)rho);
+    else
+        hipLaunchKernelGGL(k_AA<float>, dim3(blocks), dim3(kThreads), lds, st, (const float2*)in, (float2*)out, au, av,
+                           g, accumulate, (float*)rho);
+    return hipGetLastError();
 }
 
 bool cfp_applicable(Kind kind, bool dbl, int M, int g) {

@@ -23,6 +23,8 @@ struct Op {
     PassGeom g;
     int64_t in_elems;  // per op, elements read tensor size
     int64_t out_elems;
+    int axis2 = -1;    // AA: the second (later) axis
+    AAGeom aa;         // AA: geometry of the fused pair
 };
 
 constexpr int64_t kMaxAxis = 4096;
@@ -61,6 +63,8 @@ struct fx_plan {
     void* bf_state = nullptr;      // brute-force comparator: tables and buffers (built on first use)
     bool use_cfp = true;           // register E kernel where the pruned length allows it
     bool use_asr = true;           // register structured accumulate (k_ASR) for g <= asr_max_g
+    bool use_aa = false;           // fuse the last two accumulate passes (FX_AA=1; slower on the
+                                   // measured workloads, kept as an option)
     int asr_max_g = 16;            // above this the LDS-transform form (k_AS) is used
     int cfp_blocks = 1024;         // register E kernel: target workgroups per launch
     bool use_p2 = true;            // compile-time specialised kernels for power-of-two axes

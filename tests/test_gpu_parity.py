@@ -271,3 +271,21 @@ def test_batch_rejects_bad_arguments(fx):
     b = fx.Batch([dict(shape=(8,), dx=1.0, lam=2, t=1.0)], dtype=torch.complex128)
     with pytest.raises(ValueError):
         b.run([torch.zeros(9, dtype=torch.complex128, device="cuda")])
+
+
+@pytest.mark.parametrize("case", [5, 7, 9, 15, 19, 22])
+def test_fused_two_axis_accumulate_fp64(fx, case, monkeypatch):
+    # the optional fused form of the last two accumulate passes (FX_AA=1), read at plan creation
+    monkeypatch.setenv("FX_AA", "1")
+    shape, lam, dx, t, moh, shift = CASES[case]
+    say("fused accumulate", shape, lam)
+    psi_np = workloads.random_field(shape, 900 + case)
+    a, abar = oracle.default_offsets(shape, dx, lam)
+    abar = abar + shift * np.asarray(dx)
+    ref = oracle.expand(psi_np, dx, moh, t, lam, a, abar)
+    plan = fx.Plan(shape, dx, moh, t, lam, list(a), list(abar), torch.complex128)
+    assert '"AA"' in plan.describe() or len(shape) == 1
+    out, rho = plan.expand(torch.from_numpy(psi_np).cuda())
+    torch.cuda.synchronize()
+    assert rel(out.cpu().numpy(), ref) <= TOL64
+    assert rel(rho.cpu().numpy(), oracle.density(ref)) <= TOL64
