@@ -154,9 +154,9 @@ __global__ __launch_bounds__(kThreads) void k_AS(const C<T>* __restrict__ in, C<
     const int PS = P * S;
     C<T>* H0 = (C<T>*)smem;
     C<T>* H1 = H0 + TSL * G;
-    C<T>* tw = H1 + TSL * G;
+    C<T>* tw = H1 + TSL * G;  // exp(-2 pi i k / g), k < g
     const C<T>* twg = (const C<T>*)ax.tw;
-    for (int i = threadIdx.x; i < M; i += blockDim.x) tw[i] = twg[i];
+    for (int i = threadIdx.x; i < G; i += blockDim.x) tw[i] = twg[(int64_t)i * P];
     __syncthreads();
     const C<T>* Tf = (const C<T>*)ax.Tf;
     const int ngroups = (int)(g.Qin * g.A * PS);  // < 2^31, checked on the host
@@ -169,29 +169,50 @@ __global__ __launch_bounds__(kThreads) void k_AS(const C<T>* __restrict__ in, C<
         const int nt = min(TSL, ngroups - base);
         // work items (residue qr, group p): consecutive threads take consecutive groups
         const FDiv fnt(nt);
-        for (int it = threadIdx.x; it < nt * G; it += blockDim.x) {
-            const int qr = fnt.div(it);
-            const int p = it - qr * nt;
-            const int gi = base + p;
-            const int row = fPS.div(gi);
-            const int rem = gi - row * PS;
-            const int n0 = fS.div(rem);
-            const int s = rem - n0 * S;
-            const int qo = fA.div(row);
-            const int a = row - qo * (int)g.A;
-            const int r = fP.mod(n0 * ax.lg);
-            const C<T>* src = in + (((int64_t)qo * g.qn) * g.A + a) * (int64_t)PS + r * S + s;
-            const C<T>* tf = Tf + g.qb * M + n0;
-            int i0 = qr - q0r;  // first i with (qb + i) mod G == qr
-            if (i0 < 0) i0 += G;
-            C<T> acc = mk<T>(0, 0);
-            for (int i = i0; i < g.qn; i += G) acc = cfma<T>(acc, tf[i * M], src[i * step]);
-            H0[p * G + qr] = acc;
+        // two work items per thread and step, their loads issued together
+        for (int it0 = threadIdx.x; it0 < nt * G; it0 += 2 * blockDim.x) {
+            const C<T>* src[2];
+            const C<T>* tf[2];
+            int i0[2], slot[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int it = it0 + h * (int)blockDim.x;
+                slot[h] = -1;
+                i0[h] = g.qn;  // no terms
+                src[h] = in;
+                tf[h] = Tf;
+                if (it < nt * G) {
+                    const int qr = fnt.div(it);
+                    const int p = it - qr * nt;
+                    const int gi = base + p;
+                    const int row = fPS.div(gi);
+                    const int rem = gi - row * PS;
+                    const int n0 = fS.div(rem);
+                    const int s = rem - n0 * S;
+                    const int qo = fA.div(row);
+                    const int a = row - qo * (int)g.A;
+                    const int r = fP.mod(n0 * ax.lg);
+                    src[h] = in + (((int64_t)qo * g.qn) * g.A + a) * (int64_t)PS + r * S + s;
+                    tf[h] = Tf + g.qb * M + n0;
+                    int f = qr - q0r;  // first i with (qb + i) mod G == qr
+                    if (f < 0) f += G;
+                    i0[h] = f;
+                    slot[h] = p * G + qr;
+                }
+            }
+            C<T> acc0 = mk<T>(0, 0), acc1 = mk<T>(0, 0);
+            for (int d = 0; i0[0] + d < g.qn || i0[1] + d < g.qn; d += G) {
+                const int ia = i0[0] + d, ib = i0[1] + d;
+                if (ia < g.qn) acc0 = cfma<T>(acc0, tf[0][ia * M], src[0][ia * step]);
+                if (ib < g.qn) acc1 = cfma<T>(acc1, tf[1][ib * M], src[1][ib * step]);
+            }
+            if (slot[0] >= 0) H0[slot[0]] = acc0;
+            if (slot[1] >= 0) H0[slot[1]] = acc1;
         }
         for (int p = nt + threadIdx.x; p < TSL; p += blockDim.x)
             for (int qr = 0; qr < G; ++qr) H0[p * G + qr] = mk<T>(0, 0);
         __syncthreads();
-        C<T>* R = lds_fft<T>(H0, H1, TSL, G, ax.fg, tw, M / G, true);
+        C<T>* R = lds_fft<T>(H0, H1, TSL, G, ax.fg, tw, 1, true);
         for (int e = threadIdx.x; e < nt * G; e += blockDim.x) {
             const int c = fnt.div(e);
             const int p = e - c * nt;

@@ -265,6 +265,34 @@ __device__ __forceinline__ void reduce_all(C<T>* v, int lgG) {
 
 template <int P> constexpr bool kPow2 = (P & (P - 1)) == 0;
 
+// The tile of TS = kThreads / g lines of M = g P points into LDS: exactly P elements per thread,
+// loaded in chunks of CH whose loads are all issued before their stores, so that CH latencies
+// overlap (CH trades the overlap against the registers the loads hold).
+template <typename T, int P, int CH>
+__device__ __forceinline__ void load_tile(const C<T>* __restrict__ in, C<T>* B, const PassGeom& g, const Tile& tl,
+                                          int64_t qi, int M, const FDiv& fdM) {
+    const int cnt = tl.nl * M;
+#pragma unroll
+    for (int k0 = 0; k0 < P; k0 += CH) {
+        C<T> v[CH];
+        int dst[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int e = (int)threadIdx.x + (k0 + k) * kThreads;
+            dst[k] = -1;
+            if (k0 + k < P && e < cnt) {
+                int ll, n;
+                const int64_t off = tile_elem(g, tl, qi, M, fdM, e, ll, n);
+                v[k] = in[off];
+                dst[k] = ll * M + n;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+            if (dst[k] >= 0) B[dst[k]] = v[k];
+    }
+}
+
 // wst[s] = exp(+2 pi i (n2 mod 2^s) / 2^(s+1)) = conj(tw[(n2 mod 2^s) M / 2^(s+1)]), tw[k] = exp(-2 pi i k / M)
 template <typename T, int LP>
 __device__ __forceinline__ void lane_twiddles(C<T>* wst, int n2, const C<T>* tw, int M) {
@@ -322,11 +350,7 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
         const int ci = (int)(rest - tt * nqc);
         const Tile tl = decode_tile(g, tt);
         const FDiv fdM = tile_div(g, tl, M);
-        for (int e = threadIdx.x; e < tl.nl * M; e += kThreads) {
-            int ll, n;
-            const int64_t off = tile_elem(g, tl, qi, M, fdM, e, ll, n);
-            B[ll * M + n] = in[off];
-        }
+        load_tile<T, P, (sizeof(T) == 4 ? P : 1)>(in, B, g, tl, qi, M, fdM);
         __syncthreads();
         const bool live = l < tl.nl;
         const C<T>* x = B + l * M + n2;  // the line stays in LDS for every q (rows past nl are unused)
@@ -438,11 +462,7 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
         const int64_t tt = bid - qi * g.ntiles;
         const Tile tl = decode_tile(g, tt);
         const FDiv fdM = tile_div(g, tl, M);
-        for (int e = threadIdx.x; e < tl.nl * M; e += kThreads) {
-            int ll, n;
-            const int64_t off = tile_elem(g, tl, qi, M, fdM, e, ll, n);
-            B[ll * M + n] = in[off];
-        }
+        load_tile<T, P, 1>(in, B, g, tl, qi, M, fdM);  // x stays in registers: keep the load phase lean
         __syncthreads();
         const bool live = l < tl.nl;
         C<T> x[P], acc[P];
@@ -663,6 +683,97 @@ __global__ __launch_bounds__(kThreads) void k_AA(const C<T>* __restrict__ in, C<
     }
 }
 
+// Structured accumulate for g = 8K (K = 2, 4, 8 lanes per group): lane k of a group keeps the
+// eight residues j = k + K m (m < 8). With c = c1 + 8 c2 the g-point inverse transform splits as
+//   out[c1 + 8 c2] = sum_k exp(2 pi i k c2 / K) exp(2 pi i k c1 / g) sum_m exp(2 pi i m c1 / 8) H[k + K m],
+// an 8-point transform in registers, a twiddle, and a K-point transform across the K lanes
+// (radix-2 decimation in frequency; lane k ends with c2 = bitrev(k)).
+template <typename T, int K>
+__global__ __launch_bounds__(kThreads) void k_ASK(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
+                                                  PassGeom g, int accumulate, T* __restrict__ rho) {
+    constexpr int G = 8 * K;
+    constexpr int LK = (K == 8) ? 3 : (K == 4) ? 2 : 1;
+    const int M = ax.M, P = ax.P;
+    const int64_t S = g.S;
+    const int64_t PS = (int64_t)P * S;
+    const int64_t ngroups = g.Qin * g.A * PS;
+    const int64_t step = g.A * PS;
+    const C<T>* Tf = (const C<T>*)ax.Tf;
+    const C<T>* twg = (const C<T>*)ax.tw;
+    const int k = (int)(threadIdx.x & (K - 1));  // the grid stride is a multiple of K
+    int kr = 0;                                  // bitrev_LK(k)
+    for (int b = 0; b < LK; ++b) kr |= ((k >> b) & 1) << (LK - 1 - b);
+    C<T> w1[8];  // exp(2 pi i k c1 / g)
+#pragma unroll
+    for (int c1 = 0; c1 < 8; ++c1) {
+        const C<T> t = twg[((k * c1) % G) * P];
+        w1[c1] = mk<T>(t.x, -t.y);
+    }
+    const int qbr = g.qb % G;
+    const int64_t nthreads = ngroups * K;
+    for (int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gt < nthreads;
+         gt += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t gi = gt / K;
+        const int64_t row = gi / PS;
+        const int64_t rem = gi - row * PS;
+        const int n0 = (int)(rem / S);
+        const int64_t s = rem - (int64_t)n0 * S;
+        const int64_t qo = row / g.A;
+        const int64_t a = row - qo * g.A;
+        const int r = (int)(((int64_t)n0 * ax.lg) % P);
+        const C<T>* src = in + (qo * g.qn * g.A + a) * PS + (int64_t)r * S + s;
+        const C<T>* tf = Tf + (int64_t)g.qb * M + n0;
+        C<T> h[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) h[m] = mk<T>(0, 0);
+        int i0 = 0;
+        for (; i0 + G <= g.qn; i0 += G) {
+            C<T> av[8], bv[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int i = i0 + k + K * m;
+                av[m] = tf[(int64_t)i * M];
+                bv[m] = src[(int64_t)i * step];
+            }
+#pragma unroll
+            for (int m = 0; m < 8; ++m) h[m] = cfma<T>(h[m], av[m], bv[m]);
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int i = i0 + k + K * m;
+            if (i < g.qn) h[m] = cfma<T>(h[m], tf[(int64_t)i * M], src[(int64_t)i * step]);
+        }
+        RegDFT<T, 8, true>::run(h);
+#pragma unroll
+        for (int c1 = 1; c1 < 8; ++c1) h[c1] = cmul<T>(h[c1], w1[c1]);
+        // K-point inverse transform across the lanes, decimation in frequency
+#pragma unroll
+        for (int st = LK - 1; st >= 0; --st) {
+            const int hh = 1 << st;
+            const bool upper = (k & hh) != 0;
+            const int jj = k & (hh - 1);
+            // exp(+2 pi i jj / (2 hh)) = conj(tw[jj * M / (2 hh)])
+            const C<T> t = twg[(int64_t)jj * (M / (2 * hh))];
+            const C<T> om = mk<T>(t.x, -t.y);
+#pragma unroll
+            for (int c1 = 0; c1 < 8; ++c1) {
+                const C<T> b = shfl_xor_c<T>(h[c1], hh);
+                h[c1] = upper ? cmul<T>(csub<T>(b, h[c1]), om) : cadd<T>(h[c1], b);
+            }
+        }
+#pragma unroll
+        for (int c1 = 0; c1 < 8; ++c1) {
+            const int c = c1 + 8 * kr;
+            C<T> v = h[c1];
+            if (qbr != 0) v = cmulc<T>(v, twg[((qbr * c) % G) * P]);  // exp(+2 pi i qb c / g)
+            const int64_t o = (row * M + n0 + (int64_t)P * c) * S + s;
+            if (accumulate) v = cadd<T>(v, out[o]);
+            out[o] = v;
+            if (rho) rho[o] = v.x * v.x + v.y * v.y;
+        }
+    }
+}
+
 hipError_t prep_lds(const void* k, size_t lds) {
     static std::mutex mu;
     static std::set<const void*> done;
@@ -754,31 +865,42 @@ hipError_t launch_asr(const void* in, void* out, const AxisDev& ax, const PassGe
     return hipGetLastError();
 }
 
+template <typename T, int K>
+hipError_t launch_ask(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
+                      hipStream_t st) {
+    const int64_t nthreads = g.Qin * g.A * (int64_t)ax.P * g.S * K;
+    int64_t blocks = (nthreads + kThreads - 1) / kThreads;
+    if (blocks > (1 << 20)) blocks = 1 << 20;
+    hipLaunchKernelGGL((k_ASK<T, K>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), 0, st,
+                       (const C<T>*)in, (C<T>*)out, ax, g, accumulate, (T*)rho);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_asr_T(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
                         hipStream_t st) {
     switch (ax.g) {
+        case 64: return launch_ask<T, 8>(in, out, ax, g, accumulate, rho, st);
         case 1: return launch_asr<T, 1>(in, out, ax, g, accumulate, rho, st);
         case 2: return launch_asr<T, 2>(in, out, ax, g, accumulate, rho, st);
         case 4: return launch_asr<T, 4>(in, out, ax, g, accumulate, rho, st);
         case 8: return launch_asr<T, 8>(in, out, ax, g, accumulate, rho, st);
-        case 16: return launch_asr<T, 16>(in, out, ax, g, accumulate, rho, st);
-        case 32: return launch_asr<T, 32>(in, out, ax, g, accumulate, rho, st);
+        case 16: return launch_ask<T, 2>(in, out, ax, g, accumulate, rho, st);
+        case 32: return launch_ask<T, 4>(in, out, ax, g, accumulate, rho, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-// By default (plan asr_max_g = 16) g = 32 uses the LDS-transform form (k_AS): 32 complex
-// accumulators per thread leave too few threads in flight for the small group counts of 2-D cases.
+// g <= 8: one thread per group (k_ASR); g = 16, 32, 64: K = g / 8 lanes per group (k_ASK).
 bool asr_applicable(int g, int max_g) {
-    return (g == 1 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32) && g <= max_g;
+    return (g == 1 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64) && g <= max_g;
 }
 
 hipError_t launch_pass_asr(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
                            void* rho, hipStream_t st) {
-    if (!asr_applicable(ax.g, 32)) return hipErrorInvalidValue;
+    if (!asr_applicable(ax.g, 64)) return hipErrorInvalidValue;
     return dbl ? launch_asr_T<double>(in, out, ax, g, accumulate, rho, st)
                : launch_asr_T<float>(in, out, ax, g, accumulate, rho, st);
 }

@@ -65,7 +65,7 @@ struct fx_plan {
     bool use_asr = true;           // register structured accumulate (k_ASR) for g <= asr_max_g
     bool use_aa = false;           // fuse the last two accumulate passes (FX_AA=1; slower on the
                                    // measured workloads, kept as an option)
-    int asr_max_g = 16;            // above this the LDS-transform form (k_AS) is used
+    int asr_max_g = 64;            // above this the LDS-transform form (k_AS) is used
     int cfp_blocks = 1024;         // register E kernel: target workgroups per launch
     bool use_p2 = true;            // compile-time specialised kernels for power-of-two axes
     int persist = 0;               // >0: tile passes run as persistent grids of persist x CUs workgroups
