@@ -334,8 +334,10 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
     const int n2 = (int)threadIdx.x & (G - 1);
     const int qc = g.qc;
     const int nqc = (g.qn + qc - 1) / qc;
-    const int64_t per_slice = g.ntiles * nqc;
-    const int64_t total = g.Qin * per_slice;
+    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs (id mod 8), so the
+    // nqc workgroups of one tile get ids of equal residue mod 8 and share that XCD's L2 copy of it
+    const int64_t ntl = g.Qin * g.ntiles;
+    const int64_t total = ((ntl + 7) / 8) * 8 * nqc;
     const int lk = (lgG < LP) ? lgG : LP;     // reduce-scatter steps
     const int cnt = P >> lk;                  // values a lane holds afterwards
     int base = 0;
@@ -344,10 +346,12 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
     C<T> wst[LP > 0 ? LP : 1];
     lane_twiddles<T, LP>(wst, n2, (const C<T>*)ax.tw, M);
     for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
-        const int64_t qi = bid / per_slice;
-        const int64_t rest = bid - qi * per_slice;
-        const int64_t tt = rest / nqc;
-        const int ci = (int)(rest - tt * nqc);
+        const int64_t rr = bid >> 3;
+        const int ci = (int)(rr % nqc);
+        const int64_t tile = (rr / nqc) * 8 + (bid & 7);
+        if (tile >= ntl) continue;  // uniform over the workgroup
+        const int64_t qi = tile / g.ntiles;
+        const int64_t tt = tile - qi * g.ntiles;
         const Tile tl = decode_tile(g, tt);
         const FDiv fdM = tile_div(g, tl, M);
         load_tile<T, P, (sizeof(T) == 4 ? P : 1)>(in, B, g, tl, qi, M, fdM);
@@ -801,8 +805,8 @@ hipError_t launch_er(const void* in, void* out, const AxisDev& ax, const PassGeo
     hipError_t e = prep_lds((const void*)k, lds);
     if (e != hipSuccess) return e;
     const int nqc = (g.qn + g.qc - 1) / g.qc;
-    int64_t blocks = g.Qin * g.ntiles * nqc;
-    if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = g.max_blocks;
+    int64_t blocks = ((g.Qin * g.ntiles + 7) / 8) * 8 * nqc;  // the kernel's XCD-aware order
+    if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = (g.max_blocks + 7) / 8 * 8;
     if (blocks > (1 << 22)) blocks = 1 << 22;
     hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), lds, st, (const C<T>*)in,
                        (C<T>*)out, ax, g, ilog2i(ax.g), (const C<T>*)ax.TA, (const C<T>*)ax.HT);
