@@ -721,8 +721,9 @@ size_t pass_lds_bytes(Kind kind, bool dbl, int TS, int M) {
 
 hipError_t launch_pass(Kind kind, bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g,
                        int accumulate, void* rho, hipStream_t st) {
-    // tile kernels index their tiles with 32-bit integers
-    if (g.Qin * g.qn * g.ntiles >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    // tile kernels index their tiles with 32-bit integers (the count includes the padding of the
+    // XCD-aware order of the register E kernel)
+    if (((g.Qin * g.ntiles + 7) / 8) * 8 * g.qn >= (int64_t(1) << 31)) return hipErrorInvalidValue;
     if (g.qc > 0) return launch_pass_cfp(kind, dbl, in, out, ax, g, accumulate, rho, st);
     if (kind == Kind::A && g.reg_a) return launch_pass_asr(dbl, in, out, ax, g, accumulate, rho, st);
     if (p2_applicable(kind, ax.M) && g.TS == p2_tile_lines(ax.M))
