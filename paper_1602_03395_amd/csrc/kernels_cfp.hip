@@ -858,13 +858,18 @@ hipError_t launch_er_T(Kind kind, const void* in, void* out, const AxisDev& ax, 
     }
 }
 
+// Workgroup size of the accumulate kernels: one wavefront per workgroup when the launch is
+// small, so that the work spreads over every CU (these passes are latency bound).
+int acc_block(int64_t nthreads) { return nthreads < (int64_t)kThreads * 1024 ? 64 : kThreads; }
+
 template <typename T, int G>
 hipError_t launch_asr(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
                       hipStream_t st) {
     const int64_t ngroups = g.Qin * g.A * (int64_t)ax.P * g.S;
-    int64_t blocks = (ngroups + kThreads - 1) / kThreads;
+    const int bs = acc_block(ngroups);
+    int64_t blocks = (ngroups + bs - 1) / bs;
     if (blocks > (1 << 20)) blocks = 1 << 20;
-    hipLaunchKernelGGL((k_ASR<T, G>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), 0, st,
+    hipLaunchKernelGGL((k_ASR<T, G>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(bs), 0, st,
                        (const C<T>*)in, (C<T>*)out, ax, g, accumulate, (T*)rho);
     return hipGetLastError();
 }
@@ -873,9 +878,10 @@ template <typename T, int K>
 hipError_t launch_ask(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
                       hipStream_t st) {
     const int64_t nthreads = g.Qin * g.A * (int64_t)ax.P * g.S * K;
-    int64_t blocks = (nthreads + kThreads - 1) / kThreads;
+    const int bs = acc_block(nthreads);
+    int64_t blocks = (nthreads + bs - 1) / bs;
     if (blocks > (1 << 20)) blocks = 1 << 20;
-    hipLaunchKernelGGL((k_ASK<T, K>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), 0, st,
+    hipLaunchKernelGGL((k_ASK<T, K>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(bs), 0, st,
                        (const C<T>*)in, (C<T>*)out, ax, g, accumulate, (T*)rho);
     return hipGetLastError();
 }
