@@ -193,11 +193,12 @@ def main():
                     help="c4 only: expand this single realization through one plan (per-pass timing)")
     ap.add_argument("--dtype", default=None, choices=[None, "c64", "c128"])
     ap.add_argument("--schedule", default="paper", choices=["paper", "axis_factorised"])
-    ap.add_argument("--variant", default="free", choices=["free", "spectrum", "pair", "far_field", "brute_force"],
+    ap.add_argument("--variant", default="free", choices=["free", "spectrum", "pair", "far_field", "brute_force", "grad"],
                     help="free: free flight (the paper's case); spectrum: a tabulated non-quadratic "
                          "axis-additive spectrum of the same size; pair: positive-P pair psi, psi^+; "
                          "far_field: the far-field estimate (comparator) on the same output lattice; "
-                         "brute_force: the padded-lattice propagation (comparator), same result")
+                         "brute_force: the padded-lattice propagation (comparator), same result; "
+                         "grad: expansion plus the gradient of the density fit loss (adjoint)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -270,6 +271,16 @@ def main():
     elif args.variant == "brute_force":
         def step():
             return plan.brute_force(psi)
+    elif args.variant == "grad":
+        # one forward + backward of the fitting loss L = sum (rho - tau)^2 (tau: a fixed synthetic image)
+        tau = torch.full(psi.shape, 1e-6, dtype=rho.dtype, device=dev)
+        grad_rho = torch.empty_like(rho)
+        grad = torch.empty_like(psi)
+
+        def step():
+            plan.expand(psi, psi_out=out, rho_out=rho)
+            torch.sub(rho, tau, out=grad_rho).mul_(2.0)
+            return plan.density_adjoint(out, grad_rho, grad_in=grad)
     else:
         def step():
             return plan.expand(psi, psi_out=out, rho_out=rho)

@@ -195,6 +195,17 @@ fx_status fx_column_density(fx_plan* plan, const void* rho, int axis, void* imag
 fx_status fx_expand_adjoint(fx_plan* plan, const void* grad_psi_out, void* grad_psi0, void* stream);
 
 /*
+ * Gradient of a real loss of the density: grad_psi0 = U^H (2 grad_rho * psibar), the
+ * derivative dL/dRe psi0 + i dL/dIm psi0 for L a function of rho = |U psi0|^2 (a derived
+ * operation, as fx_expand_adjoint). psibar (complex) is the expansion fx_expand returned,
+ * grad_rho (real) dL/drho, both of the plan's shape; grad_psi0 receives the gradient.
+ * Device pointers, asynchronous on `stream`. Errors: FX_EINVAL (NULL arguments), FX_ENOMEM,
+ * FX_EDEVICE.
+ */
+fx_status fx_density_adjoint(fx_plan* plan, const void* psibar, const void* grad_rho, void* grad_psi0,
+                             void* stream);
+
+/*
  * Positive-P pairs (section 7.4, generalisations): the two independent fields
  * psi and psi^+ that stand for the annihilation and creation operators are
  * expanded together, as two slices of one run of the plan's passes. psi follows

@@ -80,6 +80,7 @@ def _load():
         "fx_density": (ctypes.c_int, [vp, vp, vp, vp]),
         "fx_column_density": (ctypes.c_int, [vp, vp, ctypes.c_int, vp, vp]),
         "fx_expand_adjoint": (ctypes.c_int, [vp, vp, vp, vp]),
+        "fx_density_adjoint": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "fx_expand_pair": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "fx_plan_pair_workspace_size": (ctypes.c_int, [vp, P(ctypes.c_size_t)]),
         "fx_far_field": (ctypes.c_int, [vp, vp, vp, vp, vp]),

@@ -187,6 +187,22 @@ class Plan:
                 "fx_expand_adjoint")
         return grad_in
 
+    def density_adjoint(self, psibar: torch.Tensor, grad_rho: torch.Tensor,
+                        grad_in: Optional[torch.Tensor] = None):
+        """grad_psi0 = U^H (2 grad_rho psibar), see ``fx_density_adjoint``."""
+        _check_field(psibar, "psibar")
+        self._check_shape(psibar)
+        if grad_rho.dtype != real_dtype(self.dtype) or grad_rho.device.type != "cuda":
+            raise ValueError("grad_rho must be a device tensor of the plan's real dtype")
+        grad_rho = grad_rho.contiguous()
+        if tuple(grad_rho.shape) != self.shape:
+            raise ValueError("grad_rho has the wrong shape")
+        if grad_in is None:
+            grad_in = torch.empty_like(psibar)
+        L.check(L.lib.fx_density_adjoint(self._h, _ptr(psibar), _ptr(grad_rho), _ptr(grad_in), _stream_ptr()),
+                "fx_density_adjoint")
+        return grad_in
+
     def pair_workspace_size(self) -> int:
         b = ctypes.c_size_t()
         L.check(L.lib.fx_plan_pair_workspace_size(self._h, ctypes.byref(b)), "fx_plan_pair_workspace_size")
@@ -371,8 +387,7 @@ class ExpandDensity(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_rho):
         (psi,) = ctx.saved_tensors
-        g = (2.0 * grad_rho.to(psi.real.dtype)) * psi
-        grad = ctx.plan.expand_adjoint(g.contiguous())
+        grad = ctx.plan.density_adjoint(psi, grad_rho.to(psi.real.dtype))
         return grad, None, None, None, None, None, None, None
 
 

@@ -39,6 +39,18 @@ __global__ void k_pair_out(const C<T>* __restrict__ res, C<T>* __restrict__ out,
     }
 }
 
+// g = 2 grad_rho psibar: the derivative of a real function of rho = |psibar|^2 in PyTorch's
+// complex convention (dL/dRe + i dL/dIm)
+template <typename T>
+__global__ void k_density_grad(const C<T>* __restrict__ psibar, const T* __restrict__ grad_rho, C<T>* __restrict__ g,
+                               int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const T w = (T)2 * grad_rho[i];
+        const C<T> v = psibar[i];
+        g[i] = mk<T>(w * v.x, w * v.y);
+    }
+}
+
 int blocks_for(int64_t n) {
     const int64_t b = (n + kThreads - 1) / kThreads;
     return (int)std::max<int64_t>(1, std::min<int64_t>(b, 8192));
@@ -98,6 +110,29 @@ fx_status fx_expand_pair(fx_plan* p, const void* psi, const void* psi_plus, void
                            (float2*)psi_out, (float2*)psi_plus_out, (float2*)n_out, n);
     FX_TRY_HIP(hipGetLastError());
     return FX_OK;
+}
+
+fx_status fx_density_adjoint(fx_plan* p, const void* psibar, const void* grad_rho, void* grad_psi0, void* stream) {
+    if (!p) { set_error("plan is NULL"); return FX_EINVAL; }
+    fx_status s = check_ptr(psibar, "psibar");
+    if (s != FX_OK) return s;
+    if ((s = check_ptr(grad_rho, "grad_rho")) != FX_OK) return s;
+    if ((s = check_ptr(grad_psi0, "grad_psi0")) != FX_OK) return s;
+    if (p->slices != 1) plan_setup_workspace(p, 1);
+    if ((s = ensure_workspace(p)) != FX_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = p->M;
+    // 2 grad_rho psibar goes to the output staging region, which the adjoint passes do not use
+    void* g = (char*)p->ws + (size_t)2 * p->buf_elems * csize(p);
+    if (p->dbl)
+        hipLaunchKernelGGL(k_density_grad<double>, dim3(blocks_for(n)), dim3(kThreads), 0, st,
+                           (const double2*)psibar, (const double*)grad_rho, (double2*)g, n);
+    else
+        hipLaunchKernelGGL(k_density_grad<float>, dim3(blocks_for(n)), dim3(kThreads), 0, st,
+                           (const float2*)psibar, (const float*)grad_rho, (float2*)g, n);
+    FX_TRY_HIP(hipGetLastError());
+    int qb[3] = {0, 0, 0}, qn[3] = {p->ax[0].lam, p->ax[1].lam, p->ax[2].lam};
+    return run_box(p, qb, qn, g, grad_psi0, 0, nullptr, true, st);
 }
 
 }  // extern "C"

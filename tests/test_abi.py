@@ -156,3 +156,8 @@ def test_far_field_entry_rejects_null_arguments():
 def test_brute_force_entry_rejects_null_arguments():
     L = _lib()
     assert L.lib.fx_brute_force(None, None, None, None, None) == L.FX_EINVAL
+
+
+def test_density_adjoint_entry_rejects_null_arguments():
+    L = _lib()
+    assert L.lib.fx_density_adjoint(None, None, None, None, None) == L.FX_EINVAL
