@@ -136,6 +136,10 @@ int aa_tile_groups(int gu, int gv);
 size_t aa_lds_bytes(bool dbl, int gu, int gv);
 hipError_t launch_pass_aa(bool dbl, const void* in, void* out, const AxisDev& au, const AxisDev& av, const AAGeom& g,
                           int accumulate, void* rho, hipStream_t st);
+// Adjoint of E in register form (power-of-two P <= g <= 64, P <= 16).
+bool ehr_applicable(int M, int g);
+hipError_t launch_pass_ehr(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
+                           hipStream_t st);
 // Structured accumulate (A) with one thread per output group and register accumulators (g <= 32).
 bool asr_applicable(int g, int max_g);
 hipError_t launch_pass_asr(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,

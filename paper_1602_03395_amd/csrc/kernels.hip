@@ -361,10 +361,24 @@ __global__ __launch_bounds__(kThreads) void k_EH(const C<T>* __restrict__ in, C<
         for (int i = 0; i < g.qn; ++i) {
             const int q = g.qb + i;
             const int64_t si = qo * g.qn + i;
-            for (int e = threadIdx.x; e < nl * P; e += blockDim.x) {
-                int l, u;
-                const int64_t off = tile_elem(g, tl, si, P, fdP, e, l, u);
-                B0[l * M + u] = in[off];
+            // four elements per thread and step, their loads issued before the stores
+            for (int e0 = threadIdx.x; e0 < nl * P; e0 += 4 * blockDim.x) {
+                C<T> v[4];
+                int d[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int e = e0 + k * (int)blockDim.x;
+                    d[k] = -1;
+                    if (e < nl * P) {
+                        int l, u;
+                        const int64_t off = tile_elem(g, tl, si, P, fdP, e, l, u);
+                        v[k] = in[off];
+                        d[k] = l * M + u;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (d[k] >= 0) B0[d[k]] = v[k];
             }
             __syncthreads();
             C<T>* Z = lds_fft<T>(B0, B1, nl, M, ax.fp, tw, ax.g, false);
@@ -724,6 +738,7 @@ hipError_t launch_pass(Kind kind, bool dbl, const void* in, void* out, const Axi
     // tile kernels index their tiles with 32-bit integers (the count includes the padding of the
     // XCD-aware order of the register E kernel)
     if (((g.Qin * g.ntiles + 7) / 8) * 8 * g.qn >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    if (g.qc > 0 && kind == Kind::EH) return launch_pass_ehr(dbl, in, out, ax, g, accumulate, st);
     if (g.qc > 0) return launch_pass_cfp(kind, dbl, in, out, ax, g, accumulate, rho, st);
     if (kind == Kind::A && g.reg_a) return launch_pass_asr(dbl, in, out, ax, g, accumulate, rho, st);
     if (p2_applicable(kind, ax.M) && g.TS == p2_tile_lines(ax.M))

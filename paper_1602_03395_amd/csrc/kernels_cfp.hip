@@ -778,6 +778,82 @@ __global__ __launch_bounds__(kThreads) void k_ASK(const C<T>* __restrict__ in, C
     }
 }
 
+// EH (adjoint of E, summed over q) in register form, power-of-two P <= g. For lane (line, n2):
+//   x[g n1 + n2] = sum_q conj(TA_q[g n1]) sum_r exp(2 pi i n1 r / P) conj(HT_q[n2][r]) Y_q[r],
+//   Y_q[r] = sum_u exp(-2 pi i r u / P) y_q[u],
+// the conjugate transpose of every step of the register E, in reverse order. Each lane forms the
+// P-point transform of the line's P inputs itself (the G lanes of a line read the same addresses).
+// Workgroups take a chunk of qc terms; with several chunks per tile they add into the
+// (pre-cleared) output with atomics.
+template <typename T, int P>
+__global__ __launch_bounds__(kThreads) void k_EHR(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
+                                                  PassGeom g, int accumulate, int lgG, int atomic,
+                                                  const C<T>* __restrict__ TA, const C<T>* __restrict__ HT) {
+    const int M = ax.M;
+    const int G = 1 << lgG;
+    const int l = (int)threadIdx.x >> lgG;
+    const int n2 = (int)threadIdx.x & (G - 1);
+    const int qc = g.qc;
+    const int nqc = (g.qn + qc - 1) / qc;
+    const int64_t ntl = g.Qin * g.ntiles;
+    const int64_t total = ((ntl + 7) / 8) * 8 * nqc;  // XCD-aware order as in k_ER
+    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
+        const int64_t rr = bid >> 3;
+        const int ci = (int)(rr % nqc);
+        const int64_t tile = (rr / nqc) * 8 + (bid & 7);
+        if (tile >= ntl) continue;
+        const int64_t qo = tile / g.ntiles;
+        const int64_t tt = tile - qo * g.ntiles;
+        const Tile tl = decode_tile(g, tt);
+        const bool live = l < tl.nl;
+        const int qlo = g.qb + ci * qc;
+        const int qhi = min(qlo + qc, g.qb + g.qn);
+        C<T> acc[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) acc[i] = mk<T>(0, 0);
+        if (live) {
+            for (int q = qlo; q < qhi; ++q) {
+                const int64_t si = qo * g.qn + (q - g.qb);
+                C<T> y[P];
+#pragma unroll
+                for (int u = 0; u < P; ++u) {
+                    const int64_t off = (g.S == 1) ? ((si * g.A + tl.a0 + l) * P + u)
+                                                   : (((si * g.A + tl.a0) * P + u) * g.S + tl.s0 + l);
+                    y[u] = in[off];
+                }
+                RegDFT<T, P, false>::run(y);
+                const C<T>* h = HT + ((int64_t)q * G + n2) * P;
+#pragma unroll
+                for (int r = 0; r < P; ++r) y[r] = cmulc<T>(y[r], h[r]);
+                RegDFT<T, P, true>::run(y);
+                const C<T>* ta = TA + (int64_t)q * M;
+#pragma unroll
+                for (int i = 0; i < P; ++i) acc[i] = cfmac<T>(acc[i], y[i], ta[i << lgG]);
+            }
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                const int n = (i << lgG) + n2;
+                const int64_t off = (g.S == 1) ? ((qo * g.A + tl.a0 + l) * M + n)
+                                               : (((qo * g.A + tl.a0) * M + n) * g.S + tl.s0 + l);
+                if (atomic) {
+                    atomicAdd(&((T*)out)[2 * off], acc[i].x);
+                    atomicAdd(&((T*)out)[2 * off + 1], acc[i].y);
+                } else {
+                    C<T> v = acc[i];
+                    if (accumulate) v = cadd<T>(v, out[off]);
+                    out[off] = v;
+                }
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_zero(C<T>* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = mk<T>(0, 0);
+}
+
 hipError_t prep_lds(const void* k, size_t lds) {
     static std::mutex mu;
     static std::set<const void*> done;
@@ -913,6 +989,53 @@ hipError_t launch_pass_asr(bool dbl, const void* in, void* out, const AxisDev& a
     if (!asr_applicable(ax.g, 64)) return hipErrorInvalidValue;
     return dbl ? launch_asr_T<double>(in, out, ax, g, accumulate, rho, st)
                : launch_asr_T<float>(in, out, ax, g, accumulate, rho, st);
+}
+
+template <typename T, int P>
+hipError_t launch_ehr(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
+                      hipStream_t st) {
+    const int nqc = (g.qn + g.qc - 1) / g.qc;
+    const int atomic = nqc > 1 ? 1 : 0;
+    if (atomic && !accumulate) {
+        // the chunks of a tile add into the output: clear it first (a kernel, not a memset node)
+        const int64_t n = g.Qin * g.A * (int64_t)ax.M * g.S;
+        const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kThreads - 1) / kThreads, 1 << 16));
+        hipLaunchKernelGGL(k_zero<T>, dim3(nb), dim3(kThreads), 0, st, (C<T>*)out, n);
+    }
+    int64_t blocks = ((g.Qin * g.ntiles + 7) / 8) * 8 * nqc;
+    if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = (g.max_blocks + 7) / 8 * 8;
+    if (blocks > (1 << 22)) blocks = 1 << 22;
+    hipLaunchKernelGGL((k_EHR<T, P>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), 0, st,
+                       (const C<T>*)in, (C<T>*)out, ax, g, accumulate, ilog2i(ax.g), atomic, (const C<T>*)ax.TA,
+                       (const C<T>*)ax.HT);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ehr_T(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
+                        hipStream_t st) {
+    switch (ax.P) {
+        case 1: return launch_ehr<T, 1>(in, out, ax, g, accumulate, st);
+        case 2: return launch_ehr<T, 2>(in, out, ax, g, accumulate, st);
+        case 4: return launch_ehr<T, 4>(in, out, ax, g, accumulate, st);
+        case 8: return launch_ehr<T, 8>(in, out, ax, g, accumulate, st);
+        case 16: return launch_ehr<T, 16>(in, out, ax, g, accumulate, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+bool ehr_applicable(int M, int g) {
+    if (g < 1 || g > kWave || (g & (g - 1)) != 0 || M % g != 0) return false;
+    const int P = M / g;
+    return (P == 1 || P == 2 || P == 4 || P == 8 || P == 16) && g >= P;
+}
+
+hipError_t launch_pass_ehr(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
+                           hipStream_t st) {
+    if (!ehr_applicable(ax.M, ax.g) || !ax.HT || g.TS != cfp_tile_lines(ax.g) || g.qc < 1)
+        return hipErrorInvalidValue;
+    if (((g.Qin * g.ntiles + 7) / 8) * 8 * ((g.qn + g.qc - 1) / g.qc) >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    return dbl ? launch_ehr_T<double>(in, out, ax, g, accumulate, st) : launch_ehr_T<float>(in, out, ax, g, accumulate, st);
 }
 
 bool aa_applicable(bool dbl, int gu, int gv) {
