@@ -228,9 +228,30 @@ template <typename T, bool INV> struct RegDFT<T, 12, INV> {
     __device__ __forceinline__ static void run(C<T>* v) { RegDFT2x<T, INV, 12>::run(v); }
 };
 
+// a(lane ^ m) within a wavefront. Masks 1 and 2 stay inside a quad of lanes and use a DPP
+// quad permutation (a VALU move without a trip through the LDS crossbar); other masks use
+// ds_bpermute through __shfl_xor. m is uniform over the wavefront.
+__device__ __forceinline__ int dpp_quad_xor(int v, int m) {
+    return (m == 1) ? __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false)   // quad_perm [1, 0, 3, 2]
+                    : __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2, 3, 0, 1]
+}
+__device__ __forceinline__ float xor_lane(float v, int m) {
+    if (m == 1 || m == 2) return __int_as_float(dpp_quad_xor(__float_as_int(v), m));
+    return __shfl_xor(v, m, kWave);
+}
+__device__ __forceinline__ double xor_lane(double v, int m) {
+    if (m == 1 || m == 2) {
+        const long long b = __double_as_longlong(v);
+        const int lo = dpp_quad_xor((int)(b & 0xffffffffLL), m);
+        const int hi = dpp_quad_xor((int)(b >> 32), m);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    }
+    return __shfl_xor(v, m, kWave);
+}
+
 template <typename T>
 __device__ __forceinline__ C<T> shfl_xor_c(C<T> a, int m) {
-    return mk<T>(__shfl_xor(a.x, m, kWave), __shfl_xor(a.y, m, kWave));
+    return mk<T>(xor_lane(a.x, m), xor_lane(a.y, m));
 }
 
 // Sum over the G = 2^lgG lanes of a line of each lane's P values. Reduce-scatter over the low
