@@ -110,7 +110,8 @@ size_t csize(const fx_plan* p) { return p->dbl ? 16 : 8; }
 
 bool use_cfp(const fx_plan* p, Kind kind, const AxisDev& a) {
     return p->use_cfp && a.HT != nullptr && cfp_applicable(kind, p->dbl, a.M, a.g) &&
-           (int64_t)cfp_lds_bytes(p->dbl, a.M, a.g) <= lds_limit_bytes();
+           (int64_t)(cfp_lds_bytes(p->dbl, a.M, a.g) + (size_t)a.lam * (a.M / a.g) * (p->dbl ? 16 : 8)) <=
+               lds_limit_bytes();
 }
 
 int choose_ts(const fx_plan* p, Kind kind, int M, int64_t A, int64_t S) {
@@ -531,22 +532,23 @@ fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_pla
             return FX_EUNSUPPORTED;
         }
     }
-    // Upload all tables in one allocation: per axis TA | TB | Tf | tw.
+    // Upload all tables in one allocation: per axis TA | TB | Tf | tw | HT | HTx.
     const size_t cs = csize(p);
     size_t total = 0;
-    size_t offs[3][5];
+    size_t offs[3][6];
     for (int pa = 0; pa < 3; ++pa) {
         const size_t lm = (size_t)p->ax[pa].lam * p->ax[pa].M;
-        const size_t sz[5] = {lm, lm, lm, (size_t)p->ax[pa].M, tabs[pa].HT.size() / 2};
-        for (int t = 0; t < 5; ++t) {
+        const size_t sz[6] = {lm, lm, lm, (size_t)p->ax[pa].M, tabs[pa].HT.size() / 2, tabs[pa].HTx.size() / 2};
+        for (int t = 0; t < 6; ++t) {
             offs[pa][t] = total;
             total += ((sz[t] * cs + 255) / 256) * 256;
         }
     }
     std::vector<unsigned char> host(total, 0);
     for (int pa = 0; pa < 3; ++pa) {
-        const std::vector<double>* src[5] = {&tabs[pa].TA, &tabs[pa].TB, &tabs[pa].Tf, &tabs[pa].tw, &tabs[pa].HT};
-        for (int t = 0; t < 5; ++t) {
+        const std::vector<double>* src[6] = {&tabs[pa].TA, &tabs[pa].TB, &tabs[pa].Tf, &tabs[pa].tw, &tabs[pa].HT,
+                                             &tabs[pa].HTx};
+        for (int t = 0; t < 6; ++t) {
             if (p->dbl) to_prec<double>(*src[t], host, offs[pa][t]);
             else to_prec<float>(*src[t], host, offs[pa][t]);
         }
@@ -571,6 +573,7 @@ fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_pla
         p->ax[pa].Tf = b + offs[pa][2];
         p->ax[pa].tw = b + offs[pa][3];
         p->ax[pa].HT = tabs[pa].HT.empty() ? nullptr : b + offs[pa][4];
+        p->ax[pa].HTx = tabs[pa].HTx.empty() ? nullptr : b + offs[pa][5];
     }
     size_t budget = (size_t)8 << 30;
     if (const char* e = std::getenv("FX_WORKSPACE_MB")) budget = (size_t)std::max(1L, std::atol(e)) << 20;

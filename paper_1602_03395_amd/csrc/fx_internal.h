@@ -38,6 +38,7 @@ struct AxisDev {
     const void* Tf = nullptr;
     const void* tw = nullptr;
     const void* HT = nullptr;  // [lam][g][P] chirp-folded table of the register E kernel (or null)
+    const void* HTx = nullptr; // HT arranged for the select-free first reduction step (or null)
     int M = 1;        // axis length
     int P = 1;        // M / g: number of distinct n'' values (output-pruned length)
     int g = 1;        // gcd(lam, M)
@@ -105,6 +106,7 @@ int lds_limit_bytes();
 struct AxisTables {
     std::vector<double> TA, TB, Tf, tw;  // interleaved re,im; [lam][M] for TA/TB/Tf, [M] for tw
     std::vector<double> HT;              // [lam][g][P] when requested, else empty
+    std::vector<double> HTx;             // HT for odd n2 lanes swapped or sign-modulated (see build_ht)
 };
 struct AxisParams {
     int64_t M = 1;

@@ -275,6 +275,22 @@ __device__ __forceinline__ void reduce_step(C<T>* v, int n2, int lgG) {
     }
 }
 
+// The same reduce-scatter when the odd lane of every pair (n2, n2 ^ 1) holds its P values with
+// the two halves exchanged (its input or its table row arranged for it): in the first step both
+// lanes keep v[0, P/2) and send v[P/2, P), with no per-lane select; the remaining steps follow
+// reduce_step. The result is the one reduce_step leaves.
+template <typename T, int P>
+__device__ __forceinline__ void reduce_scatter_x(C<T>* v, int n2, int lgG) {
+    if constexpr (P >= 2) {
+        if (lgG >= 1) {
+            constexpr int half = P / 2;
+#pragma unroll
+            for (int i = 0; i < half; ++i) v[i] = cadd<T>(v[i], shfl_xor_c<T>(v[i + half], 1));
+            reduce_step<T, P, 1>(v, n2, lgG);
+        }
+    }
+}
+
 // Every lane of a line ends with all P sums over the G = 2^lgG lanes (any P).
 template <typename T, int P>
 __device__ __forceinline__ void reduce_all(C<T>* v, int lgG) {
@@ -314,32 +330,37 @@ __device__ __forceinline__ void load_tile(const C<T>* __restrict__ in, C<T>* B, 
     }
 }
 
-// wst[s] = exp(+2 pi i (n2 mod 2^s) / 2^(s+1)) = conj(tw[(n2 mod 2^s) M / 2^(s+1)]), tw[k] = exp(-2 pi i k / M)
+// Twiddles of lane_idft_x: stage s uses wst[s] = w (lower lane) or -conj(w) (upper lane), with
+// w = exp(2 pi i (n2 mod 2^s) / 2^(s+1)). Returns the lane's final rescale (see lane_idft_x).
 template <typename T, int LP>
-__device__ __forceinline__ void lane_twiddles(C<T>* wst, int n2, const C<T>* tw, int M) {
+__device__ __forceinline__ C<T> lane_twiddles_x(C<T>* wst, int n2, const C<T>* tw, int M) {
+    C<T> c = mk<T>(1, 0);
 #pragma unroll
     for (int s = 0; s < LP; ++s) {
-        const C<T> w = tw[(n2 & ((1 << s) - 1)) * (M >> (s + 1))];
-        wst[s] = mk<T>(w.x, -w.y);
+        const C<T> t = tw[(n2 & ((1 << s) - 1)) * (M >> (s + 1))];  // conj(w)
+        if ((n2 >> s) & 1) {
+            wst[s] = mk<T>(-t.x, -t.y);
+            c = cmul<T>(c, wst[s]);
+        } else {
+            wst[s] = mk<T>(t.x, -t.y);
+        }
     }
+    return mk<T>(c.x, -c.y);
 }
 
 // Inverse P-point DFT across the first P lanes of a line (power-of-two P <= G). On entry lane n2
 // holds W[bitrev(n2 mod P)], the order the reduce-scatter leaves; radix-2 decimation in time on
 // bit-reversed input yields natural order, so on exit lane n2 holds sum_r W[r] exp(2 pi i r u / P)
-// for u = n2 mod P. wst[s] = exp(2 pi i (n2 mod 2^s) / 2^(s+1)) is the lane's twiddle of stage s.
+// for u = n2 mod P. No per-lane selects: both lanes of a butterfly form own + k * partner: the
+// lower lane with k = w gives a_lo + w a_up exactly; the upper lane with k = -conj(w) gives
+// a_up - conj(w) a_lo = -conj(w) (a_lo - w a_up), its true output times the unit factor
+// -conj(w). The factors of the stages where the lane is the upper one multiply up to c; the
+// result is multiplied by conj(c) = 1 / c at the end (fin from lane_twiddles_x).
 template <typename T, int LP>
-__device__ __forceinline__ C<T> lane_idft(C<T> a, int n2, const C<T>* wst) {
+__device__ __forceinline__ C<T> lane_idft_x(C<T> a, const C<T>* wst, C<T> fin) {
 #pragma unroll
-    for (int s = 0; s < LP; ++s) {
-        const int h = 1 << s;
-        const C<T> b = shfl_xor_c<T>(a, h);
-        const bool upper = (n2 & h) != 0;
-        // lower lane: a + w b; upper lane: b - w a (b is then the lower value)
-        const C<T> wx = cmul<T>(wst[s], upper ? a : b);
-        a = upper ? csub<T>(b, wx) : cadd<T>(a, wx);
-    }
-    return a;
+    for (int s = 0; s < LP; ++s) a = cfma<T>(a, wst[s], shfl_xor_c<T>(a, 1 << s));
+    return cmul<T>(a, fin);
 }
 
 template <typename T, int P, bool LANEINV>
@@ -348,7 +369,8 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
                                                  const C<T>* __restrict__ HT) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int LP = (P >= 32) ? 5 : (P >= 16) ? 4 : (P >= 8) ? 3 : (P >= 4) ? 2 : (P >= 2) ? 1 : 0;
-    C<T>* B = (C<T>*)smem;  // tile: TS lines x M points
+    C<T>* B = (C<T>*)smem;        // tile of strided lines: TS lines x M points
+    C<T>* TAs = B + kThreads * P;  // TA_q[g i] of the workgroup's qc terms, [q - qlo][i]
     const int M = ax.M;
     const int G = 1 << lgG;
     const int l = (int)threadIdx.x >> lgG;
@@ -364,8 +386,12 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
     int base = 0;
     for (int s = 0; s < lk; ++s) base += ((n2 >> s) & 1) * ((P >> s) >> 1);
     const bool writer = (n2 >> lk) == 0 || lgG <= LP;
+    // HT is the table arranged for reduce_scatter_x (pow2 P). With the lane transform the odd
+    // lane's input is modulated by (-1)^n1 (applied once per tile below), which exchanges the
+    // halves of its spectrum.
+    const bool odd_flip = LANEINV && (n2 & 1) && lgG >= 1;
     C<T> wst[LP > 0 ? LP : 1];
-    lane_twiddles<T, LP>(wst, n2, (const C<T>*)ax.tw, M);
+    const C<T> fin = lane_twiddles_x<T, LP>(wst, n2, (const C<T>*)ax.tw, M);
     for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
         const int64_t rr = bid >> 3;
         const int ci = (int)(rr % nqc);
@@ -374,75 +400,95 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
         const int64_t qi = tile / g.ntiles;
         const int64_t tt = tile - qi * g.ntiles;
         const Tile tl = decode_tile(g, tt);
-        const FDiv fdM = tile_div(g, tl, M);
-        load_tile<T, P, (sizeof(T) == 4 ? P : 1)>(in, B, g, tl, qi, M, fdM);
-        __syncthreads();
         const bool live = l < tl.nl;
-        const C<T>* x = B + l * M + n2;  // the line stays in LDS for every q (rows past nl are unused)
         const int qlo = g.qb + ci * qc;
         const int qhi = min(qlo + qc, g.qb + g.qn);
+        // the chunk's premultiply values go through LDS: issued first, stored after the tile
+        const int nta = (qhi - qlo) * P;
+        const int ti = (int)threadIdx.x;
+        C<T> tav = mk<T>(0, 0);
+        if (ti < nta) tav = TA[(int64_t)(qlo + ti / P) * M + ((ti % P) << lgG)];
+        C<T> x[P];
+        if (g.S == 1) {
+            // contiguous lines: lane n2 reads x[g i + n2] directly (G consecutive lanes per i)
+            const C<T>* src = in + (qi * g.A + tl.a0 + (live ? l : 0)) * M + n2;
+#pragma unroll
+            for (int i = 0; i < P; ++i) x[i] = live ? src[i << lgG] : mk<T>(0, 0);
+        } else {
+            const FDiv fdM = tile_div(g, tl, M);
+            load_tile<T, P, (sizeof(T) == 4 ? P : 1)>(in, B, g, tl, qi, M, fdM);
+        }
+        if (ti < nta) TAs[ti] = tav;
+        for (int e = ti + kThreads; e < nta; e += kThreads) TAs[e] = TA[(int64_t)(qlo + e / P) * M + ((e % P) << lgG)];
+        __syncthreads();
+        if (g.S != 1) {
+#pragma unroll
+            for (int i = 0; i < P; ++i) x[i] = live ? B[l * M + (i << lgG) + n2] : mk<T>(0, 0);
+        }
+        if (odd_flip) {
+#pragma unroll
+            for (int i = 1; i < P; i += 2) x[i] = mk<T>(-x[i].x, -x[i].y);
+        }
         for (int q = qlo; q < qhi; ++q) {
-            const C<T>* ta = TA + (int64_t)q * M;
+            const C<T>* ta = TAs + (q - qlo) * P;
             const C<T>* h = HT + ((int64_t)q * G + n2) * P;
             C<T> v[P];
 #pragma unroll
-            for (int i = 0; i < P; ++i) v[i] = cmul<T>(x[i << lgG], ta[i << lgG]);
+            for (int i = 0; i < P; ++i) v[i] = cmul<T>(x[i], ta[i]);
             RegDFT<T, P, false>::run(v);
 #pragma unroll
             for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r]);
             if constexpr (LANEINV) {
-                {
-                    // sum over the lanes first, then one inverse transform across the P lanes
-                    reduce_step<T, P, 0>(v, n2, lgG);
+                // sum over the lanes first, then one inverse transform across the P lanes
+                reduce_scatter_x<T, P>(v, n2, lgG);
+                C<T> s0 = v[0];
+                for (int s = LP; s < lgG; ++s) s0 = cadd<T>(s0, shfl_xor_c<T>(s0, 1 << s));
+                s0 = lane_idft_x<T, LP>(s0, wst, fin);
+                if (live && n2 < P) {
+                    const int64_t qo = qi * g.qn + (q - g.qb);
+                    const int64_t off = (g.S == 1) ? ((qo * g.A + tl.a0 + l) * P + n2)
+                                                   : (((qo * g.A + tl.a0) * P + n2) * g.S + tl.s0 + l);
+                    out[off] = s0;
+                }
+            } else {
+                RegDFT<T, P, true>::run(v);
+                if constexpr (!kPow2<P>) {
+                    // all-reduce; lane n2 writes the values u = n2 mod G
+                    reduce_all<T, P>(v, lgG);
+                    if (live) {
+                        const int64_t qo = qi * g.qn + (q - g.qb);
+#pragma unroll
+                        for (int u = 0; u < P; ++u) {
+                            if ((u & (G - 1)) == n2) {
+                                const int64_t off = (g.S == 1) ? ((qo * g.A + tl.a0 + l) * P + u)
+                                                               : (((qo * g.A + tl.a0) * P + u) * g.S + tl.s0 + l);
+                                out[off] = v[u];
+                            }
+                        }
+                    }
+                } else {
+                    // G < P: the odd lane's table row carries (-1)^r, which exchanges the halves
+                    // of its inverse output
+                    reduce_scatter_x<T, P>(v, n2, lgG);
                     C<T> s0 = v[0];
                     for (int s = LP; s < lgG; ++s) s0 = cadd<T>(s0, shfl_xor_c<T>(s0, 1 << s));
-                    s0 = lane_idft<T, LP>(s0, n2, wst);
-                    if (live && n2 < P) {
+                    v[0] = s0;
+                    if (live && writer) {
                         const int64_t qo = qi * g.qn + (q - g.qb);
-                        const int64_t off = (g.S == 1) ? ((qo * g.A + tl.a0 + l) * P + n2)
-                                                       : (((qo * g.A + tl.a0) * P + n2) * g.S + tl.s0 + l);
-                        out[off] = s0;
-                    }
-                    continue;
-                }
-            }
-            if constexpr (!LANEINV) {
-            RegDFT<T, P, true>::run(v);
-            if constexpr (!kPow2<P>) {
-                // all-reduce; lane n2 writes the values u = n2 mod G
-                reduce_all<T, P>(v, lgG);
-                if (live) {
-                    const int64_t qo = qi * g.qn + (q - g.qb);
 #pragma unroll
-                    for (int u = 0; u < P; ++u) {
-                        if ((u & (G - 1)) == n2) {
-                            const int64_t off = (g.S == 1) ? ((qo * g.A + tl.a0 + l) * P + u)
-                                                           : (((qo * g.A + tl.a0) * P + u) * g.S + tl.s0 + l);
-                            out[off] = v[u];
+                        for (int i = 0; i < P; ++i) {
+                            if (i < cnt) {
+                                const int u = base + i;
+                                const int64_t off = (g.S == 1) ? ((qo * g.A + tl.a0 + l) * P + u)
+                                                               : (((qo * g.A + tl.a0) * P + u) * g.S + tl.s0 + l);
+                                out[off] = v[i];
+                            }
                         }
                     }
                 }
-                continue;
-            }
-            reduce_step<T, P, 0>(v, n2, lgG);
-            C<T> s0 = v[0];
-            for (int s = LP; s < lgG; ++s) s0 = cadd<T>(s0, shfl_xor_c<T>(s0, 1 << s));
-            v[0] = s0;
-            if (live && writer) {
-                const int64_t qo = qi * g.qn + (q - g.qb);
-#pragma unroll
-                for (int i = 0; i < P; ++i) {
-                    if (i < cnt) {
-                        const int u = base + i;
-                        const int64_t off = (g.S == 1) ? ((qo * g.A + tl.a0 + l) * P + u)
-                                                       : (((qo * g.A + tl.a0) * P + u) * g.S + tl.s0 + l);
-                        out[off] = v[i];
-                    }
-                }
-            }
             }
         }
-        __syncthreads();  // the next tile overwrites the buffer the q loop reads
+        __syncthreads();  // the next tile overwrites the buffers the q loop reads
     }
 }
 
@@ -460,6 +506,7 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int LP = (P >= 32) ? 5 : (P >= 16) ? 4 : (P >= 8) ? 3 : (P >= 4) ? 2 : (P >= 2) ? 1 : 0;
     C<T>* B = (C<T>*)smem;
+    C<T>* TAs = B + kThreads * P;  // TA_q[g i] of every term of the pass, [q - qb][i]
     const int M = ax.M;
     const int G = 1 << lgG;
     const int l = (int)threadIdx.x >> lgG;
@@ -471,9 +518,13 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
     const int lane = (int)threadIdx.x & (kWave - 1);
     const int src_lane = lane - n2 + u_need;
     C<T> wst[LP > 0 ? LP : 1];
-    lane_twiddles<T, LP>(wst, n2, (const C<T>*)ax.tw, M);
+    const C<T> fin = lane_twiddles_x<T, LP>(wst, n2, (const C<T>*)ax.tw, M);
     // power-of-two P with G >= P: reduce-scatter and one shuffle; otherwise all-reduce and pick
     const bool scatter = kPow2<P> && G >= P;
+    // HT is the table arranged for reduce_scatter_x (pow2 P); on the scatter path the odd lane's
+    // input is modulated by (-1)^n1 as well (once per tile)
+    const bool odd_flip = scatter && (n2 & 1) && lgG >= 1;
+    const int nta = g.qn * P;
     // r(nbar) of the lane's outputs nbar = n2 + G k is r0 + k d (mod P)
     const int r0 = (int)(((int64_t)n2 * ax.lg) % P);
     const int rd = (int)(((int64_t)G * ax.lg) % P);
@@ -487,7 +538,13 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
         const int64_t tt = bid - qi * g.ntiles;
         const Tile tl = decode_tile(g, tt);
         const FDiv fdM = tile_div(g, tl, M);
+        const int ti = (int)threadIdx.x;
+        C<T> tav = mk<T>(0, 0);
+        if (ti < nta) tav = TA[(int64_t)(g.qb + ti / P) * M + ((ti % P) << lgG)];
         load_tile<T, P, 1>(in, B, g, tl, qi, M, fdM);  // x stays in registers: keep the load phase lean
+        if (ti < nta) TAs[ti] = tav;
+        for (int e = ti + kThreads; e < nta; e += kThreads)
+            TAs[e] = TA[(int64_t)(g.qb + e / P) * M + ((e % P) << lgG)];
         __syncthreads();
         const bool live = l < tl.nl;
         C<T> x[P], acc[P];
@@ -496,22 +553,26 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
             x[i] = live ? B[l * M + (i << lgG) + n2] : mk<T>(0, 0);
             acc[i] = mk<T>(0, 0);
         }
+        if (odd_flip) {
+#pragma unroll
+            for (int i = 1; i < P; i += 2) x[i] = mk<T>(-x[i].x, -x[i].y);
+        }
         __syncthreads();
         for (int q = g.qb; q < g.qb + g.qn; ++q) {
-            const C<T>* ta = TA + (int64_t)q * M;
+            const C<T>* ta = TAs + (q - g.qb) * P;
             const C<T>* h = HT + ((int64_t)q * G + n2) * P;
             const C<T>* tf = Tf + (int64_t)q * M + n2;
             C<T> v[P];
 #pragma unroll
-            for (int i = 0; i < P; ++i) v[i] = cmul<T>(x[i], ta[i << lgG]);
+            for (int i = 0; i < P; ++i) v[i] = cmul<T>(x[i], ta[i]);
             RegDFT<T, P, false>::run(v);
 #pragma unroll
             for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r]);
             if (scatter) {
-                reduce_step<T, P, 0>(v, n2, lgG);
+                reduce_scatter_x<T, P>(v, n2, lgG);
                 C<T> s0 = v[0];
                 for (int s = LP; s < lgG; ++s) s0 = cadd<T>(s0, shfl_xor_c<T>(s0, 1 << s));
-                s0 = lane_idft<T, LP>(s0, n2, wst);  // lane n2 < P now holds E[n2]
+                s0 = lane_idft_x<T, LP>(s0, wst, fin);  // lane n2 < P now holds E[n2]
                 const C<T> e = mk<T>(__shfl(s0.x, src_lane, kWave), __shfl(s0.y, src_lane, kWave));
 #pragma unroll
                 for (int k = 0; k < P; ++k) acc[k] = cfma<T>(acc[k], tf[k << lgG], e);
@@ -520,7 +581,7 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
                 // the line's P sums go through LDS (the tile buffer is free during the q loop)
                 C<T>* El = B + l * P;
                 if constexpr (kPow2<P>) {
-                    reduce_step<T, P, 0>(v, n2, lgG);  // G < P: the lane holds P / G values from base
+                    reduce_scatter_x<T, P>(v, n2, lgG);  // G < P: the lane holds P / G values from base
 #pragma unroll
                     for (int i = 0; i < P; ++i)
                         if (i < cnt) El[base + i] = v[i];
@@ -895,7 +956,8 @@ int ilog2i(int v) {
 
 template <typename T, int P>
 hipError_t launch_er(const void* in, void* out, const AxisDev& ax, const PassGeom& g, hipStream_t st) {
-    const size_t lds = cfp_lds_bytes(sizeof(T) == 8, ax.M, ax.g);
+    // tile buffer (strided lines only; its size is fixed by the kernel's layout) + the chunk's TA values
+    const size_t lds = cfp_lds_bytes(sizeof(T) == 8, ax.M, ax.g) + (size_t)g.qc * P * sizeof(C<T>);
     // power-of-two P with at least P lanes per line: reduce first, inverse transform across lanes
     constexpr bool pow2 = kPow2<P>;
     auto k = (pow2 && ax.g >= P) ? k_ER<T, P, pow2> : k_ER<T, P, false>;
@@ -906,14 +968,14 @@ hipError_t launch_er(const void* in, void* out, const AxisDev& ax, const PassGeo
     if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = (g.max_blocks + 7) / 8 * 8;
     if (blocks > (1 << 22)) blocks = 1 << 22;
     hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), lds, st, (const C<T>*)in,
-                       (C<T>*)out, ax, g, ilog2i(ax.g), (const C<T>*)ax.TA, (const C<T>*)ax.HT);
+                       (C<T>*)out, ax, g, ilog2i(ax.g), (const C<T>*)ax.TA, (const C<T>*)ax.HTx);
     return hipGetLastError();
 }
 
 template <typename T, int P>
 hipError_t launch_ear(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
                       hipStream_t st) {
-    const size_t lds = cfp_lds_bytes(sizeof(T) == 8, ax.M, ax.g);
+    const size_t lds = cfp_lds_bytes(sizeof(T) == 8, ax.M, ax.g) + (size_t)g.qn * P * sizeof(C<T>);
     auto k = k_EAR<T, P>;
     hipError_t e = prep_lds((const void*)k, lds);
     if (e != hipSuccess) return e;
@@ -922,7 +984,7 @@ hipError_t launch_ear(const void* in, void* out, const AxisDev& ax, const PassGe
     if (blocks > (1 << 22)) blocks = 1 << 22;
     hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), lds, st, (const C<T>*)in,
                        (C<T>*)out, ax, g, accumulate, (T*)rho, ilog2i(ax.g), (const C<T>*)ax.TA,
-                       (const C<T>*)ax.Tf, (const C<T>*)ax.HT);
+                       (const C<T>*)ax.Tf, (const C<T>*)ax.HTx);
     return hipGetLastError();
 }
 
@@ -1105,7 +1167,7 @@ size_t cfp_lds_bytes(bool dbl, int M, int g) {
 
 hipError_t launch_pass_cfp(Kind kind, bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g,
                            int accumulate, void* rho, hipStream_t st) {
-    if (!cfp_applicable(kind, dbl, ax.M, ax.g) || !ax.HT || g.TS != cfp_tile_lines(ax.g) || g.qc < 1)
+    if (!cfp_applicable(kind, dbl, ax.M, ax.g) || !ax.HTx || g.TS != cfp_tile_lines(ax.g) || g.qc < 1)
         return hipErrorInvalidValue;
     if (g.Qin * g.ntiles * ((g.qn + g.qc - 1) / g.qc) >= (int64_t(1) << 31)) return hipErrorInvalidValue;
     return dbl ? launch_er_T<double>(kind, in, out, ax, g, accumulate, rho, st)

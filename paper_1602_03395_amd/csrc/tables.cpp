@@ -94,6 +94,34 @@ void build_ht(AxisTables& t, int64_t M, int64_t lam) {
             }
         }
     }
+    // Second copy for the forward register kernels. Their first cross-lane reduction step pairs
+    // lanes n2 and n2 ^ 1; the odd lane keeps the upper half of the P sums. When the odd lane's
+    // P values come with their halves exchanged, both lanes keep the lower half and send the upper
+    // one, so no per-lane selects are needed:
+    //   g >= P (transform, multiply, then reduce): the odd lane's input is modulated by (-1)^n1,
+    //     which moves its spectrum by P/2, so its table row is HT[n2][r ^ P/2];
+    //   g <  P (transform, multiply, inverse, then reduce): the odd lane's inverse output is moved
+    //     by P/2 when its row is modulated by (-1)^r.
+    t.HTx = t.HT;
+    const bool p2 = (P & (P - 1)) == 0;
+    if (p2 && P >= 2 && g >= 2) {
+        for (int64_t q = 0; q < lam; ++q) {
+            for (int64_t n2 = 1; n2 < g; n2 += 2) {
+                const size_t row = 2 * (size_t)((q * g + n2) * P);
+                for (int64_t r = 0; r < P; ++r) {
+                    const size_t d = row + 2 * (size_t)r;
+                    if (g >= P) {
+                        const size_t s = row + 2 * (size_t)(r ^ (P / 2));
+                        t.HTx[d] = t.HT[s];
+                        t.HTx[d + 1] = t.HT[s + 1];
+                    } else if (r & 1) {
+                        t.HTx[d] = -t.HT[d];
+                        t.HTx[d + 1] = -t.HT[d + 1];
+                    }
+                }
+            }
+        }
+    }
 }
 
 }  // namespace

@@ -66,8 +66,9 @@ def kernels_hash() -> str:
     return h.hexdigest()[:16]
 
 
-# pass kernels: k_E, k_E2 (power-of-two), k_Ect (3*2^k), k_EA*, k_A, k_AS (structured), adjoints
-PASS_KIND = re.compile(r"\bk_(EAH|EA|EH|AH|E|A)(?:2|ct|S|R)?<")
+# pass kernels: k_E, k_E2 (power-of-two), k_Ect (3*2^k), k_ER (register form), k_EA*, k_A,
+# k_AS / k_ASR / k_ASK (structured accumulates), k_AA (fused two-axis accumulate), adjoints
+PASS_KIND = re.compile(r"\bk_(EAH|EA|EH|AH|AA|E|A)(?:2|ct|S|R|SR|SK)?<")
 
 
 def _pass_dispatches(path: str, counter: str):
