@@ -309,6 +309,28 @@ template <typename T, int P, int CH>
 __device__ __forceinline__ void load_tile(const C<T>* __restrict__ in, C<T>* B, const PassGeom& g, const Tile& tl,
                                           int64_t qi, int M, const FDiv& fdM) {
     const int cnt = tl.nl * M;
+    if (g.S != 1 && (kThreads % tl.nl) == 0) {
+        // strided lines, nl | kThreads (every full tile): the thread's line l = tid mod nl is fixed
+        // and its points advance by kThreads / nl, so the offsets are one base plus a stride
+        const int tid = (int)threadIdx.x;
+        const int l = tid % tl.nl;
+        const int dn = kThreads / tl.nl;
+        const int n0 = tid / tl.nl;
+        const C<T>* src = in + ((qi * g.A + tl.a0) * M + n0) * g.S + tl.s0 + l;
+        const int64_t stride = (int64_t)dn * g.S;
+        C<T>* dst = B + l * M + n0;
+#pragma unroll
+        for (int k0 = 0; k0 < P; k0 += CH) {
+            C<T> v[CH];
+#pragma unroll
+            for (int k = 0; k < CH; ++k)
+                if (k0 + k < P && n0 + (k0 + k) * dn < M) v[k] = src[(k0 + k) * stride];
+#pragma unroll
+            for (int k = 0; k < CH; ++k)
+                if (k0 + k < P && n0 + (k0 + k) * dn < M) dst[(k0 + k) * dn] = v[k];
+        }
+        return;
+    }
 #pragma unroll
     for (int k0 = 0; k0 < P; k0 += CH) {
         C<T> v[CH];
@@ -393,11 +415,12 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
     C<T> wst[LP > 0 ? LP : 1];
     const C<T> fin = lane_twiddles_x<T, LP>(wst, n2, (const C<T>*)ax.tw, M);
     for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
-        const int64_t rr = bid >> 3;
-        const int ci = (int)(rr % nqc);
-        const int64_t tile = (rr / nqc) * 8 + (bid & 7);
+        // every id and index here is below 2^31 (checked on the host): 32-bit division
+        const unsigned rr = (unsigned)bid >> 3;
+        const int ci = (int)(rr % (unsigned)nqc);
+        const int64_t tile = (int64_t)((rr / (unsigned)nqc) * 8u + ((unsigned)bid & 7u));
         if (tile >= ntl) continue;  // uniform over the workgroup
-        const int64_t qi = tile / g.ntiles;
+        const int64_t qi = (int64_t)((unsigned)tile / (unsigned)g.ntiles);
         const int64_t tt = tile - qi * g.ntiles;
         const Tile tl = decode_tile(g, tt);
         const bool live = l < tl.nl;
@@ -534,7 +557,7 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
     int base = 0;
     for (int s = 0; s < lk; ++s) base += ((n2 >> s) & 1) * ((P >> s) >> 1);
     for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
-        const int64_t qi = bid / g.ntiles;
+        const int64_t qi = (int64_t)((unsigned)bid / (unsigned)g.ntiles);  // total < 2^31 (host check)
         const int64_t tt = bid - qi * g.ntiles;
         const Tile tl = decode_tile(g, tt);
         const FDiv fdM = tile_div(g, tl, M);
@@ -618,6 +641,28 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
     }
 }
 
+// Group decode of the structured accumulates: group index gi -> (qo, a, n0, s, r) with
+// gi = ((qo A + a) P + n0) S + s and r = (n0 lg) mod P. Every group index is below 2^31
+// (checked on the host), so the divisions are 32-bit.
+struct AccGroup {
+    int64_t row, qo, a, s;
+    int n0, r;
+};
+__device__ __forceinline__ AccGroup acc_group(unsigned gi, unsigned PS, unsigned S, unsigned A, int P, int lg) {
+    AccGroup o;
+    const unsigned row = gi / PS;
+    const unsigned rem = gi - row * PS;
+    const unsigned n0 = rem / S;
+    const unsigned qo = row / A;
+    o.row = row;
+    o.qo = qo;
+    o.a = row - qo * A;
+    o.s = rem - n0 * S;
+    o.n0 = (int)n0;
+    o.r = (P < 46341) ? (int)((n0 * (unsigned)lg) % (unsigned)P) : (int)(((int64_t)n0 * lg) % P);
+    return o;
+}
+
 // Structured accumulate in registers: one thread per group (qo, a, n0, s). For the outputs
 // nbar = n0 + P c (c < g) every term reads the same input sample r(n0), and the twiddle (presf)
 // satisfies Tf_q[n0 + P c] = Tf_q[n0] exp(2 pi i q c / g), so with j = (q - qb) mod g
@@ -637,13 +682,9 @@ __global__ __launch_bounds__(kThreads) void k_ASR(const C<T>* __restrict__ in, C
     const int qbr = g.qb % G;
     for (int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < ngroups;
          gi += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t row = gi / PS;  // (qo, a)
-        const int64_t rem = gi - row * PS;
-        const int n0 = (int)(rem / S);
-        const int64_t s = rem - (int64_t)n0 * S;
-        const int64_t qo = row / g.A;
-        const int64_t a = row - qo * g.A;
-        const int r = (int)(((int64_t)n0 * ax.lg) % P);
+        const AccGroup grp = acc_group((unsigned)gi, (unsigned)PS, (unsigned)S, (unsigned)g.A, P, ax.lg);
+        const int64_t row = grp.row, qo = grp.qo, a = grp.a, s = grp.s;
+        const int n0 = grp.n0, r = grp.r;
         const C<T>* src = in + (qo * g.qn * g.A + a) * PS + (int64_t)r * S + s;
         const C<T>* tf = Tf + (int64_t)g.qb * M + n0;
         C<T> h[G];
@@ -799,14 +840,9 @@ __global__ __launch_bounds__(kThreads) void k_ASK(const C<T>* __restrict__ in, C
     const int64_t nthreads = ngroups * K;
     for (int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gt < nthreads;
          gt += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t gi = gt / K;
-        const int64_t row = gi / PS;
-        const int64_t rem = gi - row * PS;
-        const int n0 = (int)(rem / S);
-        const int64_t s = rem - (int64_t)n0 * S;
-        const int64_t qo = row / g.A;
-        const int64_t a = row - qo * g.A;
-        const int r = (int)(((int64_t)n0 * ax.lg) % P);
+        const AccGroup grp = acc_group((unsigned)(gt / K), (unsigned)PS, (unsigned)S, (unsigned)g.A, P, ax.lg);
+        const int64_t row = grp.row, qo = grp.qo, a = grp.a, s = grp.s;
+        const int n0 = grp.n0, r = grp.r;
         const C<T>* src = in + (qo * g.qn * g.A + a) * PS + (int64_t)r * S + s;
         const C<T>* tf = Tf + (int64_t)g.qb * M + n0;
         C<T> h[8];
@@ -880,11 +916,12 @@ __global__ __launch_bounds__(kThreads) void k_EHR(const C<T>* __restrict__ in, C
     const int64_t ntl = g.Qin * g.ntiles;
     const int64_t total = ((ntl + 7) / 8) * 8 * nqc;  // XCD-aware order as in k_ER
     for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
-        const int64_t rr = bid >> 3;
-        const int ci = (int)(rr % nqc);
-        const int64_t tile = (rr / nqc) * 8 + (bid & 7);
+        // every id and index here is below 2^31 (checked on the host): 32-bit division
+        const unsigned rr = (unsigned)bid >> 3;
+        const int ci = (int)(rr % (unsigned)nqc);
+        const int64_t tile = (int64_t)((rr / (unsigned)nqc) * 8u + ((unsigned)bid & 7u));
         if (tile >= ntl) continue;
-        const int64_t qo = tile / g.ntiles;
+        const int64_t qo = (int64_t)((unsigned)tile / (unsigned)g.ntiles);
         const int64_t tt = tile - qo * g.ntiles;
         const Tile tl = decode_tile(g, tt);
         const bool live = l < tl.nl;
@@ -1169,7 +1206,7 @@ hipError_t launch_pass_cfp(Kind kind, bool dbl, const void* in, void* out, const
                            int accumulate, void* rho, hipStream_t st) {
     if (!cfp_applicable(kind, dbl, ax.M, ax.g) || !ax.HTx || g.TS != cfp_tile_lines(ax.g) || g.qc < 1)
         return hipErrorInvalidValue;
-    if (g.Qin * g.ntiles * ((g.qn + g.qc - 1) / g.qc) >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    if (((g.Qin * g.ntiles + 7) / 8) * 8 * ((g.qn + g.qc - 1) / g.qc) >= (int64_t(1) << 31)) return hipErrorInvalidValue;
     return dbl ? launch_er_T<double>(kind, in, out, ax, g, accumulate, rho, st)
                : launch_er_T<float>(kind, in, out, ax, g, accumulate, rho, st);
 }
