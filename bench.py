@@ -30,6 +30,7 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
+ADJOINT_SLOT0 = 32  # first pass-timing slot of the adjoint schedule (FX_ADJOINT_SLOT0 in include/fx.h)
 
 
 def pass_cost(p: dict, csize: int, outer_chunks: int = 1):
@@ -49,7 +50,7 @@ def pass_cost(p: dict, csize: int, outer_chunks: int = 1):
     qn = p.get("qn", lam)
     lines = p["Qin"] * p["A"] * p["S"]
     lg = lambda n: math.log2(n) if n > 1 else 0.0
-    if p.get("reg") and kind in ("E", "EA"):
+    if p.get("reg") and kind in ("E", "EA", "EH"):
         e_line = 6 * M + 5 * M * lg(P) + 6 * M + 2 * M + 5 * P * lg(P)
     else:
         e_line = 6 * M + 5 * M * lg(M) + 6 * M + 2 * (M - P) + 5 * P * lg(P) + 2 * P
@@ -328,7 +329,11 @@ def main():
     pass_rows = []
     seen = {}
     for i, (n_launch, tot_ms) in enumerate(passes):
-        p = dict(desc["passes"][i]) if i < len(desc["passes"]) else {"kind": "?"}
+        if n_launch == 0:
+            continue
+        # slots from ADJOINT_SLOT0 on time the passes of the adjoint schedule (gradient variant)
+        lst, j = (desc["passes"], i) if i < ADJOINT_SLOT0 else (desc.get("adjoint_passes", []), i - ADJOINT_SLOT0)
+        p = dict(lst[j]) if j < len(lst) else {"kind": "?"}
         key = f'{p["kind"]}#{seen.get(p["kind"], 0)}'
         seen[p["kind"]] = seen.get(p["kind"], 0) + 1
         avg_ms = tot_ms / max(n_launch, 1)

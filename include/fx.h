@@ -289,8 +289,12 @@ fx_status fx_batch_run(fx_batch* batch, const void* const* psi0, void* const* ps
  * launched on. fx_plan_pass_times waits for the recorded events and returns,
  * for each pass of the schedule in order (at most max entries; *n_passes gets
  * the count), the number of timed launches and their summed duration in
- * milliseconds, then clears the counters. Arrays are host memory.
+ * milliseconds, then clears the counters. Entries 0.. are the passes of the
+ * forward schedule ("passes" of fx_plan_describe); entries FX_ADJOINT_SLOT0..
+ * are those of the adjoint schedule ("adjoint_passes"); entries that were not
+ * run read 0 launches. Arrays are host memory.
  */
+#define FX_ADJOINT_SLOT0 32
 fx_status fx_plan_set_timing(fx_plan* plan, int enable);
 fx_status fx_plan_pass_times(fx_plan* plan, int32_t* n_passes, int64_t* launches, double* ms, int32_t max);
 

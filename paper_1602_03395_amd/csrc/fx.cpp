@@ -166,7 +166,7 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
         if (g.S == 1) g.ntiles = (g.A + g.TS - 1) / g.TS;
         else g.ntiles = g.A * ((g.S + g.TS - 1) / g.TS);
         g.max_blocks = p->persist > 0 ? p->persist * num_cus() : 0;
-        g.reg_a = (kind == Kind::A) && p->use_asr && asr_applicable(p->ax[ax].g, p->asr_max_g);
+        g.reg_a = (kind == Kind::A || kind == Kind::AH) && p->use_asr && asr_applicable(p->ax[ax].g, p->asr_max_g);
         if (reg && kind == Kind::EA) {
             g.qc = g.qn;  // the fused pass sums every magnification index inside the workgroup
         } else if (reg && kind == Kind::EH) {
@@ -370,7 +370,7 @@ fx_status ensure_workspace(fx_plan* p) {
 
 // Runs the op list of one block. src: input tensor, dst: final output; X/Y ping-pong.
 fx_status run_ops(fx_plan* p, const std::vector<Op>& ops, const void* src, void* dst, int accumulate, void* rho,
-                  hipStream_t st) {
+                  hipStream_t st, int slot0) {
     char* base = (char*)p->ws;
     void* bufs[2] = {base, base + (size_t)p->buf_elems * csize(p)};
     const void* cur = src;
@@ -393,7 +393,7 @@ fx_status run_ops(fx_plan* p, const std::vector<Op>& ops, const void* src, void*
                                          last ? rho : nullptr, st);
         if (p->timing) {
             FX_TRY_HIP(hipEventRecord(eb, st));
-            p->pending.push_back({(int)i, ea, eb});
+            p->pending.push_back({slot0 + (int)i, ea, eb});
         }
         if (e != hipSuccess) {
             set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));
@@ -429,7 +429,8 @@ fx_status run_box(fx_plan* p, const int qb[3], const int qn[3], const void* src,
         const bool first = (c == qb[outer]);
         const bool lastc = (c + step >= qb[outer] + qn[outer]);
         std::vector<Op> ops = build_ops(p, b2, n2, p->slices, adjoint);
-        fx_status s = run_ops(p, ops, src, dst, first ? accumulate : 1, lastc ? rho : nullptr, st);
+        fx_status s = run_ops(p, ops, src, dst, first ? accumulate : 1, lastc ? rho : nullptr, st,
+                              adjoint ? FX_ADJOINT_SLOT0 : 0);
         if (s != FX_OK) return s;
     }
     return FX_OK;
@@ -838,7 +839,6 @@ fx_status fx_plan_describe(const fx_plan* p, char* buf, size_t len) {
     if (!p || !buf || len == 0) { set_error("NULL argument"); return FX_EINVAL; }
     int qb[3] = {0, 0, 0}, qn[3] = {p->ax[0].lam, p->ax[1].lam, p->ax[2].lam};
     if (p->nact > 0 && p->schedule == FX_SCHED_PAPER) qn[p->act[p->nact - 1]] = (int)p->nb_outer;
-    std::vector<Op> ops = build_ops(p, qb, qn, p->slices, false);
     std::string s = "{\"schedule\":\"";
     s += (p->schedule == FX_SCHED_PAPER) ? "paper" : "axis_factorised";
     s += "\",\"precision\":\"";
@@ -849,8 +849,10 @@ fx_status fx_plan_describe(const fx_plan* p, char* buf, size_t len) {
         s += j ? "," : "";
         s += p->spectrum[3 - p->ndim + j] ? "\"table\"" : "\"free\"";
     }
-    s += "],\"passes\":[";
     static const char* names[] = {"E", "A", "EA", "EH", "AH", "EAH", "AA"};
+    for (int adj = 0; adj < 2; ++adj) {
+    std::vector<Op> ops = build_ops(p, qb, qn, p->slices, adj != 0);
+    s += adj ? "],\"adjoint_passes\":[" : "],\"passes\":[";
     for (size_t i = 0; i < ops.size(); ++i) {
         const Op& o = ops[i];
         const AxisDev& a = p->ax[o.axis];
@@ -872,6 +874,7 @@ fx_status fx_plan_describe(const fx_plan* p, char* buf, size_t len) {
             s += tmp;
         }
         s += "}";
+    }
     }
     s += "]}";
     std::snprintf(buf, len, "%s", s.c_str());

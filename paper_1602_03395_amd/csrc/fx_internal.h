@@ -142,10 +142,11 @@ hipError_t launch_pass_aa(bool dbl, const void* in, void* out, const AxisDev& au
 bool ehr_applicable(int M, int g);
 hipError_t launch_pass_ehr(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
                            hipStream_t st);
-// Structured accumulate (A) with one thread per output group and register accumulators (g <= 32).
+// Structured accumulate (A) and its adjoint (AH) in registers: one thread per output group for
+// g <= 8, g / 8 lanes per group for g = 16, 32, 64.
 bool asr_applicable(int g, int max_g);
-hipError_t launch_pass_asr(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
-                           void* rho, hipStream_t st);
+hipError_t launch_pass_asr(Kind kind, bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g,
+                           int accumulate, void* rho, hipStream_t st);
 
 void set_error(const std::string& msg);
 

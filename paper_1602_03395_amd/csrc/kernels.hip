@@ -741,8 +741,8 @@ hipError_t launch_pass(Kind kind, bool dbl, const void* in, void* out, const Axi
     if (g.qc > 0 && kind == Kind::EH) return launch_pass_ehr(dbl, in, out, ax, g, accumulate, st);
     if (g.qc > 0) return launch_pass_cfp(kind, dbl, in, out, ax, g, accumulate, rho, st);
     // the register accumulates decode their groups (up to 8 lanes each) with 32-bit integers
-    if (kind == Kind::A && g.reg_a && g.Qin * g.A * (int64_t)ax.P * g.S * 8 < (int64_t(1) << 31))
-        return launch_pass_asr(dbl, in, out, ax, g, accumulate, rho, st);
+    if ((kind == Kind::A || kind == Kind::AH) && g.reg_a && g.Qin * g.A * (int64_t)ax.P * g.S * 8 < (int64_t(1) << 31))
+        return launch_pass_asr(kind, dbl, in, out, ax, g, accumulate, rho, st);
     if (p2_applicable(kind, ax.M) && g.TS == p2_tile_lines(ax.M))
         return launch_pass_p2(kind, dbl, in, out, ax, g, accumulate, rho, st);
     if (ct_applicable(kind, ax.M) && g.TS == ct_tile_lines(ax.M))

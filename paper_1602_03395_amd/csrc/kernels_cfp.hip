@@ -354,17 +354,19 @@ __device__ __forceinline__ void load_tile(const C<T>* __restrict__ in, C<T>* B, 
 
 // Twiddles of lane_idft_x: stage s uses wst[s] = w (lower lane) or -conj(w) (upper lane), with
 // w = exp(2 pi i (n2 mod 2^s) / 2^(s+1)). Returns the lane's final rescale (see lane_idft_x).
-template <typename T, int LP>
+// With INV = false the same for the forward transform, w = exp(-2 pi i (n2 mod 2^s) / 2^(s+1)).
+template <typename T, int LP, bool INV = true>
 __device__ __forceinline__ C<T> lane_twiddles_x(C<T>* wst, int n2, const C<T>* tw, int M) {
     C<T> c = mk<T>(1, 0);
 #pragma unroll
     for (int s = 0; s < LP; ++s) {
-        const C<T> t = tw[(n2 & ((1 << s) - 1)) * (M >> (s + 1))];  // conj(w)
+        const C<T> t = tw[(n2 & ((1 << s) - 1)) * (M >> (s + 1))];  // exp(-2 pi i (n2 mod 2^s) / 2^(s+1))
+        const C<T> w = INV ? mk<T>(t.x, -t.y) : t;
         if ((n2 >> s) & 1) {
-            wst[s] = mk<T>(-t.x, -t.y);
+            wst[s] = mk<T>(-w.x, w.y);  // -conj(w)
             c = cmul<T>(c, wst[s]);
         } else {
-            wst[s] = mk<T>(t.x, -t.y);
+            wst[s] = w;
         }
     }
     return mk<T>(c.x, -c.y);
@@ -896,31 +898,159 @@ __global__ __launch_bounds__(kThreads) void k_ASK(const C<T>* __restrict__ in, C
     }
 }
 
+// AH (adjoint of A) in register form. For the group (qo, a, n0, s) of the forward structured
+// accumulate, the inputs y[c] = in[.., n0 + P c, ..] (c < g) give every term's output sample
+//   out_q[r(n0)] = conj(Tf_q[n0]) sum_c exp(-2 pi i q c / g) y[c] = conj(Tf_q[n0]) Yh[(q - qb) mod g],
+//   Yh[j] = sum_c exp(-2 pi i j c / g) exp(-2 pi i qb c / g) y[c],
+// the conjugate transpose of the forward group: one g-point forward transform per group, read
+// by every term. One thread per group (g <= 8).
+template <typename T, int G>
+__global__ __launch_bounds__(kThreads) void k_AHR(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
+                                                  PassGeom g, int accumulate) {
+    const int M = ax.M, P = ax.P;
+    const int64_t S = g.S;
+    const int64_t PS = (int64_t)P * S;
+    const int64_t ngroups = g.Qin * g.A * PS;
+    const int64_t step = g.A * PS;  // one magnification slice of the output
+    const C<T>* Tf = (const C<T>*)ax.Tf;
+    const C<T>* twg = (const C<T>*)ax.tw;
+    const int qbr = g.qb % G;
+    for (int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < ngroups;
+         gi += (int64_t)gridDim.x * blockDim.x) {
+        const AccGroup grp = acc_group((unsigned)gi, (unsigned)PS, (unsigned)S, (unsigned)g.A, P, ax.lg);
+        const C<T>* src = in + (grp.row * M + grp.n0) * S + grp.s;
+        C<T>* dst = out + (grp.qo * g.qn * g.A + grp.a) * PS + (int64_t)grp.r * S + grp.s;
+        const C<T>* tf = Tf + (int64_t)g.qb * M + grp.n0;
+        C<T> y[G];
+#pragma unroll
+        for (int c = 0; c < G; ++c) y[c] = src[(int64_t)c * PS];
+        if (qbr != 0) {
+#pragma unroll
+            for (int c = 1; c < G; ++c) y[c] = cmul<T>(y[c], twg[((qbr * c) % G) * P]);  // exp(-2 pi i qb c / g)
+        }
+        RegDFT<T, G, false>::run(y);
+        for (int i0 = 0; i0 < g.qn; i0 += G) {
+            C<T> t[G];
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+                if (i0 + j < g.qn) t[j] = tf[(int64_t)(i0 + j) * M];
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                if (i0 + j < g.qn) {
+                    C<T>* o = dst + (int64_t)(i0 + j) * step;
+                    C<T> v = cmulc<T>(y[j], t[j]);
+                    if (accumulate) v = cadd<T>(v, *o);
+                    *o = v;
+                }
+            }
+        }
+    }
+}
+
+// AH in register form for g = 8K (K = 2, 4, 8 lanes per group), the transpose of k_ASK: lane k
+// reads y[c1 + 8 bitrev(k)] (c1 < 8), a K-point forward transform across the lanes (decimation
+// in time on bit-reversed input) gives Z[c1] = sum_c2 exp(-2 pi i k c2 / K) y[c1 + 8 c2], the
+// twiddle exp(-2 pi i k c1 / g), and an 8-point transform over c1 leaves Yh[k + K m] (m < 8).
+template <typename T, int K>
+__global__ __launch_bounds__(kThreads) void k_AHK(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
+                                                  PassGeom g, int accumulate) {
+    constexpr int G = 8 * K;
+    constexpr int LK = (K == 8) ? 3 : (K == 4) ? 2 : 1;
+    const int M = ax.M, P = ax.P;
+    const int64_t S = g.S;
+    const int64_t PS = (int64_t)P * S;
+    const int64_t ngroups = g.Qin * g.A * PS;
+    const int64_t step = g.A * PS;
+    const C<T>* Tf = (const C<T>*)ax.Tf;
+    const C<T>* twg = (const C<T>*)ax.tw;
+    const int k = (int)(threadIdx.x & (K - 1));  // the grid stride is a multiple of K
+    int kr = 0;                                  // bitrev_LK(k)
+    for (int b = 0; b < LK; ++b) kr |= ((k >> b) & 1) << (LK - 1 - b);
+    // cross-lane stage twiddles (select-free form; its rescale goes into w1)
+    C<T> wst[LK];
+    const C<T> fin = lane_twiddles_x<T, LK, false>(wst, k, twg, M);
+    C<T> w1[8];  // exp(-2 pi i k c1 / g) times the rescale
+#pragma unroll
+    for (int c1 = 0; c1 < 8; ++c1) w1[c1] = cmul<T>(twg[((k * c1) % G) * P], fin);
+    const int qbr = g.qb % G;
+    const int64_t nthreads = ngroups * K;
+    for (int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gt < nthreads;
+         gt += (int64_t)gridDim.x * blockDim.x) {
+        const AccGroup grp = acc_group((unsigned)(gt / K), (unsigned)PS, (unsigned)S, (unsigned)g.A, P, ax.lg);
+        const C<T>* src = in + (grp.row * M + grp.n0) * S + grp.s;
+        C<T>* dst = out + (grp.qo * g.qn * g.A + grp.a) * PS + (int64_t)grp.r * S + grp.s;
+        const C<T>* tf = Tf + (int64_t)g.qb * M + grp.n0;
+        C<T> h[8];
+#pragma unroll
+        for (int c1 = 0; c1 < 8; ++c1) h[c1] = src[(int64_t)(c1 + 8 * kr) * PS];
+        if (qbr != 0) {
+#pragma unroll
+            for (int c1 = 0; c1 < 8; ++c1) h[c1] = cmul<T>(h[c1], twg[((qbr * (c1 + 8 * kr)) % G) * P]);
+        }
+#pragma unroll
+        for (int st = 0; st < LK; ++st) {
+#pragma unroll
+            for (int c1 = 0; c1 < 8; ++c1) h[c1] = cfma<T>(h[c1], wst[st], shfl_xor_c<T>(h[c1], 1 << st));
+        }
+#pragma unroll
+        for (int c1 = 0; c1 < 8; ++c1) h[c1] = cmul<T>(h[c1], w1[c1]);
+        RegDFT<T, 8, false>::run(h);
+        for (int i0 = 0; i0 < g.qn; i0 += G) {
+            C<T> t[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int i = i0 + k + K * m;
+                if (i < g.qn) t[m] = tf[(int64_t)i * M];
+            }
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int i = i0 + k + K * m;
+                if (i < g.qn) {
+                    C<T>* o = dst + (int64_t)i * step;
+                    C<T> v = cmulc<T>(h[m], t[m]);
+                    if (accumulate) v = cadd<T>(v, *o);
+                    *o = v;
+                }
+            }
+        }
+    }
+}
+
 // EH (adjoint of E, summed over q) in register form, power-of-two P <= g. For lane (line, n2):
 //   x[g n1 + n2] = sum_q conj(TA_q[g n1]) sum_r exp(2 pi i n1 r / P) conj(HT_q[n2][r]) Y_q[r],
 //   Y_q[r] = sum_u exp(-2 pi i r u / P) y_q[u],
 // the conjugate transpose of every step of the register E, in reverse order. Each lane forms the
-// P-point transform of the line's P inputs itself (the G lanes of a line read the same addresses).
-// Workgroups take a chunk of qc terms; with several chunks per tile they add into the
-// (pre-cleared) output with atomics.
+// P-point transform of the line's P inputs itself (the G lanes of a line read the same values).
+// The inputs and premultiply values of kEhrStage terms at a time are staged in LDS with all their
+// loads in flight together. Workgroups take a chunk of qc terms; with several chunks per tile
+// they add into the (pre-cleared) output with atomics.
+constexpr int kEhrStage = 4;
+
 template <typename T, int P>
 __global__ __launch_bounds__(kThreads) void k_EHR(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
                                                   PassGeom g, int accumulate, int lgG, int atomic,
                                                   const C<T>* __restrict__ TA, const C<T>* __restrict__ HT) {
+    extern __shared__ __align__(16) unsigned char smem[];
     const int M = ax.M;
     const int G = 1 << lgG;
+    const int TS = kThreads >> lgG;  // lines per tile
+    C<T>* Ys = (C<T>*)smem;                 // [kEhrStage][TS][P]
+    C<T>* TAs = Ys + kEhrStage * TS * P;    // [kEhrStage][P]
     const int l = (int)threadIdx.x >> lgG;
     const int n2 = (int)threadIdx.x & (G - 1);
+    const int tid = (int)threadIdx.x;
     const int qc = g.qc;
     const int nqc = (g.qn + qc - 1) / qc;
     const int64_t ntl = g.Qin * g.ntiles;
     const int64_t total = ((ntl + 7) / 8) * 8 * nqc;  // XCD-aware order as in k_ER
+    // staged elements per thread: kEhrStage TS P / kThreads = kEhrStage P / G <= kEhrStage
+    constexpr int kPer = kEhrStage;
     for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
         // every id and index here is below 2^31 (checked on the host): 32-bit division
         const unsigned rr = (unsigned)bid >> 3;
         const int ci = (int)(rr % (unsigned)nqc);
         const int64_t tile = (int64_t)((rr / (unsigned)nqc) * 8u + ((unsigned)bid & 7u));
-        if (tile >= ntl) continue;
+        if (tile >= ntl) continue;  // uniform over the workgroup
         const int64_t qo = (int64_t)((unsigned)tile / (unsigned)g.ntiles);
         const int64_t tt = tile - qo * g.ntiles;
         const Tile tl = decode_tile(g, tt);
@@ -930,25 +1060,58 @@ __global__ __launch_bounds__(kThreads) void k_EHR(const C<T>* __restrict__ in, C
         C<T> acc[P];
 #pragma unroll
         for (int i = 0; i < P; ++i) acc[i] = mk<T>(0, 0);
-        if (live) {
-            for (int q = qlo; q < qhi; ++q) {
-                const int64_t si = qo * g.qn + (q - g.qb);
-                C<T> y[P];
+        for (int q0 = qlo; q0 < qhi; q0 += kEhrStage) {
+            const int nq = min(kEhrStage, qhi - q0);
+            const int cnt = nq * TS * P;
+            C<T> v[kPer];
+            int dst[kPer];
 #pragma unroll
-                for (int u = 0; u < P; ++u) {
-                    const int64_t off = (g.S == 1) ? ((si * g.A + tl.a0 + l) * P + u)
-                                                   : (((si * g.A + tl.a0) * P + u) * g.S + tl.s0 + l);
-                    y[u] = in[off];
+            for (int k = 0; k < kPer; ++k) {
+                const int e = tid + k * kThreads;
+                dst[k] = -1;
+                v[k] = mk<T>(0, 0);
+                if (e < cnt) {
+                    const int qq = e / (TS * P);
+                    const int rem = e - qq * (TS * P);
+                    // contiguous lines: u fastest; strided lines: the line index fastest
+                    const int ll = (g.S == 1) ? rem / P : rem % TS;
+                    const int u = (g.S == 1) ? rem % P : rem / TS;
+                    if (ll < tl.nl) {
+                        const int64_t si = qo * g.qn + (q0 + qq - g.qb);
+                        const int64_t off = (g.S == 1) ? ((si * g.A + tl.a0 + ll) * P + u)
+                                                       : (((si * g.A + tl.a0) * P + u) * g.S + tl.s0 + ll);
+                        v[k] = in[off];
+                        dst[k] = (qq * TS + ll) * P + u;
+                    }
                 }
-                RegDFT<T, P, false>::run(y);
-                const C<T>* h = HT + ((int64_t)q * G + n2) * P;
-#pragma unroll
-                for (int r = 0; r < P; ++r) y[r] = cmulc<T>(y[r], h[r]);
-                RegDFT<T, P, true>::run(y);
-                const C<T>* ta = TA + (int64_t)q * M;
-#pragma unroll
-                for (int i = 0; i < P; ++i) acc[i] = cfmac<T>(acc[i], y[i], ta[i << lgG]);
             }
+            C<T> tav = mk<T>(0, 0);
+            if (tid < nq * P) tav = TA[(int64_t)(q0 + tid / P) * M + ((tid % P) << lgG)];
+#pragma unroll
+            for (int k = 0; k < kPer; ++k)
+                if (dst[k] >= 0) Ys[dst[k]] = v[k];
+            if (tid < nq * P) TAs[tid] = tav;
+            __syncthreads();
+            if (live) {
+                for (int qq = 0; qq < nq; ++qq) {
+                    const int q = q0 + qq;
+                    C<T> y[P];
+                    const C<T>* ys = Ys + (qq * TS + l) * P;
+#pragma unroll
+                    for (int u = 0; u < P; ++u) y[u] = ys[u];
+                    RegDFT<T, P, false>::run(y);
+                    const C<T>* h = HT + ((int64_t)q * G + n2) * P;
+#pragma unroll
+                    for (int r = 0; r < P; ++r) y[r] = cmulc<T>(y[r], h[r]);
+                    RegDFT<T, P, true>::run(y);
+                    const C<T>* ta = TAs + qq * P;
+#pragma unroll
+                    for (int i = 0; i < P; ++i) acc[i] = cfmac<T>(acc[i], y[i], ta[i]);
+                }
+            }
+            __syncthreads();  // the next round overwrites the staged values
+        }
+        if (live) {
 #pragma unroll
             for (int i = 0; i < P; ++i) {
                 const int n = (i << lgG) + n2;
@@ -1082,6 +1245,45 @@ hipError_t launch_ask(const void* in, void* out, const AxisDev& ax, const PassGe
     return hipGetLastError();
 }
 
+template <typename T, int G>
+hipError_t launch_ahr(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
+                      hipStream_t st) {
+    const int64_t ngroups = g.Qin * g.A * (int64_t)ax.P * g.S;
+    const int bs = acc_block(ngroups);
+    int64_t blocks = (ngroups + bs - 1) / bs;
+    if (blocks > (1 << 20)) blocks = 1 << 20;
+    hipLaunchKernelGGL((k_AHR<T, G>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(bs), 0, st,
+                       (const C<T>*)in, (C<T>*)out, ax, g, accumulate);
+    return hipGetLastError();
+}
+
+template <typename T, int K>
+hipError_t launch_ahk(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
+                      hipStream_t st) {
+    const int64_t nthreads = g.Qin * g.A * (int64_t)ax.P * g.S * K;
+    const int bs = acc_block(nthreads);
+    int64_t blocks = (nthreads + bs - 1) / bs;
+    if (blocks > (1 << 20)) blocks = 1 << 20;
+    hipLaunchKernelGGL((k_AHK<T, K>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(bs), 0, st,
+                       (const C<T>*)in, (C<T>*)out, ax, g, accumulate);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ahr_T(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
+                        hipStream_t st) {
+    switch (ax.g) {
+        case 64: return launch_ahk<T, 8>(in, out, ax, g, accumulate, st);
+        case 1: return launch_ahr<T, 1>(in, out, ax, g, accumulate, st);
+        case 2: return launch_ahr<T, 2>(in, out, ax, g, accumulate, st);
+        case 4: return launch_ahr<T, 4>(in, out, ax, g, accumulate, st);
+        case 8: return launch_ahr<T, 8>(in, out, ax, g, accumulate, st);
+        case 16: return launch_ahk<T, 2>(in, out, ax, g, accumulate, st);
+        case 32: return launch_ahk<T, 4>(in, out, ax, g, accumulate, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 hipError_t launch_asr_T(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
                         hipStream_t st) {
@@ -1104,9 +1306,12 @@ bool asr_applicable(int g, int max_g) {
     return (g == 1 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64) && g <= max_g;
 }
 
-hipError_t launch_pass_asr(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
-                           void* rho, hipStream_t st) {
-    if (!asr_applicable(ax.g, 64)) return hipErrorInvalidValue;
+hipError_t launch_pass_asr(Kind kind, bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g,
+                           int accumulate, void* rho, hipStream_t st) {
+    if (!asr_applicable(ax.g, 64) || (kind != Kind::A && kind != Kind::AH)) return hipErrorInvalidValue;
+    if (kind == Kind::AH)
+        return dbl ? launch_ahr_T<double>(in, out, ax, g, accumulate, st)
+                   : launch_ahr_T<float>(in, out, ax, g, accumulate, st);
     return dbl ? launch_asr_T<double>(in, out, ax, g, accumulate, rho, st)
                : launch_asr_T<float>(in, out, ax, g, accumulate, rho, st);
 }
@@ -1125,7 +1330,8 @@ hipError_t launch_ehr(const void* in, void* out, const AxisDev& ax, const PassGe
     int64_t blocks = ((g.Qin * g.ntiles + 7) / 8) * 8 * nqc;
     if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = (g.max_blocks + 7) / 8 * 8;
     if (blocks > (1 << 22)) blocks = 1 << 22;
-    hipLaunchKernelGGL((k_EHR<T, P>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), 0, st,
+    const size_t lds = (size_t)kEhrStage * P * ((kThreads >> ilog2i(ax.g)) + 1) * sizeof(C<T>);
+    hipLaunchKernelGGL((k_EHR<T, P>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), lds, st,
                        (const C<T>*)in, (C<T>*)out, ax, g, accumulate, ilog2i(ax.g), atomic, (const C<T>*)ax.TA,
                        (const C<T>*)ax.HT);
     return hipGetLastError();

@@ -90,8 +90,9 @@ fx_status validate(const fx_problem* pr);
 void workspace_layout(const fx_plan* p, int64_t slices, int64_t* nb, int64_t* buf, size_t* need);
 fx_status plan_setup_workspace(fx_plan* p, int64_t slices);
 fx_status ensure_workspace(fx_plan* p);
+// slot0: first timing slot of the list (0 forward, FX_ADJOINT_SLOT0 adjoint)
 fx_status run_ops(fx_plan* p, const std::vector<Op>& ops, const void* src, void* dst, int accumulate, void* rho,
-                  hipStream_t st);
+                  hipStream_t st, int slot0);
 fx_status run_box(fx_plan* p, const int qb[3], const int qn[3], const void* src, void* dst, int accumulate,
                   void* rho, bool adjoint, hipStream_t st);
 fx_status check_ptr(const void* ptr, const char* what);

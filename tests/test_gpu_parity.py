@@ -153,6 +153,40 @@ def test_adjoint_matches_oracle(fx, shape, lam, schedule):
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
+# g = gcd(lam, M) of 16, 32 and 64: the adjoint accumulate with g / 8 lanes per group
+@pytest.mark.parametrize("shape,lam", [((64,), (16,)), ((24, 64), (3, 32)), ((128,), (64,)), ((48, 40), (16, 2))])
+def test_adjoint_lane_groups_match_oracle(fx, shape, lam):
+    say("adjoint lanes", shape, lam)
+    dx = tuple(1.0 for _ in shape)
+    y_np = workloads.random_field(shape, 33)
+    plan = fx.get_plan(shape, dx, 1.0, 7.0, lam)
+    g = plan.expand_adjoint(torch.from_numpy(y_np).cuda()).cpu().numpy()
+    assert rel(g, oracle.expand_adjoint(y_np, dx, 1.0, 7.0, lam)) <= TOL64
+
+
+def test_adjoint_fp32_form_matches_oracle(fx):
+    shape, lam, dx = (48, 64), (4, 32), (1.0, 1.0)
+    say("adjoint fp32", shape, lam)
+    y_np = workloads.random_field(shape, 34)
+    plan = fx.get_plan(shape, dx, 1.0, 9.0, lam, dtype=torch.complex64)
+    g = plan.expand_adjoint(torch.from_numpy(y_np).to(torch.complex64).cuda()).cpu().numpy()
+    assert rel(g, oracle.expand_adjoint(y_np, dx, 1.0, 9.0, lam)) <= TOL32_RHO
+
+
+def test_adjoint_blocked_outer_axis_matches_oracle(fx, monkeypatch):
+    # a tiny workspace splits the outer magnification index into blocks whose first index is not
+    # a multiple of g = 32: every block's adjoint accumulate carries the phase of its offset
+    monkeypatch.setenv("FX_WORKSPACE_MB", "1")
+    shape, lam, dx = (128, 512), (4, 32), (1.0, 1.0)
+    say("adjoint blocked", shape, lam)
+    y_np = workloads.random_field(shape, 35)
+    plan = fx.Plan(shape, dx, 1.0, 11.0, lam)
+    import json
+    assert json.loads(plan.describe())["outer_block"] < 32
+    g = plan.expand_adjoint(torch.from_numpy(y_np).cuda()).cpu().numpy()
+    assert rel(g, oracle.expand_adjoint(y_np, dx, 1.0, 11.0, lam)) <= TOL64
+
+
 def test_autograd_gradient_matches_oracle_and_fd(fx):
     shape, lam, dx, t = (16, 20), (3, 2), (1.0, 1.0), 6.0
     say("autograd", shape, lam)
