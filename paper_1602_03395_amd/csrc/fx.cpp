@@ -110,7 +110,7 @@ size_t csize(const fx_plan* p) { return p->dbl ? 16 : 8; }
 
 bool use_cfp(const fx_plan* p, Kind kind, const AxisDev& a) {
     return p->use_cfp && a.HT != nullptr && cfp_applicable(kind, p->dbl, a.M, a.g) &&
-           (int64_t)(cfp_lds_bytes(p->dbl, a.M, a.g) + (size_t)a.lam * (a.M / a.g) * (p->dbl ? 16 : 8)) <=
+           (int64_t)(cfp_lds_bytes(p->dbl, a.M, a.g) + ((size_t)a.lam * (a.M / a.g) + 4 * (size_t)a.M) * (p->dbl ? 16 : 8)) <=
                lds_limit_bytes();
 }
 
@@ -159,22 +159,19 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
         g.Qin = qin;
         g.qb = qb[ax];
         g.qn = qn[ax];
-        const bool reg = use_cfp(p, kind, p->ax[ax]) ||
-                         (kind == Kind::EH && p->use_cfp && p->ax[ax].HT != nullptr &&
-                          ehr_applicable(p->ax[ax].M, p->ax[ax].g));
-        g.TS = reg ? cfp_tile_lines(p->ax[ax].g) : choose_ts(p, kind, p->ax[ax].M, g.A, g.S);
+        const bool reg_eh = kind == Kind::EH && p->use_cfp && p->ax[ax].HT != nullptr && qn[ax] <= 64 &&
+                            ehr_applicable(p->ax[ax].M, p->ax[ax].g);
+        const bool reg = use_cfp(p, kind, p->ax[ax]) || reg_eh;
+        g.TS = reg_eh ? ehr_tile_lines(p->ax[ax].g)
+                      : reg ? cfp_tile_lines(p->ax[ax].g) : choose_ts(p, kind, p->ax[ax].M, g.A, g.S);
         if (g.S == 1) g.ntiles = (g.A + g.TS - 1) / g.TS;
         else g.ntiles = g.A * ((g.S + g.TS - 1) / g.TS);
         g.max_blocks = p->persist > 0 ? p->persist * num_cus() : 0;
         g.reg_a = (kind == Kind::A || kind == Kind::AH) && p->use_asr && asr_applicable(p->ax[ax].g, p->asr_max_g);
         if (reg && kind == Kind::EA) {
             g.qc = g.qn;  // the fused pass sums every magnification index inside the workgroup
-        } else if (reg && kind == Kind::EH) {
-            // chunks of the sum over q per workgroup (several chunks add with atomics)
-            const int64_t base = g.Qin * g.ntiles;
-            const int64_t want = std::max<int64_t>(1, (int64_t)p->ehr_blocks);
-            const int64_t chunks = std::max<int64_t>(1, std::min<int64_t>(g.qn, want / std::max<int64_t>(1, base)));
-            g.qc = (int)((g.qn + chunks - 1) / chunks);
+        } else if (reg_eh) {
+            g.qc = g.qn;  // the waves of a workgroup share the terms and add through LDS
         } else if (reg) {
             // magnification indices per workgroup: as many as keep >= cfp_blocks workgroups
             const int64_t base = g.Qin * g.ntiles;
@@ -590,8 +587,6 @@ fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_pla
     if (const char* e = std::getenv("FX_ASR_MAXG")) p->asr_max_g = std::max(1, std::atoi(e));
     p->cfp_blocks = 2 * num_cus();
     if (const char* e = std::getenv("FX_CFP_BLOCKS")) p->cfp_blocks = std::max(1, std::atoi(e));
-    p->ehr_blocks = num_cus();
-    if (const char* e = std::getenv("FX_EHR_BLOCKS")) p->ehr_blocks = std::max(1, std::atoi(e));
     plan_setup_workspace(p, 1);
     *out = p;
     return FX_OK;

@@ -37,7 +37,7 @@ struct AxisDev {
     const void* TB = nullptr;
     const void* Tf = nullptr;
     const void* tw = nullptr;
-    const void* HT = nullptr;  // [lam][g][P] chirp-folded table of the register E kernel (or null)
+    const void* HT = nullptr;  // [lam][P][g] chirp-folded table of the register E kernel (or null)
     const void* HTx = nullptr; // HT arranged for the select-free first reduction step (or null)
     int M = 1;        // axis length
     int P = 1;        // M / g: number of distinct n'' values (output-pruned length)
@@ -105,7 +105,7 @@ int lds_limit_bytes();
 // Host-built FP64 tables (tables.cpp).
 struct AxisTables {
     std::vector<double> TA, TB, Tf, tw;  // interleaved re,im; [lam][M] for TA/TB/Tf, [M] for tw
-    std::vector<double> HT;              // [lam][g][P] when requested, else empty
+    std::vector<double> HT;              // [lam][P][g] when requested, else empty
     std::vector<double> HTx;             // HT for odd n2 lanes swapped or sign-modulated (see build_ht)
 };
 struct AxisParams {
@@ -138,8 +138,9 @@ int aa_tile_groups(int gu, int gv);
 size_t aa_lds_bytes(bool dbl, int gu, int gv);
 hipError_t launch_pass_aa(bool dbl, const void* in, void* out, const AxisDev& au, const AxisDev& av, const AAGeom& g,
                           int accumulate, void* rho, hipStream_t st);
-// Adjoint of E in register form (power-of-two P <= g <= 64, P <= 16).
+// Adjoint of E in register form (power-of-two P <= g <= 64, P <= 16): 64 / g lines per workgroup.
 bool ehr_applicable(int M, int g);
+int ehr_tile_lines(int g);
 hipError_t launch_pass_ehr(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
                            hipStream_t st);
 // Structured accumulate (A) and its adjoint (AH) in registers: one thread per output group for

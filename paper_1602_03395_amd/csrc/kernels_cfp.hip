@@ -387,15 +387,38 @@ __device__ __forceinline__ C<T> lane_idft_x(C<T> a, const C<T>* wst, C<T> fin) {
     return cmul<T>(a, fin);
 }
 
+// Terms whose chirp-folded table rows (M values each) are staged in LDS at a time.
+constexpr int kErStage = 4;
+
+// Copies cnt contiguous values into LDS, the loads of every chunk of 8 per thread issued before
+// their stores.
+template <typename T>
+__device__ __forceinline__ void copy_to_lds(C<T>* dst, const C<T>* __restrict__ src, int cnt) {
+    for (int e0 = 0; e0 < cnt; e0 += 8 * kThreads) {
+        C<T> v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = e0 + (int)threadIdx.x + k * kThreads;
+            v[k] = (e < cnt) ? src[e] : mk<T>(0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = e0 + (int)threadIdx.x + k * kThreads;
+            if (e < cnt) dst[e] = v[k];
+        }
+    }
+}
+
 template <typename T, int P, bool LANEINV>
 __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
                                                  PassGeom g, int lgG, const C<T>* __restrict__ TA,
                                                  const C<T>* __restrict__ HT) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int LP = (P >= 32) ? 5 : (P >= 16) ? 4 : (P >= 8) ? 3 : (P >= 4) ? 2 : (P >= 2) ? 1 : 0;
-    C<T>* B = (C<T>*)smem;        // tile of strided lines: TS lines x M points
-    C<T>* TAs = B + kThreads * P;  // TA_q[g i] of the workgroup's qc terms, [q - qlo][i]
     const int M = ax.M;
+    C<T>* B = (C<T>*)smem;          // tile of strided lines: TS lines x M points
+    C<T>* TAs = B + kThreads * P;    // TA_q[g i] of the workgroup's qc terms, [q - qlo][i]
+    C<T>* Hs = TAs + g.qc * P;       // table rows of kErStage terms, [q - q0][r][n2]
     const int G = 1 << lgG;
     const int l = (int)threadIdx.x >> lgG;
     const int n2 = (int)threadIdx.x & (G - 1);
@@ -433,6 +456,16 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
         const int ti = (int)threadIdx.x;
         C<T> tav = mk<T>(0, 0);
         if (ti < nta) tav = TA[(int64_t)(qlo + ti / P) * M + ((ti % P) << lgG)];
+        // the first round's table rows: their loads go out with the tile's
+        const int nq0 = min(kErStage, qhi - qlo);
+        const int hcnt = nq0 * M;
+        const C<T>* hsrc = HT + (int64_t)qlo * M;
+        C<T> hv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = ti + k * kThreads;
+            hv[k] = (e < hcnt) ? hsrc[e] : mk<T>(0, 0);
+        }
         C<T> x[P];
         if (g.S == 1) {
             // contiguous lines: lane n2 reads x[g i + n2] directly (G consecutive lanes per i)
@@ -445,6 +478,12 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
         }
         if (ti < nta) TAs[ti] = tav;
         for (int e = ti + kThreads; e < nta; e += kThreads) TAs[e] = TA[(int64_t)(qlo + e / P) * M + ((e % P) << lgG)];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = ti + k * kThreads;
+            if (e < hcnt) Hs[e] = hv[k];
+        }
+        if (hcnt > 8 * kThreads) copy_to_lds<T>(Hs + 8 * kThreads, hsrc + 8 * kThreads, hcnt - 8 * kThreads);
         __syncthreads();
         if (g.S != 1) {
 #pragma unroll
@@ -455,14 +494,20 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
             for (int i = 1; i < P; i += 2) x[i] = mk<T>(-x[i].x, -x[i].y);
         }
         for (int q = qlo; q < qhi; ++q) {
+            if (q > qlo && (q - qlo) % kErStage == 0) {
+                // next round of table rows (the previous round's reads are done first)
+                __syncthreads();
+                copy_to_lds<T>(Hs, HT + (int64_t)q * M, min(kErStage, qhi - q) * M);
+                __syncthreads();
+            }
             const C<T>* ta = TAs + (q - qlo) * P;
-            const C<T>* h = HT + ((int64_t)q * G + n2) * P;
+            const C<T>* h = Hs + ((q - qlo) % kErStage) * M + n2;
             C<T> v[P];
 #pragma unroll
             for (int i = 0; i < P; ++i) v[i] = cmul<T>(x[i], ta[i]);
             RegDFT<T, P, false>::run(v);
 #pragma unroll
-            for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r]);
+            for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r << lgG]);
             if constexpr (LANEINV) {
                 // sum over the lanes first, then one inverse transform across the P lanes
                 reduce_scatter_x<T, P>(v, n2, lgG);
@@ -585,14 +630,14 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
         __syncthreads();
         for (int q = g.qb; q < g.qb + g.qn; ++q) {
             const C<T>* ta = TAs + (q - g.qb) * P;
-            const C<T>* h = HT + ((int64_t)q * G + n2) * P;
+            const C<T>* h = HT + (int64_t)q * M + n2;
             const C<T>* tf = Tf + (int64_t)q * M + n2;
             C<T> v[P];
 #pragma unroll
             for (int i = 0; i < P; ++i) v[i] = cmul<T>(x[i], ta[i]);
             RegDFT<T, P, false>::run(v);
 #pragma unroll
-            for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r]);
+            for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r << lgG]);
             if (scatter) {
                 reduce_scatter_x<T, P>(v, n2, lgG);
                 C<T> s0 = v[0];
@@ -1021,119 +1066,80 @@ __global__ __launch_bounds__(kThreads) void k_AHK(const C<T>* __restrict__ in, C
 //   Y_q[r] = sum_u exp(-2 pi i r u / P) y_q[u],
 // the conjugate transpose of every step of the register E, in reverse order. Each lane forms the
 // P-point transform of the line's P inputs itself (the G lanes of a line read the same values).
-// The inputs and premultiply values of kEhrStage terms at a time are staged in LDS with all their
-// loads in flight together. Workgroups take a chunk of qc terms; with several chunks per tile
-// they add into the (pre-cleared) output with atomics.
-constexpr int kEhrStage = 4;
+// A workgroup holds the 64 / g lines of one wavefront kEhWaves times: wave w sums the terms
+// q = qb + w (mod kEhWaves), and the partial sums of the waves are added through LDS, so every
+// output is written once (no atomics, no clearing pass).
+constexpr int kEhWaves = 8;
 
 template <typename T, int P>
-__global__ __launch_bounds__(kThreads) void k_EHR(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
-                                                  PassGeom g, int accumulate, int lgG, int atomic,
-                                                  const C<T>* __restrict__ TA, const C<T>* __restrict__ HT) {
+__global__ __launch_bounds__(kEhWaves * kWave) void k_EHR(const C<T>* __restrict__ in, C<T>* __restrict__ out,
+                                                         AxisDev ax, PassGeom g, int accumulate, int lgG,
+                                                         const C<T>* __restrict__ TA, const C<T>* __restrict__ HT) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int M = ax.M;
     const int G = 1 << lgG;
-    const int TS = kThreads >> lgG;  // lines per tile
-    C<T>* Ys = (C<T>*)smem;                 // [kEhrStage][TS][P]
-    C<T>* TAs = Ys + kEhrStage * TS * P;    // [kEhrStage][P]
-    const int l = (int)threadIdx.x >> lgG;
-    const int n2 = (int)threadIdx.x & (G - 1);
+    C<T>* Red = (C<T>*)smem;                    // [kEhWaves][P][kWave] partial sums
+    C<T>* TAs = Red + kEhWaves * P * kWave;     // [q - qb][i] premultiply values of every term
     const int tid = (int)threadIdx.x;
-    const int qc = g.qc;
-    const int nqc = (g.qn + qc - 1) / qc;
-    const int64_t ntl = g.Qin * g.ntiles;
-    const int64_t total = ((ntl + 7) / 8) * 8 * nqc;  // XCD-aware order as in k_ER
-    // staged elements per thread: kEhrStage TS P / kThreads = kEhrStage P / G <= kEhrStage
-    constexpr int kPer = kEhrStage;
+    const int w = tid / kWave;
+    const int lane = tid % kWave;
+    const int l = lane >> lgG;
+    const int n2 = lane & (G - 1);
+    for (int e = tid; e < g.qn * P; e += kEhWaves * kWave)
+        TAs[e] = TA[(int64_t)(g.qb + e / P) * M + ((e % P) << lgG)];
+    __syncthreads();
+    const int64_t total = g.Qin * g.ntiles;  // < 2^31 (host check)
     for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
-        // every id and index here is below 2^31 (checked on the host): 32-bit division
-        const unsigned rr = (unsigned)bid >> 3;
-        const int ci = (int)(rr % (unsigned)nqc);
-        const int64_t tile = (int64_t)((rr / (unsigned)nqc) * 8u + ((unsigned)bid & 7u));
-        if (tile >= ntl) continue;  // uniform over the workgroup
-        const int64_t qo = (int64_t)((unsigned)tile / (unsigned)g.ntiles);
-        const int64_t tt = tile - qo * g.ntiles;
+        const int64_t qo = (int64_t)((unsigned)bid / (unsigned)g.ntiles);
+        const int64_t tt = bid - qo * g.ntiles;
         const Tile tl = decode_tile(g, tt);
         const bool live = l < tl.nl;
-        const int qlo = g.qb + ci * qc;
-        const int qhi = min(qlo + qc, g.qb + g.qn);
         C<T> acc[P];
 #pragma unroll
         for (int i = 0; i < P; ++i) acc[i] = mk<T>(0, 0);
-        for (int q0 = qlo; q0 < qhi; q0 += kEhrStage) {
-            const int nq = min(kEhrStage, qhi - q0);
-            const int cnt = nq * TS * P;
-            C<T> v[kPer];
-            int dst[kPer];
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const int e = tid + k * kThreads;
-                dst[k] = -1;
-                v[k] = mk<T>(0, 0);
-                if (e < cnt) {
-                    const int qq = e / (TS * P);
-                    const int rem = e - qq * (TS * P);
-                    // contiguous lines: u fastest; strided lines: the line index fastest
-                    const int ll = (g.S == 1) ? rem / P : rem % TS;
-                    const int u = (g.S == 1) ? rem % P : rem / TS;
-                    if (ll < tl.nl) {
-                        const int64_t si = qo * g.qn + (q0 + qq - g.qb);
-                        const int64_t off = (g.S == 1) ? ((si * g.A + tl.a0 + ll) * P + u)
-                                                       : (((si * g.A + tl.a0) * P + u) * g.S + tl.s0 + ll);
-                        v[k] = in[off];
-                        dst[k] = (qq * TS + ll) * P + u;
-                    }
-                }
-            }
-            C<T> tav = mk<T>(0, 0);
-            if (tid < nq * P) tav = TA[(int64_t)(q0 + tid / P) * M + ((tid % P) << lgG)];
-#pragma unroll
-            for (int k = 0; k < kPer; ++k)
-                if (dst[k] >= 0) Ys[dst[k]] = v[k];
-            if (tid < nq * P) TAs[tid] = tav;
-            __syncthreads();
-            if (live) {
-                for (int qq = 0; qq < nq; ++qq) {
-                    const int q = q0 + qq;
-                    C<T> y[P];
-                    const C<T>* ys = Ys + (qq * TS + l) * P;
-#pragma unroll
-                    for (int u = 0; u < P; ++u) y[u] = ys[u];
-                    RegDFT<T, P, false>::run(y);
-                    const C<T>* h = HT + ((int64_t)q * G + n2) * P;
-#pragma unroll
-                    for (int r = 0; r < P; ++r) y[r] = cmulc<T>(y[r], h[r]);
-                    RegDFT<T, P, true>::run(y);
-                    const C<T>* ta = TAs + qq * P;
-#pragma unroll
-                    for (int i = 0; i < P; ++i) acc[i] = cfmac<T>(acc[i], y[i], ta[i]);
-                }
-            }
-            __syncthreads();  // the next round overwrites the staged values
-        }
         if (live) {
+            for (int qq = w; qq < g.qn; qq += kEhWaves) {
+                const int q = g.qb + qq;
+                const int64_t si = qo * g.qn + qq;
+                const C<T>* h = HT + (int64_t)q * M + n2;
+                C<T> y[P], hv[P];
 #pragma unroll
-            for (int i = 0; i < P; ++i) {
-                const int n = (i << lgG) + n2;
-                const int64_t off = (g.S == 1) ? ((qo * g.A + tl.a0 + l) * M + n)
-                                               : (((qo * g.A + tl.a0) * M + n) * g.S + tl.s0 + l);
-                if (atomic) {
-                    atomicAdd(&((T*)out)[2 * off], acc[i].x);
-                    atomicAdd(&((T*)out)[2 * off + 1], acc[i].y);
-                } else {
-                    C<T> v = acc[i];
-                    if (accumulate) v = cadd<T>(v, out[off]);
-                    out[off] = v;
+                for (int u = 0; u < P; ++u) {
+                    const int64_t off = (g.S == 1) ? ((si * g.A + tl.a0 + l) * P + u)
+                                                   : (((si * g.A + tl.a0) * P + u) * g.S + tl.s0 + l);
+                    y[u] = in[off];
+                    hv[u] = h[u << lgG];
                 }
+                RegDFT<T, P, false>::run(y);
+#pragma unroll
+                for (int r = 0; r < P; ++r) y[r] = cmulc<T>(y[r], hv[r]);
+                RegDFT<T, P, true>::run(y);
+                const C<T>* ta = TAs + qq * P;
+#pragma unroll
+                for (int i = 0; i < P; ++i) acc[i] = cfmac<T>(acc[i], y[i], ta[i]);
             }
         }
+#pragma unroll
+        for (int i = 0; i < P; ++i) Red[(w * P + i) * kWave + lane] = acc[i];
+        __syncthreads();
+        // the kWave P outputs of the tile, (i, lane) pairs spread over the workgroup
+        for (int o = tid; o < P * kWave; o += kEhWaves * kWave) {
+            const int i = o / kWave;
+            const int ln = o % kWave;
+            const int ll = ln >> lgG;
+            if (ll < tl.nl) {
+                C<T> v = Red[i * kWave + ln];
+#pragma unroll
+                for (int ww = 1; ww < kEhWaves; ++ww) v = cadd<T>(v, Red[(ww * P + i) * kWave + ln]);
+                const int n = (i << lgG) + (ln & (G - 1));
+                const int64_t off = (g.S == 1) ? ((qo * g.A + tl.a0 + ll) * M + n)
+                                               : (((qo * g.A + tl.a0) * M + n) * g.S + tl.s0 + ll);
+                if (accumulate) v = cadd<T>(v, out[off]);
+                out[off] = v;
+            }
+        }
+        __syncthreads();  // the next tile overwrites the partial sums
     }
-}
-
-template <typename T>
-__global__ void k_zero(C<T>* __restrict__ p, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = mk<T>(0, 0);
 }
 
 hipError_t prep_lds(const void* k, size_t lds) {
@@ -1157,7 +1163,7 @@ int ilog2i(int v) {
 template <typename T, int P>
 hipError_t launch_er(const void* in, void* out, const AxisDev& ax, const PassGeom& g, hipStream_t st) {
     // tile buffer (strided lines only; its size is fixed by the kernel's layout) + the chunk's TA values
-    const size_t lds = cfp_lds_bytes(sizeof(T) == 8, ax.M, ax.g) + (size_t)g.qc * P * sizeof(C<T>);
+    const size_t lds = cfp_lds_bytes(sizeof(T) == 8, ax.M, ax.g) + ((size_t)g.qc * P + (size_t)kErStage * ax.M) * sizeof(C<T>);
     // power-of-two P with at least P lanes per line: reduce first, inverse transform across lanes
     constexpr bool pow2 = kPow2<P>;
     auto k = (pow2 && ax.g >= P) ? k_ER<T, P, pow2> : k_ER<T, P, false>;
@@ -1319,20 +1325,14 @@ hipError_t launch_pass_asr(Kind kind, bool dbl, const void* in, void* out, const
 template <typename T, int P>
 hipError_t launch_ehr(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
                       hipStream_t st) {
-    const int nqc = (g.qn + g.qc - 1) / g.qc;
-    const int atomic = nqc > 1 ? 1 : 0;
-    if (atomic && !accumulate) {
-        // the chunks of a tile add into the output: clear it first (a kernel, not a memset node)
-        const int64_t n = g.Qin * g.A * (int64_t)ax.M * g.S;
-        const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kThreads - 1) / kThreads, 1 << 16));
-        hipLaunchKernelGGL(k_zero<T>, dim3(nb), dim3(kThreads), 0, st, (C<T>*)out, n);
-    }
-    int64_t blocks = ((g.Qin * g.ntiles + 7) / 8) * 8 * nqc;
-    if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = (g.max_blocks + 7) / 8 * 8;
+    int64_t blocks = g.Qin * g.ntiles;
+    if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = g.max_blocks;
     if (blocks > (1 << 22)) blocks = 1 << 22;
-    const size_t lds = (size_t)kEhrStage * P * ((kThreads >> ilog2i(ax.g)) + 1) * sizeof(C<T>);
-    hipLaunchKernelGGL((k_EHR<T, P>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), lds, st,
-                       (const C<T>*)in, (C<T>*)out, ax, g, accumulate, ilog2i(ax.g), atomic, (const C<T>*)ax.TA,
+    const size_t lds = ((size_t)kEhWaves * P * kWave + (size_t)g.qn * P) * sizeof(C<T>);
+    hipError_t e = prep_lds((const void*)k_EHR<T, P>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_EHR<T, P>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kEhWaves * kWave), lds, st,
+                       (const C<T>*)in, (C<T>*)out, ax, g, accumulate, ilog2i(ax.g), (const C<T>*)ax.TA,
                        (const C<T>*)ax.HT);
     return hipGetLastError();
 }
@@ -1356,11 +1356,13 @@ bool ehr_applicable(int M, int g) {
     return (P == 1 || P == 2 || P == 4 || P == 8 || P == 16) && g >= P;
 }
 
+int ehr_tile_lines(int g) { return kWave / std::max(1, g); }
+
 hipError_t launch_pass_ehr(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
                            hipStream_t st) {
-    if (!ehr_applicable(ax.M, ax.g) || !ax.HT || g.TS != cfp_tile_lines(ax.g) || g.qc < 1)
+    if (!ehr_applicable(ax.M, ax.g) || !ax.HT || g.TS != ehr_tile_lines(ax.g) || g.qn > 64)
         return hipErrorInvalidValue;
-    if (((g.Qin * g.ntiles + 7) / 8) * 8 * ((g.qn + g.qc - 1) / g.qc) >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    if (g.Qin * g.ntiles >= (int64_t(1) << 31)) return hipErrorInvalidValue;
     return dbl ? launch_ehr_T<double>(in, out, ax, g, accumulate, st) : launch_ehr_T<float>(in, out, ax, g, accumulate, st);
 }
 

@@ -67,7 +67,6 @@ struct fx_plan {
                                    // measured workloads, kept as an option)
     int asr_max_g = 64;            // above this the LDS-transform form (k_AS) is used
     int cfp_blocks = 1024;         // register E kernel: target workgroups per launch
-    int ehr_blocks = 512;          // register adjoint E kernel: target workgroups per launch
     bool use_p2 = true;            // compile-time specialised kernels for power-of-two axes
     int persist = 0;               // >0: tile passes run as persistent grids of persist x CUs workgroups
     size_t budget = 0;

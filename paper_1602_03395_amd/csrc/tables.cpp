@@ -65,7 +65,8 @@ inline void put(std::vector<double>& v, size_t i, double cycles, double amp) {
 //   W[r] = sum_c TB[r + P c] Y[r + P c] = sum_n2 HT[n2][r] V[n2][r],
 //   HT[n2][r] = w_M^(n2 r) TA'[n2] sum_c TB[r + P c] w_g^(n2 c) / M,
 // where the n2 part of (presA), TA'[n2] = exp(-2 pi i q n2 / (lam M)), and the 1/M of the inverse
-// are folded in as well. Layout [q][n2][r], FP64 complex.
+// are folded in as well. Layout [q][r][n2] (the g lanes of a line read consecutive values, and the
+// P g = M values of one q are contiguous), FP64 complex.
 void build_ht(AxisTables& t, int64_t M, int64_t lam) {
     int64_t g = lam, b = M;
     while (b) { const int64_t r = g % b; g = b; b = r; }
@@ -74,6 +75,7 @@ void build_ht(AxisTables& t, int64_t M, int64_t lam) {
     t.HT.assign(2 * (size_t)(lam * M), 0.0);
     std::vector<double> rg(2 * (size_t)g);  // exp(-2 pi i k / g)
     for (int64_t k = 0; k < g; ++k) put(rg, (size_t)k, -rational_cycles(k, g), 1.0);
+    auto at = [&](int64_t q, int64_t r, int64_t n2) { return 2 * (size_t)((q * P + r) * g + n2); };
     for (int64_t q = 0; q < lam; ++q) {
         const double* tb = &t.TB[2 * (size_t)(q * M)];
         for (int64_t n2 = 0; n2 < g; ++n2) {
@@ -88,7 +90,7 @@ void build_ht(AxisTables& t, int64_t M, int64_t lam) {
                 // exp(-2 pi i (n2 r lam + q n2) / (lam M)) / M
                 const double ang = -kTwoPi * rational_cycles(n2 * r * lam + q * n2, N);
                 const double er = std::cos(ang) / (double)M, ei = std::sin(ang) / (double)M;
-                const size_t i = 2 * (size_t)((q * g + n2) * P + r);
+                const size_t i = at(q, r, n2);
                 t.HT[i] = sr * er - si * ei;
                 t.HT[i + 1] = sr * ei + si * er;
             }
@@ -107,11 +109,10 @@ void build_ht(AxisTables& t, int64_t M, int64_t lam) {
     if (p2 && P >= 2 && g >= 2) {
         for (int64_t q = 0; q < lam; ++q) {
             for (int64_t n2 = 1; n2 < g; n2 += 2) {
-                const size_t row = 2 * (size_t)((q * g + n2) * P);
                 for (int64_t r = 0; r < P; ++r) {
-                    const size_t d = row + 2 * (size_t)r;
+                    const size_t d = at(q, r, n2);
                     if (g >= P) {
-                        const size_t s = row + 2 * (size_t)(r ^ (P / 2));
+                        const size_t s = at(q, r ^ (P / 2), n2);
                         t.HTx[d] = t.HT[s];
                         t.HTx[d + 1] = t.HT[s + 1];
                     } else if (r & 1) {
