@@ -161,9 +161,13 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
         g.qn = qn[ax];
         const bool reg_eh = kind == Kind::EH && p->use_cfp && p->ax[ax].HT != nullptr && qn[ax] <= 64 &&
                             ehr_applicable(p->ax[ax].M, p->ax[ax].g);
-        const bool reg = use_cfp(p, kind, p->ax[ax]) || reg_eh;
-        g.TS = reg_eh ? ehr_tile_lines(p->ax[ax].g)
-                      : reg ? cfp_tile_lines(p->ax[ax].g) : choose_ts(p, kind, p->ax[ax].M, g.A, g.S);
+        g.eas = kind == Kind::EA && p->use_cfp && p->ax[ax].HTx != nullptr &&
+                (p->use_eas == 2 || (p->use_eas == 1 && p->ax[ax].P >= 8 && p->ax[ax].g <= 16)) &&
+                eas_applicable(p->dbl, p->ax[ax].M, p->ax[ax].g, qn[ax]);
+        const bool reg = !g.eas && (use_cfp(p, kind, p->ax[ax]) || reg_eh);
+        g.TS = g.eas ? eas_tile_lines(p->ax[ax].g)
+                     : reg_eh ? ehr_tile_lines(p->ax[ax].g)
+                              : reg ? cfp_tile_lines(p->ax[ax].g) : choose_ts(p, kind, p->ax[ax].M, g.A, g.S);
         if (g.S == 1) g.ntiles = (g.A + g.TS - 1) / g.TS;
         else g.ntiles = g.A * ((g.S + g.TS - 1) / g.TS);
         g.max_blocks = p->persist > 0 ? p->persist * num_cus() : 0;
@@ -219,11 +223,19 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
         return g.Qin * g.ntiles < 2 * (int64_t)num_cus();
     };
     auto do_EA = [&](int ax) {
-        if (split(Kind::EA, ax)) { do_E(ax); do_A(ax); return; }
+        // the structured EA kernel spreads the terms over the waves of a workgroup: never split
+        if (!geom(Kind::EA, ax, slices).eas && split(Kind::EA, ax)) { do_E(ax); do_A(ax); return; }
         emit(Kind::EA, ax, geom(Kind::EA, ax, slices), vol());
     };
+    // the adjoint of EA runs as AH + EH when both have register forms (each is cheaper than the
+    // fused generic pass), or when the fused launch would be small
+    auto reg_adjoint = [&](int ax) {
+        const AxisDev& a = p->ax[ax];
+        return p->use_asr && asr_applicable(a.g, p->asr_max_g) && p->use_cfp && a.HT != nullptr &&
+               qn[ax] <= 64 && ehr_applicable(a.M, a.g);
+    };
     auto do_EAH = [&](int ax) {
-        if (split(Kind::EAH, ax)) { do_AH(ax); do_EH(ax); return; }
+        if (reg_adjoint(ax) || split(Kind::EAH, ax)) { do_AH(ax); do_EH(ax); return; }
         emit(Kind::EAH, ax, geom(Kind::EAH, ax, slices), vol());
     };
     const int k = p->nact;
@@ -584,6 +596,8 @@ fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_pla
     if (const char* e = std::getenv("FX_NO_CFP")) p->use_cfp = (e[0] != '1');
     if (const char* e = std::getenv("FX_NO_ASR")) p->use_asr = (e[0] != '1');
     if (const char* e = std::getenv("FX_AA")) p->use_aa = (e[0] == '1');
+    if (const char* e = std::getenv("FX_EAS")) p->use_eas = (e[0] == '1') ? 2 : 1;
+    if (std::getenv("FX_NO_EAS")) p->use_eas = 0;
     if (const char* e = std::getenv("FX_ASR_MAXG")) p->asr_max_g = std::max(1, std::atoi(e));
     p->cfp_blocks = 2 * num_cus();
     if (const char* e = std::getenv("FX_CFP_BLOCKS")) p->cfp_blocks = std::max(1, std::atoi(e));
@@ -857,8 +871,9 @@ fx_status fx_plan_describe(const fx_plan* p, char* buf, size_t len) {
                       "\"A\":%lld,\"S\":%lld,\"TS\":%d,\"reg\":%d",
                       i ? "," : "", names[(int)o.kind], o.axis - (3 - p->ndim), a.M, a.P, a.lam, o.g.qn,
                       (long long)o.g.Qin, (long long)o.g.A, (long long)o.g.S, o.g.TS,
-                      (o.g.qc > 0 || o.g.reg_a) ? 1 : 0);
+                      (o.g.qc > 0 || o.g.reg_a || o.g.eas) ? 1 : 0);
         s += tmp;
+        if (o.g.eas) s += ",\"eas\":1";
         if (o.kind == Kind::AA) {
             const AxisDev& b = p->ax[o.axis2];
             std::snprintf(tmp, sizeof(tmp),

@@ -63,6 +63,7 @@ struct PassGeom {
     int max_blocks = 0;  // persistent grid: cap on workgroups (0 = one per tile)
     int qc = 0;        // > 0: register E kernel, magnification indices per workgroup
     bool reg_a = false;  // A pass: register structured accumulate
+    bool eas = false;    // EA pass: waves share the terms of 64 / g lines, structured accumulate
 };
 
 enum class Kind { E, A, EA, EH, AH, EAH, AA };
@@ -138,6 +139,12 @@ int aa_tile_groups(int gu, int gv);
 size_t aa_lds_bytes(bool dbl, int gu, int gv);
 hipError_t launch_pass_aa(bool dbl, const void* in, void* out, const AxisDev& au, const AxisDev& av, const AAGeom& g,
                           int accumulate, void* rho, hipStream_t st);
+// EA in register form with the structured accumulate (power-of-two P <= g, 8 <= g <= 64, P <= 16):
+// 64 / g lines per workgroup, its waves share the terms.
+bool eas_applicable(bool dbl, int M, int g, int qn);
+int eas_tile_lines(int g);
+hipError_t launch_pass_eas(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
+                           void* rho, hipStream_t st);
 // Adjoint of E in register form (power-of-two P <= g <= 64, P <= 16): 64 / g lines per workgroup.
 bool ehr_applicable(int M, int g);
 int ehr_tile_lines(int g);

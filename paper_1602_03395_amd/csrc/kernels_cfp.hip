@@ -688,6 +688,160 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
     }
 }
 
+// EA with the structured accumulate, power-of-two P <= g, g = 8, 16, 32 or 64. A workgroup holds
+// the TS = 64 / g lines of one wavefront kEaWaves times; wave w takes the terms q with
+// q - qb = w (mod kEaWaves). For each term the wave forms E_q of its lines as the register E
+// kernel does (lane u < P ends with E_q[u]) and adds Tf_q[n0] E_q[u] into H[line][n0][j],
+// n0 = (u lg_inv) mod P (the n0 with r(n0) = u), j = (q - qb) mod g: the waves own disjoint j
+// (g is a multiple of kEaWaves). Then, as the structured accumulate (presf),
+//   out[n0 + P c] = exp(2 pi i qb c / g) sum_j exp(2 pi i j c / g) H[line][n0][j],
+// one g-point inverse per (line, n0), computed by K = g / 8 lanes as in k_ASK.
+constexpr int kEaWaves = 8;
+
+template <typename T, int P, int K>
+__global__ __launch_bounds__(kEaWaves * kWave) void k_EAS(const C<T>* __restrict__ in, C<T>* __restrict__ out,
+                                                         AxisDev ax, PassGeom g, int accumulate, T* __restrict__ rho,
+                                                         int lgG, const C<T>* __restrict__ TA,
+                                                         const C<T>* __restrict__ HT) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int LP = (P >= 16) ? 4 : (P >= 8) ? 3 : (P >= 4) ? 2 : (P >= 2) ? 1 : 0;
+    constexpr int G = 8 * K;  // g
+    constexpr int LK = (K == 8) ? 3 : (K == 4) ? 2 : (K == 2) ? 1 : 0;
+    constexpr int TS = kWave / G;
+    const int M = ax.M;
+    C<T>* B = (C<T>*)smem;              // [TS][M] the tile's lines
+    C<T>* H = B + TS * M;               // [TS][P][G]
+    C<T>* TAs = H + TS * P * G;         // [q - qb][i]
+    const C<T>* Tf = (const C<T>*)ax.Tf;
+    const C<T>* twg = (const C<T>*)ax.tw;
+    const int tid = (int)threadIdx.x;
+    const int w = tid / kWave;
+    const int lane = tid % kWave;
+    const int l = lane / G;
+    const int n2 = lane % G;
+    for (int e = tid; e < g.qn * P; e += kEaWaves * kWave)
+        TAs[e] = TA[(int64_t)(g.qb + e / P) * M + ((e % P) << lgG)];
+    // E part: lane twiddles, the odd lane's spectrum exchange, the lane's accumulate target
+    const bool odd_flip = (n2 & 1) && lgG >= 1;
+    C<T> wst[LP > 0 ? LP : 1];
+    const C<T> fin = lane_twiddles_x<T, LP>(wst, n2, twg, M);
+    const int n0u = (int)(((int64_t)(n2 % P) * ax.lg_inv) % P);
+    // accumulate part: thread t < TS P K is lane k of group (l, n0)
+    const int ak = tid % K;
+    const int agrp = tid / K;
+    const bool acc_thread = agrp < TS * P;
+    int kr = 0;
+    for (int b = 0; b < LK; ++b) kr |= ((ak >> b) & 1) << (LK - 1 - b);
+    C<T> w1[8];  // exp(2 pi i k c1 / g)
+#pragma unroll
+    for (int c1 = 0; c1 < 8; ++c1) {
+        const C<T> t = twg[((ak * c1) % G) * P];
+        w1[c1] = mk<T>(t.x, -t.y);
+    }
+    C<T> om[LK > 0 ? LK : 1];  // cross-lane stage twiddles exp(2 pi i (k mod h) / (2 h))
+#pragma unroll
+    for (int st = 0; st < LK; ++st) {
+        const int hh = 1 << st;
+        const C<T> t = twg[(int64_t)(ak & (hh - 1)) * (M / (2 * hh))];
+        om[st] = mk<T>(t.x, -t.y);
+    }
+    const int qbr = g.qb % G;
+    const int64_t total = g.Qin * g.ntiles;  // < 2^31 (host check)
+    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
+        const int64_t qi = (int64_t)((unsigned)bid / (unsigned)g.ntiles);
+        const int64_t tt = bid - qi * g.ntiles;
+        const Tile tl = decode_tile(g, tt);
+        const bool live = l < tl.nl;
+        // the tile's lines into LDS (TS M = 64 P <= 2 kEaWaves kWave values: two per thread, both
+        // loads issued first), H cleared
+        C<T> bv[2];
+        int bd[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int e = tid + k * kEaWaves * kWave;
+            const int ll = (g.S == 1) ? e / M : e % TS;
+            const int n = (g.S == 1) ? e % M : e / TS;
+            bd[k] = -1;
+            bv[k] = mk<T>(0, 0);
+            if (e < TS * M && ll < tl.nl) {
+                const int64_t off = (g.S == 1) ? ((qi * g.A + tl.a0 + ll) * M + n)
+                                               : (((qi * g.A + tl.a0) * M + n) * g.S + tl.s0 + ll);
+                bv[k] = in[off];
+                bd[k] = ll * M + n;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            if (bd[k] >= 0) B[bd[k]] = bv[k];
+        for (int e = tid; e < TS * P * G; e += kEaWaves * kWave) H[e] = mk<T>(0, 0);
+        __syncthreads();
+        C<T> x[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) x[i] = live ? B[l * M + (i << lgG) + n2] : mk<T>(0, 0);
+        if (odd_flip) {
+#pragma unroll
+            for (int i = 1; i < P; i += 2) x[i] = mk<T>(-x[i].x, -x[i].y);
+        }
+        for (int qq = w; qq < g.qn; qq += kEaWaves) {
+            const int q = g.qb + qq;
+            const C<T>* ta = TAs + qq * P;
+            const C<T>* h = HT + (int64_t)q * M + n2;
+            C<T> v[P];
+#pragma unroll
+            for (int i = 0; i < P; ++i) v[i] = cmul<T>(x[i], ta[i]);
+            RegDFT<T, P, false>::run(v);
+#pragma unroll
+            for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r << lgG]);
+            reduce_scatter_x<T, P>(v, n2, lgG);
+            C<T> s0 = v[0];
+            for (int s = LP; s < lgG; ++s) s0 = cadd<T>(s0, shfl_xor_c<T>(s0, 1 << s));
+            s0 = lane_idft_x<T, LP>(s0, wst, fin);  // lane n2 < P holds E_q[n2]
+            if (live && n2 < P) {
+                C<T>* hp = H + (l * P + n0u) * G + (qq % G);
+                *hp = cfma<T>(*hp, Tf[(int64_t)q * M + n0u], s0);
+            }
+        }
+        __syncthreads();
+        if (acc_thread) {
+            const int al = agrp / P;
+            const int n0 = agrp % P;
+            if (al < tl.nl) {
+                const C<T>* hs = H + (al * P + n0) * G;
+                C<T> hv[8];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) hv[m] = hs[ak + K * m];
+                RegDFT<T, 8, true>::run(hv);
+#pragma unroll
+                for (int c1 = 1; c1 < 8; ++c1) hv[c1] = cmul<T>(hv[c1], w1[c1]);
+                // K-point inverse transform across the lanes, decimation in frequency
+#pragma unroll
+                for (int st = LK - 1; st >= 0; --st) {
+                    const int hh = 1 << st;
+                    const bool upper = (ak & hh) != 0;
+#pragma unroll
+                    for (int c1 = 0; c1 < 8; ++c1) {
+                        const C<T> b = shfl_xor_c<T>(hv[c1], hh);
+                        hv[c1] = upper ? cmul<T>(csub<T>(b, hv[c1]), om[st]) : cadd<T>(hv[c1], b);
+                    }
+                }
+#pragma unroll
+                for (int c1 = 0; c1 < 8; ++c1) {
+                    const int c = c1 + 8 * kr;
+                    C<T> v = hv[c1];
+                    if (qbr != 0) v = cmulc<T>(v, twg[((qbr * c) % G) * P]);  // exp(+2 pi i qb c / g)
+                    const int nb = n0 + P * c;
+                    const int64_t off = (g.S == 1) ? ((qi * g.A + tl.a0 + al) * M + nb)
+                                                   : (((qi * g.A + tl.a0) * M + nb) * g.S + tl.s0 + al);
+                    if (accumulate) v = cadd<T>(v, out[off]);
+                    out[off] = v;
+                    if (rho) rho[off] = v.x * v.x + v.y * v.y;
+                }
+            }
+        }
+        __syncthreads();  // the next tile overwrites B and H
+    }
+}
+
 // Group decode of the structured accumulates: group index gi -> (qo, a, n0, s, r) with
 // gi = ((qo A + a) P + n0) S + s and r = (n0 lg) mod P. Every group index is below 2^31
 // (checked on the host), so the divisions are 32-bit.
@@ -1348,6 +1502,69 @@ hipError_t launch_ehr_T(const void* in, void* out, const AxisDev& ax, const Pass
         case 16: return launch_ehr<T, 16>(in, out, ax, g, accumulate, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <typename T, int P, int K>
+hipError_t launch_eas(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
+                      hipStream_t st) {
+    constexpr int G = 8 * K;
+    constexpr int TS = kWave / G;
+    int64_t blocks = g.Qin * g.ntiles;
+    if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = g.max_blocks;
+    if (blocks > (1 << 22)) blocks = 1 << 22;
+    const size_t lds = ((size_t)TS * ax.M + (size_t)TS * P * G + (size_t)g.qn * P) * sizeof(C<T>);
+    hipError_t e = prep_lds((const void*)k_EAS<T, P, K>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_EAS<T, P, K>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kEaWaves * kWave), lds,
+                       st, (const C<T>*)in, (C<T>*)out, ax, g, accumulate, (T*)rho, ilog2i(ax.g), (const C<T>*)ax.TA,
+                       (const C<T>*)ax.HTx);
+    return hipGetLastError();
+}
+
+template <typename T, int P>
+hipError_t launch_eas_P(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
+                        hipStream_t st) {
+    switch (ax.g) {
+        case 8: if constexpr (P <= 8) return launch_eas<T, P, 1>(in, out, ax, g, accumulate, rho, st); break;
+        case 16: return launch_eas<T, P, 2>(in, out, ax, g, accumulate, rho, st);
+        case 32: return launch_eas<T, P, 4>(in, out, ax, g, accumulate, rho, st);
+        case 64: return launch_eas<T, P, 8>(in, out, ax, g, accumulate, rho, st);
+        default: break;
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_eas_T(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
+                        hipStream_t st) {
+    switch (ax.P) {
+        case 1: return launch_eas_P<T, 1>(in, out, ax, g, accumulate, rho, st);
+        case 2: return launch_eas_P<T, 2>(in, out, ax, g, accumulate, rho, st);
+        case 4: return launch_eas_P<T, 4>(in, out, ax, g, accumulate, rho, st);
+        case 8: return launch_eas_P<T, 8>(in, out, ax, g, accumulate, rho, st);
+        case 16: return launch_eas_P<T, 16>(in, out, ax, g, accumulate, rho, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+bool eas_applicable(bool dbl, int M, int g, int qn) {
+    if (g < 8 || g > kWave || (g & (g - 1)) != 0 || M % g != 0 || qn < 1 || qn > 64) return false;
+    const int P = M / g;
+    if (!(P == 1 || P == 2 || P == 4 || P == 8 || P == 16) || P > g) return false;
+    if (dbl && P == 16) return false;  // does not fit the registers of an eight-wave workgroup
+    const size_t cs = dbl ? 16 : 8;
+    const int TS = kWave / g;
+    return ((size_t)TS * M + (size_t)TS * P * g + (size_t)qn * P) * cs <= (size_t)lds_limit_bytes();
+}
+
+int eas_tile_lines(int g) { return kWave / std::max(1, g); }
+
+hipError_t launch_pass_eas(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
+                           void* rho, hipStream_t st) {
+    if (!eas_applicable(dbl, ax.M, ax.g, g.qn) || !ax.HTx || g.TS != eas_tile_lines(ax.g)) return hipErrorInvalidValue;
+    if (g.Qin * g.ntiles >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    return dbl ? launch_eas_T<double>(in, out, ax, g, accumulate, rho, st)
+               : launch_eas_T<float>(in, out, ax, g, accumulate, rho, st);
 }
 
 bool ehr_applicable(int M, int g) {

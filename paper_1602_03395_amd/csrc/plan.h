@@ -65,6 +65,11 @@ struct fx_plan {
     bool use_asr = true;           // register structured accumulate (k_ASR) for g <= asr_max_g
     bool use_aa = false;           // fuse the last two accumulate passes (FX_AA=1; slower on the
                                    // measured workloads, kept as an option)
+    int use_eas = 1;               // EA through the structured register kernel: 0 never (FX_NO_EAS),
+                                   // 1 where it applies with P >= 8 and g <= 16 (smaller transforms
+                                   // are dominated by the per-wave overheads; its table-row traffic
+                                   // per line grows as g^2 / 64 times the line's output), 2 wherever
+                                   // it applies (FX_EAS=1)
     int asr_max_g = 64;            // above this the LDS-transform form (k_AS) is used
     int cfp_blocks = 1024;         // register E kernel: target workgroups per launch
     bool use_p2 = true;            // compile-time specialised kernels for power-of-two axes

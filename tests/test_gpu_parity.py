@@ -153,6 +153,32 @@ def test_adjoint_matches_oracle(fx, shape, lam, schedule):
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
+# the fused transform + structured accumulate pass (g = 8..64, power-of-two P <= g), on the
+# contiguous axis of a 1-D field and on strided axes
+@pytest.mark.parametrize("shape,lam,dtype", [
+    ((512,), (32,), torch.complex64),
+    ((64, 256), (32, 4), torch.complex128),
+    ((64, 256), (32, 4), torch.complex64),
+    ((256, 128), (16, 8), torch.complex64),
+    ((32, 24, 16), (8, 3, 2), torch.complex128),
+    ((128, 16), (64, 2), torch.complex128),
+    ((128, 16), (64, 2), torch.complex64),
+])
+def test_structured_ea_matches_oracle(fx, shape, lam, dtype, monkeypatch):
+    import json
+    monkeypatch.setenv("FX_EAS", "1")  # wherever it applies (by default only for P >= 8)
+    say("structured EA", shape, lam, dtype)
+    dx = tuple(0.9 for _ in shape)
+    psi_np = workloads.random_field(shape, 81)
+    plan = fx.Plan(shape, dx, 1.0, 13.0, lam, dtype=dtype)  # not cached: the switch is read at creation
+    assert any(p.get("eas") for p in json.loads(plan.describe())["passes"])
+    out, rho = plan.expand(torch.from_numpy(psi_np).to(dtype).cuda())
+    ref = oracle.expand(psi_np, dx, 1.0, 13.0, lam)
+    if dtype == torch.complex128:
+        assert rel(out.cpu().numpy(), ref) <= TOL64
+    assert rel(rho.cpu().numpy(), oracle.density(ref)) <= (TOL64 if dtype == torch.complex128 else TOL32_RHO)
+
+
 # g = gcd(lam, M) of 16, 32 and 64: the adjoint accumulate with g / 8 lanes per group
 @pytest.mark.parametrize("shape,lam", [((64,), (16,)), ((24, 64), (3, 32)), ((128,), (64,)), ((48, 40), (16, 2))])
 def test_adjoint_lane_groups_match_oracle(fx, shape, lam):
@@ -309,8 +335,10 @@ def test_batch_rejects_bad_arguments(fx):
 
 @pytest.mark.parametrize("case", [5, 7, 9, 15, 19, 22])
 def test_fused_two_axis_accumulate_fp64(fx, case, monkeypatch):
-    # the optional fused form of the last two accumulate passes (FX_AA=1), read at plan creation
+    # the optional fused form of the last two accumulate passes (FX_AA=1), read at plan creation;
+    # the structured EA pass, which leaves a single accumulate pass, is switched off for it
     monkeypatch.setenv("FX_AA", "1")
+    monkeypatch.setenv("FX_NO_EAS", "1")
     shape, lam, dx, t, moh, shift = CASES[case]
     say("fused accumulate", shape, lam)
     psi_np = workloads.random_field(shape, 900 + case)
