@@ -42,7 +42,9 @@ def pass_cost(p: dict, csize: int, outer_chunks: int = 1):
                             + 5P log2 P (pruned inverse) + 2P
       register form of E:   6M (premultiply) + 5M log2 P (g transforms of P points) + 6M (folded
                             chirp table) + 2M (sum over the g subsequences) + 5P log2 P (inverse)
-      EA adds 8M (the twiddle multiply-accumulate of every output point).
+      EA adds 8M (the twiddle multiply-accumulate of every output point), or with the structured
+      accumulate (EA with "eas") 8P (one twiddle product per pruned output) per line and term plus
+      a g-point inverse transform (5 g log2 g) per output group (P groups per line).
     A: 8 flops per output and term; AA (two fused accumulates): 16 per input sample plus a
     g_u x g_v inverse transform per output group.
     """
@@ -58,7 +60,11 @@ def pass_cost(p: dict, csize: int, outer_chunks: int = 1):
         flops = lines * qn * e_line
         byts = (lines * M + lines * qn * P) * csize
     elif kind in ("EA", "EAH"):
-        flops = lines * qn * (e_line + 8 * M) + lines * M * 2
+        if p.get("eas"):
+            g = M // P
+            flops = lines * qn * (e_line + 8 * P) + lines * P * 5 * g * lg(g)
+        else:
+            flops = lines * qn * (e_line + 8 * M) + lines * M * 2
         byts = 2 * lines * M * csize
     elif kind == "AA":
         nin = p["O"] * p["qn2"] * qn * p["X"] * P * p["Y"] * p["P2"] * p["Z"]

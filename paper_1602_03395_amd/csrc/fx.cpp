@@ -180,7 +180,7 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
             // magnification indices per workgroup: as many as keep >= cfp_blocks workgroups
             const int64_t base = g.Qin * g.ntiles;
             const int64_t want = std::max<int64_t>(1, (int64_t)p->cfp_blocks);
-            g.qc = (int)std::max<int64_t>(1, std::min<int64_t>(g.qn, (base * g.qn) / want));
+            g.qc = (int)std::max<int64_t>(1, std::min<int64_t>(g.qn, (base * g.qn + want - 1) / want));
         }
         return g;
     };

@@ -577,6 +577,7 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
     constexpr int LP = (P >= 32) ? 5 : (P >= 16) ? 4 : (P >= 8) ? 3 : (P >= 4) ? 2 : (P >= 2) ? 1 : 0;
     C<T>* B = (C<T>*)smem;
     C<T>* TAs = B + kThreads * P;  // TA_q[g i] of every term of the pass, [q - qb][i]
+    C<T>* Hs = TAs + g.qn * P;       // table rows of kErStage terms, [q - q0][r][n2]
     const int M = ax.M;
     const int G = 1 << lgG;
     const int l = (int)threadIdx.x >> lgG;
@@ -629,8 +630,14 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
         }
         __syncthreads();
         for (int q = g.qb; q < g.qb + g.qn; ++q) {
+            if ((q - g.qb) % kErStage == 0) {
+                // the next round of table rows (after the previous round's reads)
+                __syncthreads();
+                copy_to_lds<T>(Hs, HT + (int64_t)q * M, min(kErStage, g.qb + g.qn - q) * M);
+                __syncthreads();
+            }
             const C<T>* ta = TAs + (q - g.qb) * P;
-            const C<T>* h = HT + (int64_t)q * M + n2;
+            const C<T>* h = Hs + ((q - g.qb) % kErStage) * M + n2;
             const C<T>* tf = Tf + (int64_t)q * M + n2;
             C<T> v[P];
 #pragma unroll
@@ -1335,7 +1342,7 @@ hipError_t launch_er(const void* in, void* out, const AxisDev& ax, const PassGeo
 template <typename T, int P>
 hipError_t launch_ear(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
                       hipStream_t st) {
-    const size_t lds = cfp_lds_bytes(sizeof(T) == 8, ax.M, ax.g) + (size_t)g.qn * P * sizeof(C<T>);
+    const size_t lds = cfp_lds_bytes(sizeof(T) == 8, ax.M, ax.g) + ((size_t)g.qn * P + (size_t)kErStage * ax.M) * sizeof(C<T>);
     auto k = k_EAR<T, P>;
     hipError_t e = prep_lds((const void*)k, lds);
     if (e != hipSuccess) return e;
@@ -1524,7 +1531,8 @@ hipError_t launch_eas(const void* in, void* out, const AxisDev& ax, const PassGe
 template <typename T, int P>
 hipError_t launch_eas_P(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
                         hipStream_t st) {
-    switch (ax.g) {
+    if constexpr (sizeof(T) == 8 && P == 16) return hipErrorInvalidValue;  // excluded by eas_applicable
+    else switch (ax.g) {
         case 8: if constexpr (P <= 8) return launch_eas<T, P, 1>(in, out, ax, g, accumulate, rho, st); break;
         case 16: return launch_eas<T, P, 2>(in, out, ax, g, accumulate, rho, st);
         case 32: return launch_eas<T, P, 4>(in, out, ax, g, accumulate, rho, st);
