@@ -542,23 +542,24 @@ fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_pla
             return FX_EUNSUPPORTED;
         }
     }
-    // Upload all tables in one allocation: per axis TA | TB | Tf | tw | HT | HTx.
+    // Upload all tables in one allocation: per axis TA | TB | Tf | tw | HT | HTx | HTl.
     const size_t cs = csize(p);
     size_t total = 0;
-    size_t offs[3][6];
+    size_t offs[3][7];
     for (int pa = 0; pa < 3; ++pa) {
         const size_t lm = (size_t)p->ax[pa].lam * p->ax[pa].M;
-        const size_t sz[6] = {lm, lm, lm, (size_t)p->ax[pa].M, tabs[pa].HT.size() / 2, tabs[pa].HTx.size() / 2};
-        for (int t = 0; t < 6; ++t) {
+        const size_t sz[7] = {lm, lm, lm, (size_t)p->ax[pa].M, tabs[pa].HT.size() / 2, tabs[pa].HTx.size() / 2,
+                              tabs[pa].HTl.size() / 2};
+        for (int t = 0; t < 7; ++t) {
             offs[pa][t] = total;
             total += ((sz[t] * cs + 255) / 256) * 256;
         }
     }
     std::vector<unsigned char> host(total, 0);
     for (int pa = 0; pa < 3; ++pa) {
-        const std::vector<double>* src[6] = {&tabs[pa].TA, &tabs[pa].TB, &tabs[pa].Tf, &tabs[pa].tw, &tabs[pa].HT,
-                                             &tabs[pa].HTx};
-        for (int t = 0; t < 6; ++t) {
+        const std::vector<double>* src[7] = {&tabs[pa].TA, &tabs[pa].TB, &tabs[pa].Tf, &tabs[pa].tw, &tabs[pa].HT,
+                                             &tabs[pa].HTx, &tabs[pa].HTl};
+        for (int t = 0; t < 7; ++t) {
             if (p->dbl) to_prec<double>(*src[t], host, offs[pa][t]);
             else to_prec<float>(*src[t], host, offs[pa][t]);
         }
@@ -584,6 +585,7 @@ fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_pla
         p->ax[pa].tw = b + offs[pa][3];
         p->ax[pa].HT = tabs[pa].HT.empty() ? nullptr : b + offs[pa][4];
         p->ax[pa].HTx = tabs[pa].HTx.empty() ? nullptr : b + offs[pa][5];
+        p->ax[pa].HTl = tabs[pa].HTl.empty() ? nullptr : b + offs[pa][6];
     }
     size_t budget = (size_t)8 << 30;
     if (const char* e = std::getenv("FX_WORKSPACE_MB")) budget = (size_t)std::max(1L, std::atol(e)) << 20;

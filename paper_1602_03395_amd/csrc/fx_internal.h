@@ -39,6 +39,7 @@ struct AxisDev {
     const void* tw = nullptr;
     const void* HT = nullptr;  // [lam][P][g] chirp-folded table of the register E kernel (or null)
     const void* HTx = nullptr; // HT arranged for the select-free first reduction step (or null)
+    const void* HTl = nullptr; // HTx in [lam][g][P] order (each lane's P values contiguous)
     int M = 1;        // axis length
     int P = 1;        // M / g: number of distinct n'' values (output-pruned length)
     int g = 1;        // gcd(lam, M)
@@ -108,6 +109,7 @@ struct AxisTables {
     std::vector<double> TA, TB, Tf, tw;  // interleaved re,im; [lam][M] for TA/TB/Tf, [M] for tw
     std::vector<double> HT;              // [lam][P][g] when requested, else empty
     std::vector<double> HTx;             // HT for odd n2 lanes swapped or sign-modulated (see build_ht)
+    std::vector<double> HTl;             // HTx in [lam][g][P] order
 };
 struct AxisParams {
     int64_t M = 1;

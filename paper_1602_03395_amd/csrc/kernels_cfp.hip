@@ -305,9 +305,13 @@ template <int P> constexpr bool kPow2 = (P & (P - 1)) == 0;
 // The tile of TS = kThreads / g lines of M = g P points into LDS: exactly P elements per thread,
 // loaded in chunks of CH whose loads are all issued before their stores, so that CH latencies
 // overlap (CH trades the overlap against the registers the loads hold).
+// Rows of the LDS tile are kTilePad elements longer than a line: with the line index fastest over
+// the threads of a strided tile, rows M apart would put every line on the same LDS banks.
+constexpr int kTilePad = 8;
+
 template <typename T, int P, int CH>
 __device__ __forceinline__ void load_tile(const C<T>* __restrict__ in, C<T>* B, const PassGeom& g, const Tile& tl,
-                                          int64_t qi, int M, const FDiv& fdM) {
+                                          int64_t qi, int M, const FDiv& fdM, int ldb) {
     const int cnt = tl.nl * M;
     if (g.S != 1 && (kThreads % tl.nl) == 0) {
         // strided lines, nl | kThreads (every full tile): the thread's line l = tid mod nl is fixed
@@ -318,7 +322,7 @@ __device__ __forceinline__ void load_tile(const C<T>* __restrict__ in, C<T>* B, 
         const int n0 = tid / tl.nl;
         const C<T>* src = in + ((qi * g.A + tl.a0) * M + n0) * g.S + tl.s0 + l;
         const int64_t stride = (int64_t)dn * g.S;
-        C<T>* dst = B + l * M + n0;
+        C<T>* dst = B + l * ldb + n0;
 #pragma unroll
         for (int k0 = 0; k0 < P; k0 += CH) {
             C<T> v[CH];
@@ -343,7 +347,7 @@ __device__ __forceinline__ void load_tile(const C<T>* __restrict__ in, C<T>* B, 
                 int ll, n;
                 const int64_t off = tile_elem(g, tl, qi, M, fdM, e, ll, n);
                 v[k] = in[off];
-                dst[k] = ll * M + n;
+                dst[k] = ll * ldb + n;
             }
         }
 #pragma unroll
@@ -416,8 +420,9 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int LP = (P >= 32) ? 5 : (P >= 16) ? 4 : (P >= 8) ? 3 : (P >= 4) ? 2 : (P >= 2) ? 1 : 0;
     const int M = ax.M;
-    C<T>* B = (C<T>*)smem;          // tile of strided lines: TS lines x M points
-    C<T>* TAs = B + kThreads * P;    // TA_q[g i] of the workgroup's qc terms, [q - qlo][i]
+    const int ldb = M + kTilePad;
+    C<T>* B = (C<T>*)smem;          // tile of strided lines: TS rows of ldb (M points each)
+    C<T>* TAs = B + (kThreads >> lgG) * ldb;  // TA_q[g i] of the workgroup's qc terms, [q - qlo][i]
     C<T>* Hs = TAs + g.qc * P;       // table rows of kErStage terms, [q - q0][r][n2]
     const int G = 1 << lgG;
     const int l = (int)threadIdx.x >> lgG;
@@ -474,7 +479,7 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
             for (int i = 0; i < P; ++i) x[i] = live ? src[i << lgG] : mk<T>(0, 0);
         } else {
             const FDiv fdM = tile_div(g, tl, M);
-            load_tile<T, P, (sizeof(T) == 4 ? P : 1)>(in, B, g, tl, qi, M, fdM);
+            load_tile<T, P, (sizeof(T) == 4 ? P : 1)>(in, B, g, tl, qi, M, fdM, ldb);
         }
         if (ti < nta) TAs[ti] = tav;
         for (int e = ti + kThreads; e < nta; e += kThreads) TAs[e] = TA[(int64_t)(qlo + e / P) * M + ((e % P) << lgG)];
@@ -487,7 +492,7 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
         __syncthreads();
         if (g.S != 1) {
 #pragma unroll
-            for (int i = 0; i < P; ++i) x[i] = live ? B[l * M + (i << lgG) + n2] : mk<T>(0, 0);
+            for (int i = 0; i < P; ++i) x[i] = live ? B[l * ldb + (i << lgG) + n2] : mk<T>(0, 0);
         }
         if (odd_flip) {
 #pragma unroll
@@ -575,10 +580,10 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
                                                   const C<T>* __restrict__ HT) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int LP = (P >= 32) ? 5 : (P >= 16) ? 4 : (P >= 8) ? 3 : (P >= 4) ? 2 : (P >= 2) ? 1 : 0;
-    C<T>* B = (C<T>*)smem;
-    C<T>* TAs = B + kThreads * P;  // TA_q[g i] of every term of the pass, [q - qb][i]
-    C<T>* Hs = TAs + g.qn * P;       // table rows of kErStage terms, [q - q0][r][n2]
     const int M = ax.M;
+    const int ldb = M + kTilePad;
+    C<T>* B = (C<T>*)smem;         // tile: TS rows of ldb (M points each)
+    C<T>* TAs = B + (kThreads / ax.g) * ldb;  // TA_q[g i] of every term of the pass, [q - qb][i]
     const int G = 1 << lgG;
     const int l = (int)threadIdx.x >> lgG;
     const int n2 = (int)threadIdx.x & (G - 1);
@@ -612,7 +617,7 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
         const int ti = (int)threadIdx.x;
         C<T> tav = mk<T>(0, 0);
         if (ti < nta) tav = TA[(int64_t)(g.qb + ti / P) * M + ((ti % P) << lgG)];
-        load_tile<T, P, 1>(in, B, g, tl, qi, M, fdM);  // x stays in registers: keep the load phase lean
+        load_tile<T, P, 1>(in, B, g, tl, qi, M, fdM, ldb);  // x stays in registers: keep the load phase lean
         if (ti < nta) TAs[ti] = tav;
         for (int e = ti + kThreads; e < nta; e += kThreads)
             TAs[e] = TA[(int64_t)(g.qb + e / P) * M + ((e % P) << lgG)];
@@ -621,7 +626,7 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
         C<T> x[P], acc[P];
 #pragma unroll
         for (int i = 0; i < P; ++i) {
-            x[i] = live ? B[l * M + (i << lgG) + n2] : mk<T>(0, 0);
+            x[i] = live ? B[l * ldb + (i << lgG) + n2] : mk<T>(0, 0);
             acc[i] = mk<T>(0, 0);
         }
         if (odd_flip) {
@@ -630,21 +635,15 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
         }
         __syncthreads();
         for (int q = g.qb; q < g.qb + g.qn; ++q) {
-            if ((q - g.qb) % kErStage == 0) {
-                // the next round of table rows (after the previous round's reads)
-                __syncthreads();
-                copy_to_lds<T>(Hs, HT + (int64_t)q * M, min(kErStage, g.qb + g.qn - q) * M);
-                __syncthreads();
-            }
             const C<T>* ta = TAs + (q - g.qb) * P;
-            const C<T>* h = Hs + ((q - g.qb) % kErStage) * M + n2;
+            const C<T>* h = HT + ((int64_t)q * G + n2) * P;  // [q][n2][r]: the lane's P values contiguous
             const C<T>* tf = Tf + (int64_t)q * M + n2;
             C<T> v[P];
 #pragma unroll
             for (int i = 0; i < P; ++i) v[i] = cmul<T>(x[i], ta[i]);
             RegDFT<T, P, false>::run(v);
 #pragma unroll
-            for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r << lgG]);
+            for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r]);
             if (scatter) {
                 reduce_scatter_x<T, P>(v, n2, lgG);
                 C<T> s0 = v[0];
@@ -1342,7 +1341,7 @@ hipError_t launch_er(const void* in, void* out, const AxisDev& ax, const PassGeo
 template <typename T, int P>
 hipError_t launch_ear(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
                       hipStream_t st) {
-    const size_t lds = cfp_lds_bytes(sizeof(T) == 8, ax.M, ax.g) + ((size_t)g.qn * P + (size_t)kErStage * ax.M) * sizeof(C<T>);
+    const size_t lds = cfp_lds_bytes(sizeof(T) == 8, ax.M, ax.g) + (size_t)g.qn * P * sizeof(C<T>);
     auto k = k_EAR<T, P>;
     hipError_t e = prep_lds((const void*)k, lds);
     if (e != hipSuccess) return e;
@@ -1351,7 +1350,7 @@ hipError_t launch_ear(const void* in, void* out, const AxisDev& ax, const PassGe
     if (blocks > (1 << 22)) blocks = 1 << 22;
     hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), lds, st, (const C<T>*)in,
                        (C<T>*)out, ax, g, accumulate, (T*)rho, ilog2i(ax.g), (const C<T>*)ax.TA,
-                       (const C<T>*)ax.Tf, (const C<T>*)ax.HTx);
+                       (const C<T>*)ax.Tf, (const C<T>*)ax.HTl);
     return hipGetLastError();
 }
 
@@ -1631,8 +1630,9 @@ bool cfp_applicable(Kind kind, bool dbl, int M, int g) {
 int cfp_tile_lines(int g) { return kThreads / std::max(1, g); }
 
 size_t cfp_lds_bytes(bool dbl, int M, int g) {
-    // TS lines of M points with TS = kThreads / g, i.e. kThreads * P points
-    return (size_t)kThreads * (size_t)(M / std::max(1, g)) * (dbl ? 16 : 8);
+    // TS rows of M + kTilePad points with TS = kThreads / g
+    const size_t ts = (size_t)(kThreads / std::max(1, g));
+    return ts * (size_t)(M + kTilePad) * (dbl ? 16 : 8);
 }
 
 hipError_t launch_pass_cfp(Kind kind, bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g,

@@ -123,6 +123,16 @@ void build_ht(AxisTables& t, int64_t M, int64_t lam) {
             }
         }
     }
+    // HTx once more in [q][n2][r] order, for kernels whose lanes read their own P values of a row
+    // straight from memory
+    t.HTl.assign(t.HTx.size(), 0.0);
+    for (int64_t q = 0; q < lam; ++q)
+        for (int64_t n2 = 0; n2 < g; ++n2)
+            for (int64_t r = 0; r < P; ++r) {
+                const size_t d = 2 * (size_t)((q * g + n2) * P + r), src = at(q, r, n2);
+                t.HTl[d] = t.HTx[src];
+                t.HTl[d + 1] = t.HTx[src + 1];
+            }
 }
 
 }  // namespace

@@ -11,6 +11,10 @@
         kernel of known size read (and write) exactly its size; stored under <tag>
         (workload/dtype/schedule) and stamped with the hash of the kernel sources
 
+    python -m paper_1602_03395_amd.profiling passes <kernel_trace.csv> <calls>
+        markdown table of the average kernel-trace duration of every pass of the schedule (key
+        'kind#ordinal' as above; <calls> = expansion calls in the traced run)
+
 Only the csv files rocprofv3 writes are read; nothing here touches the GPU.
 """
 
@@ -131,10 +135,27 @@ def traffic(fetch_csv: str, write_csv: str, copy_mib: float, calls: int, out_jso
     return res
 
 
+def passes(trace_csv: str, calls: int) -> str:
+    rows = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"])
+                  for r in csv.DictReader(open(trace_csv)))
+    seq = [(m.group(1), (e - b) / 1e3) for b, e, n in rows for m in [PASS_KIND.search(n)] if m]
+    per = max(1, len(seq) // max(1, calls))
+    kinds = [k for k, _ in seq[:per]]
+    acc = collections.OrderedDict()
+    for i, (kind, us) in enumerate(seq):
+        j = i % per
+        acc.setdefault(f"{kind}#{kinds[:j].count(kind)}", []).append(us)
+    out = ["| pass | launches | avg us |", "|---|---:|---:|"]
+    out += ["| %s | %d | %.2f |" % (k, len(v), sum(v) / len(v)) for k, v in acc.items()]
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
     cmd = sys.argv[1]
     if cmd == "stats":
         print(stats(sys.argv[2]))
+    elif cmd == "passes":
+        print(passes(sys.argv[2], int(sys.argv[3])))
     elif cmd == "counters":
         avg, n = counters(sys.argv[2], sys.argv[3])
         for k in sorted(avg, key=lambda x: -avg[x]):
