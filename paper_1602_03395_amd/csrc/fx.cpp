@@ -110,7 +110,7 @@ size_t csize(const fx_plan* p) { return p->dbl ? 16 : 8; }
 
 bool use_cfp(const fx_plan* p, Kind kind, const AxisDev& a) {
     return p->use_cfp && a.HT != nullptr && cfp_applicable(kind, p->dbl, a.M, a.g) &&
-           (int64_t)(cfp_lds_bytes(p->dbl, a.M, a.g) + ((size_t)a.lam * (a.M / a.g) + 4 * (size_t)a.M) * (p->dbl ? 16 : 8)) <=
+           (int64_t)(cfp_lds_bytes(p->dbl, a.M, a.g) + ((size_t)a.lam * (a.M / a.g) + 4 * (size_t)(a.M + a.g)) * (p->dbl ? 16 : 8)) <=
                lds_limit_bytes();
 }
 

@@ -394,21 +394,29 @@ __device__ __forceinline__ C<T> lane_idft_x(C<T> a, const C<T>* wst, C<T> fin) {
 // Terms whose chirp-folded table rows (M values each) are staged in LDS at a time.
 constexpr int kErStage = 4;
 
-// Copies cnt contiguous values into LDS, the loads of every chunk of 8 per thread issued before
-// their stores.
-template <typename T>
-__device__ __forceinline__ void copy_to_lds(C<T>* dst, const C<T>* __restrict__ src, int cnt) {
-    for (int e0 = 0; e0 < cnt; e0 += 8 * kThreads) {
+// Copies elements e0 <= e < cnt of a block of rows of P values into LDS with a row stride of P + 1, the
+// loads of every chunk of 8 per thread issued before their stores: element e goes to
+// (e / P)(P + 1) + e mod P. A lane then reads its own row with immediate
+// offsets, and with the odd stride the g lanes of a line hit distinct banks.
+template <typename T, int P>
+__device__ __forceinline__ void copy_rows_to_lds(C<T>* dst, const C<T>* __restrict__ src, int e0, int cnt) {
+    for (int b = e0; b < cnt; b += 8 * kThreads) {
+        const int t = b + (int)threadIdx.x;
         C<T> v[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int e = e0 + (int)threadIdx.x + k * kThreads;
-            v[k] = (e < cnt) ? src[e] : mk<T>(0, 0);
-        }
+        for (int k = 0; k < 8; ++k) v[k] = (t + k * kThreads < cnt) ? src[t + k * kThreads] : mk<T>(0, 0);
+        if constexpr (kThreads % P == 0) {
+            // element t + k kThreads sits in row t / P + k kThreads / P, column t mod P
+            C<T>* d = dst + (t / P) * (P + 1) + t % P;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int e = e0 + (int)threadIdx.x + k * kThreads;
-            if (e < cnt) dst[e] = v[k];
+            for (int k = 0; k < 8; ++k)
+                if (t + k * kThreads < cnt) d[k * (kThreads / P) * (P + 1)] = v[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int e = t + k * kThreads;
+                if (e < cnt) dst[(e / P) * (P + 1) + e % P] = v[k];
+            }
         }
     }
 }
@@ -423,7 +431,7 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
     const int ldb = M + kTilePad;
     C<T>* B = (C<T>*)smem;          // tile of strided lines: TS rows of ldb (M points each)
     C<T>* TAs = B + (kThreads >> lgG) * ldb;  // TA_q[g i] of the workgroup's qc terms, [q - qlo][i]
-    C<T>* Hs = TAs + g.qc * P;       // table rows of kErStage terms, [q - q0][r][n2]
+    C<T>* Hs = TAs + g.qc * P;       // table rows of kErStage terms, [q - q0][n2][P + 1]
     const int G = 1 << lgG;
     const int l = (int)threadIdx.x >> lgG;
     const int n2 = (int)threadIdx.x & (G - 1);
@@ -486,9 +494,12 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int e = ti + k * kThreads;
-            if (e < hcnt) Hs[e] = hv[k];
+            if (e < hcnt) {
+                if constexpr (kThreads % P == 0) Hs[(ti / P + k * (kThreads / P)) * (P + 1) + ti % P] = hv[k];
+                else Hs[(e / P) * (P + 1) + e % P] = hv[k];
+            }
         }
-        if (hcnt > 8 * kThreads) copy_to_lds<T>(Hs + 8 * kThreads, hsrc + 8 * kThreads, hcnt - 8 * kThreads);
+        if (hcnt > 8 * kThreads) copy_rows_to_lds<T, P>(Hs, hsrc, 8 * kThreads, hcnt);
         __syncthreads();
         if (g.S != 1) {
 #pragma unroll
@@ -502,17 +513,17 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
             if (q > qlo && (q - qlo) % kErStage == 0) {
                 // next round of table rows (the previous round's reads are done first)
                 __syncthreads();
-                copy_to_lds<T>(Hs, HT + (int64_t)q * M, min(kErStage, qhi - q) * M);
+                copy_rows_to_lds<T, P>(Hs, HT + (int64_t)q * M, 0, min(kErStage, qhi - q) * M);
                 __syncthreads();
             }
             const C<T>* ta = TAs + (q - qlo) * P;
-            const C<T>* h = Hs + ((q - qlo) % kErStage) * M + n2;
+            const C<T>* h = Hs + (((q - qlo) % kErStage) * G + n2) * (P + 1);
             C<T> v[P];
 #pragma unroll
             for (int i = 0; i < P; ++i) v[i] = cmul<T>(x[i], ta[i]);
             RegDFT<T, P, false>::run(v);
 #pragma unroll
-            for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r << lgG]);
+            for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r]);
             if constexpr (LANEINV) {
                 // sum over the lanes first, then one inverse transform across the P lanes
                 reduce_scatter_x<T, P>(v, n2, lgG);
@@ -1323,7 +1334,8 @@ int ilog2i(int v) {
 template <typename T, int P>
 hipError_t launch_er(const void* in, void* out, const AxisDev& ax, const PassGeom& g, hipStream_t st) {
     // tile buffer (strided lines only; its size is fixed by the kernel's layout) + the chunk's TA values
-    const size_t lds = cfp_lds_bytes(sizeof(T) == 8, ax.M, ax.g) + ((size_t)g.qc * P + (size_t)kErStage * ax.M) * sizeof(C<T>);
+    const size_t lds = cfp_lds_bytes(sizeof(T) == 8, ax.M, ax.g) +
+                       ((size_t)g.qc * P + (size_t)kErStage * (ax.M + ax.g)) * sizeof(C<T>);
     // power-of-two P with at least P lanes per line: reduce first, inverse transform across lanes
     constexpr bool pow2 = kPow2<P>;
     auto k = (pow2 && ax.g >= P) ? k_ER<T, P, pow2> : k_ER<T, P, false>;
@@ -1334,7 +1346,7 @@ hipError_t launch_er(const void* in, void* out, const AxisDev& ax, const PassGeo
     if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = (g.max_blocks + 7) / 8 * 8;
     if (blocks > (1 << 22)) blocks = 1 << 22;
     hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), lds, st, (const C<T>*)in,
-                       (C<T>*)out, ax, g, ilog2i(ax.g), (const C<T>*)ax.TA, (const C<T>*)ax.HTx);
+                       (C<T>*)out, ax, g, ilog2i(ax.g), (const C<T>*)ax.TA, (const C<T>*)ax.HTl);
     return hipGetLastError();
 }
 

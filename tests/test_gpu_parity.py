@@ -180,7 +180,8 @@ def test_structured_ea_matches_oracle(fx, shape, lam, dtype, monkeypatch):
 
 
 # g = gcd(lam, M) of 16, 32 and 64: the adjoint accumulate with g / 8 lanes per group
-@pytest.mark.parametrize("shape,lam", [((64,), (16,)), ((24, 64), (3, 32)), ((128,), (64,)), ((48, 40), (16, 2))])
+@pytest.mark.parametrize("shape,lam", [((64,), (16,)), ((24, 64), (3, 32)), ((128,), (64,)), ((48, 40), (16, 2)),
+                                       ((256,), (16,)), ((64, 64), (8, 8))])
 def test_adjoint_lane_groups_match_oracle(fx, shape, lam):
     say("adjoint lanes", shape, lam)
     dx = tuple(1.0 for _ in shape)
@@ -190,8 +191,9 @@ def test_adjoint_lane_groups_match_oracle(fx, shape, lam):
     assert rel(g, oracle.expand_adjoint(y_np, dx, 1.0, 7.0, lam)) <= TOL64
 
 
-def test_adjoint_fp32_form_matches_oracle(fx):
-    shape, lam, dx = (48, 64), (4, 32), (1.0, 1.0)
+@pytest.mark.parametrize("shape,lam", [((48, 64), (4, 32)), ((512,), (32,)), ((64, 128), (8, 8))])
+def test_adjoint_fp32_form_matches_oracle(fx, shape, lam):
+    dx = (1.0,) * len(shape)
     say("adjoint fp32", shape, lam)
     y_np = workloads.random_field(shape, 34)
     plan = fx.get_plan(shape, dx, 1.0, 9.0, lam, dtype=torch.complex64)
