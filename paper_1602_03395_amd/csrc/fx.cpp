@@ -168,8 +168,19 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
         g.TS = g.eas ? eas_tile_lines(p->ax[ax].g)
                      : reg_eh ? ehr_tile_lines(p->ax[ax].g)
                               : reg ? cfp_tile_lines(p->ax[ax].g) : choose_ts(p, kind, p->ax[ax].M, g.A, g.S);
-        if (g.S == 1) g.ntiles = (g.A + g.TS - 1) / g.TS;
-        else g.ntiles = g.A * ((g.S + g.TS - 1) / g.TS);
+        auto set_tiles = [&]() {
+            if (g.S == 1) g.ntiles = (g.A + g.TS - 1) / g.TS;
+            else g.ntiles = g.A * ((g.S + g.TS - 1) / g.TS);
+        };
+        set_tiles();
+        if (!reg && (kind == Kind::EH || kind == Kind::EAH)) {
+            // these sum every term inside the workgroup: fewer lines per tile when the tiles alone
+            // would leave CUs idle
+            while (g.TS > 1 && g.Qin * g.ntiles < 2 * (int64_t)num_cus()) {
+                g.TS = (g.TS + 1) / 2;
+                set_tiles();
+            }
+        }
         g.max_blocks = p->persist > 0 ? p->persist * num_cus() : 0;
         g.reg_a = (kind == Kind::A || kind == Kind::AH) && p->use_asr && asr_applicable(p->ax[ax].g, p->asr_max_g);
         if (reg && kind == Kind::EA) {
