@@ -362,6 +362,23 @@ def main():
         tag = f"{wl.name}/{dtype_name}/{args.schedule}" + ("" if args.variant == "free" else f"/{args.variant}")
         roofline["traffic"] = load_traffic(tag, dom["key"])
 
+    # Whole-step HBM view: (1) measured bytes (copy-calibrated counters of every pass, while they
+    # match the kernel sources) over the step time, (2) the per-term streaming model (two M-point
+    # round trips per term: 2 Q M complex per solve) over the step time, which the shared per-axis
+    # prefixes and the register-resident transforms beat, so it exceeds 1 (the passes are bound by
+    # VALU issue, see roofline).
+    step_s = ms_per_step * 1e-3
+    hbm = {"peak_GBs": PEAK_HBM_GBS, "stream_model_bytes_per_step": 2.0 * terms * int(np.prod(psi.shape)) * csize}
+    hbm["stream_model_frac"] = hbm["stream_model_bytes_per_step"] / step_s / 1e9 / PEAK_HBM_GBS
+    measured = [load_traffic(tag, r["key"]) for r in pass_rows] if pass_rows else []
+    if measured and all(m is not None for m in measured):
+        tot = sum(m * r["launches_per_step"] for m, r in zip(measured, pass_rows))
+        hbm["measured_bytes_per_step"] = tot
+        hbm["measured_GBs"] = tot / step_s / 1e9
+        hbm["measured_frac"] = hbm["measured_GBs"] / PEAK_HBM_GBS
+    else:
+        hbm["measured_bytes_per_step"] = None
+
     result = {
         "metric": "expanded lattice pts/s + HBM roofline %, FP32/FP64-phase vs FP64 at 1e-5 err",
         "value": value,
@@ -382,6 +399,7 @@ def main():
                    "outer_block": desc["outer_block"]},
         "q_term_pts_per_s": npts * terms / (ms_per_step * 1e-3),
         "roofline": roofline,
+        "hbm": hbm,
         "passes": pass_rows,
     }
 

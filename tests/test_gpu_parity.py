@@ -327,6 +327,26 @@ def test_batch_ragged_matches_single_plans_and_replays(fx):
                 assert np.array_equal(outs[i].cpu().numpy(), first[i])
 
 
+def test_batch_with_register_passes_matches_oracle(fx):
+    # a ragged batch whose classes run the register kernels, the fused structured EA pass
+    # (64-point axis, g = 8, P = 8) and the register EA pass (32-point axis, P = 4), in one graph
+    shapes = [(64, 6, 8), (32, 6, 8), (64, 6, 8)]
+    lam = (8, 2, 2)
+    say("batch register passes", shapes)
+    specs = [dict(shape=s, dx=(1.0, 1.0, 1.0), lam=lam, t=11.0) for s in shapes]
+    fields = [workloads.random_field(s, 700 + i) for i, s in enumerate(shapes)]
+    for dtype, tol in ((torch.complex128, 1e-12), (torch.complex64, 1e-5)):
+        psis = [torch.from_numpy(f).to(dtype).cuda() for f in fields]
+        b = fx.Batch(specs, dtype=dtype)
+        outs, rhos = b.run(psis)
+        torch.cuda.synchronize()
+        for i, s in enumerate(shapes):
+            ref = oracle.expand(psis[i].cpu().numpy().astype(np.complex128), (1.0,) * 3, 1.0, 11.0, lam)
+            if dtype == torch.complex128:
+                assert rel(outs[i].cpu().numpy(), ref) <= tol
+            assert rel(rhos[i].cpu().numpy(), oracle.density(ref)) <= tol
+
+
 def test_batch_rejects_bad_arguments(fx):
     with pytest.raises(ValueError):
         fx.Batch([dict(shape=(8,), dx=1.0, lam=2, t=1.0), dict(shape=(8,), dx=1.0, lam=0, t=1.0)])
