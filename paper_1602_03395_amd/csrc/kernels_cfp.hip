@@ -1028,16 +1028,17 @@ __global__ __launch_bounds__(kThreads) void k_AA(const C<T>* __restrict__ in, C<
     }
 }
 
-// Structured accumulate for g = 8K (K = 2, 4, 8 lanes per group): lane k of a group keeps the
-// eight residues j = k + K m (m < 8). With c = c1 + 8 c2 the g-point inverse transform splits as
-//   out[c1 + 8 c2] = sum_k exp(2 pi i k c2 / K) exp(2 pi i k c1 / g) sum_m exp(2 pi i m c1 / 8) H[k + K m],
-// an 8-point transform in registers, a twiddle, and a K-point transform across the K lanes
+// Structured accumulate for g = R K (K lanes per group, R = 8 or 4 residues per lane): lane k of a
+// group keeps the residues j = k + K m (m < R). With c = c1 + R c2 the g-point inverse transform
+// splits as
+//   out[c1 + R c2] = sum_k exp(2 pi i k c2 / K) exp(2 pi i k c1 / g) sum_m exp(2 pi i m c1 / R) H[k + K m],
+// an R-point transform in registers, a twiddle, and a K-point transform across the K lanes
 // (radix-2 decimation in frequency; lane k ends with c2 = bitrev(k)).
-template <typename T, int K>
+template <typename T, int K, int R>
 __global__ __launch_bounds__(kThreads) void k_ASK(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
                                                   PassGeom g, int accumulate, T* __restrict__ rho) {
-    constexpr int G = 8 * K;
-    constexpr int LK = (K == 8) ? 3 : (K == 4) ? 2 : 1;
+    constexpr int G = R * K;
+    constexpr int LK = (K == 16) ? 4 : (K == 8) ? 3 : (K == 4) ? 2 : (K == 2) ? 1 : 0;
     const int M = ax.M, P = ax.P;
     const int64_t S = g.S;
     const int64_t PS = (int64_t)P * S;
@@ -1048,9 +1049,9 @@ __global__ __launch_bounds__(kThreads) void k_ASK(const C<T>* __restrict__ in, C
     const int k = (int)(threadIdx.x & (K - 1));  // the grid stride is a multiple of K
     int kr = 0;                                  // bitrev_LK(k)
     for (int b = 0; b < LK; ++b) kr |= ((k >> b) & 1) << (LK - 1 - b);
-    C<T> w1[8];  // exp(2 pi i k c1 / g)
+    C<T> w1[R];  // exp(2 pi i k c1 / g)
 #pragma unroll
-    for (int c1 = 0; c1 < 8; ++c1) {
+    for (int c1 = 0; c1 < R; ++c1) {
         const C<T> t = twg[((k * c1) % G) * P];
         w1[c1] = mk<T>(t.x, -t.y);
     }
@@ -1063,29 +1064,29 @@ __global__ __launch_bounds__(kThreads) void k_ASK(const C<T>* __restrict__ in, C
         const int n0 = grp.n0, r = grp.r;
         const C<T>* src = in + (qo * g.qn * g.A + a) * PS + (int64_t)r * S + s;
         const C<T>* tf = Tf + (int64_t)g.qb * M + n0;
-        C<T> h[8];
+        C<T> h[R];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) h[m] = mk<T>(0, 0);
+        for (int m = 0; m < R; ++m) h[m] = mk<T>(0, 0);
         int i0 = 0;
         for (; i0 + G <= g.qn; i0 += G) {
-            C<T> av[8], bv[8];
+            C<T> av[R], bv[R];
 #pragma unroll
-            for (int m = 0; m < 8; ++m) {
+            for (int m = 0; m < R; ++m) {
                 const int i = i0 + k + K * m;
                 av[m] = tf[(int64_t)i * M];
                 bv[m] = src[(int64_t)i * step];
             }
 #pragma unroll
-            for (int m = 0; m < 8; ++m) h[m] = cfma<T>(h[m], av[m], bv[m]);
+            for (int m = 0; m < R; ++m) h[m] = cfma<T>(h[m], av[m], bv[m]);
         }
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
+        for (int m = 0; m < R; ++m) {
             const int i = i0 + k + K * m;
             if (i < g.qn) h[m] = cfma<T>(h[m], tf[(int64_t)i * M], src[(int64_t)i * step]);
         }
-        RegDFT<T, 8, true>::run(h);
+        RegDFT<T, R, true>::run(h);
 #pragma unroll
-        for (int c1 = 1; c1 < 8; ++c1) h[c1] = cmul<T>(h[c1], w1[c1]);
+        for (int c1 = 1; c1 < R; ++c1) h[c1] = cmul<T>(h[c1], w1[c1]);
         // K-point inverse transform across the lanes, decimation in frequency
 #pragma unroll
         for (int st = LK - 1; st >= 0; --st) {
@@ -1096,14 +1097,14 @@ __global__ __launch_bounds__(kThreads) void k_ASK(const C<T>* __restrict__ in, C
             const C<T> t = twg[(int64_t)jj * (M / (2 * hh))];
             const C<T> om = mk<T>(t.x, -t.y);
 #pragma unroll
-            for (int c1 = 0; c1 < 8; ++c1) {
+            for (int c1 = 0; c1 < R; ++c1) {
                 const C<T> b = shfl_xor_c<T>(h[c1], hh);
                 h[c1] = upper ? cmul<T>(csub<T>(b, h[c1]), om) : cadd<T>(h[c1], b);
             }
         }
 #pragma unroll
-        for (int c1 = 0; c1 < 8; ++c1) {
-            const int c = c1 + 8 * kr;
+        for (int c1 = 0; c1 < R; ++c1) {
+            const int c = c1 + R * kr;
             C<T> v = h[c1];
             if (qbr != 0) v = cmulc<T>(v, twg[((qbr * c) % G) * P]);  // exp(+2 pi i qb c / g)
             const int64_t o = (row * M + n0 + (int64_t)P * c) * S + s;
@@ -1163,15 +1164,15 @@ __global__ __launch_bounds__(kThreads) void k_AHR(const C<T>* __restrict__ in, C
     }
 }
 
-// AH in register form for g = 8K (K = 2, 4, 8 lanes per group), the transpose of k_ASK: lane k
-// reads y[c1 + 8 bitrev(k)] (c1 < 8), a K-point forward transform across the lanes (decimation
-// in time on bit-reversed input) gives Z[c1] = sum_c2 exp(-2 pi i k c2 / K) y[c1 + 8 c2], the
-// twiddle exp(-2 pi i k c1 / g), and an 8-point transform over c1 leaves Yh[k + K m] (m < 8).
-template <typename T, int K>
+// AH in register form for g = R K (K lanes per group, R = 8 or 4 residues per lane), the transpose
+// of k_ASK: lane k reads y[c1 + R bitrev(k)] (c1 < R), a K-point forward transform across the lanes
+// (decimation in time on bit-reversed input) gives Z[c1] = sum_c2 exp(-2 pi i k c2 / K) y[c1 + R c2],
+// the twiddle exp(-2 pi i k c1 / g), and an R-point transform over c1 leaves Yh[k + K m] (m < R).
+template <typename T, int K, int R>
 __global__ __launch_bounds__(kThreads) void k_AHK(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
                                                   PassGeom g, int accumulate) {
-    constexpr int G = 8 * K;
-    constexpr int LK = (K == 8) ? 3 : (K == 4) ? 2 : 1;
+    constexpr int G = R * K;
+    constexpr int LK = (K == 16) ? 4 : (K == 8) ? 3 : (K == 4) ? 2 : (K == 2) ? 1 : 0;
     const int M = ax.M, P = ax.P;
     const int64_t S = g.S;
     const int64_t PS = (int64_t)P * S;
@@ -1183,11 +1184,11 @@ __global__ __launch_bounds__(kThreads) void k_AHK(const C<T>* __restrict__ in, C
     int kr = 0;                                  // bitrev_LK(k)
     for (int b = 0; b < LK; ++b) kr |= ((k >> b) & 1) << (LK - 1 - b);
     // cross-lane stage twiddles (select-free form; its rescale goes into w1)
-    C<T> wst[LK];
+    C<T> wst[LK > 0 ? LK : 1];
     const C<T> fin = lane_twiddles_x<T, LK, false>(wst, k, twg, M);
-    C<T> w1[8];  // exp(-2 pi i k c1 / g) times the rescale
+    C<T> w1[R];  // exp(-2 pi i k c1 / g) times the rescale
 #pragma unroll
-    for (int c1 = 0; c1 < 8; ++c1) w1[c1] = cmul<T>(twg[((k * c1) % G) * P], fin);
+    for (int c1 = 0; c1 < R; ++c1) w1[c1] = cmul<T>(twg[((k * c1) % G) * P], fin);
     const int qbr = g.qb % G;
     const int64_t nthreads = ngroups * K;
     for (int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gt < nthreads;
@@ -1196,30 +1197,30 @@ __global__ __launch_bounds__(kThreads) void k_AHK(const C<T>* __restrict__ in, C
         const C<T>* src = in + (grp.row * M + grp.n0) * S + grp.s;
         C<T>* dst = out + (grp.qo * g.qn * g.A + grp.a) * PS + (int64_t)grp.r * S + grp.s;
         const C<T>* tf = Tf + (int64_t)g.qb * M + grp.n0;
-        C<T> h[8];
+        C<T> h[R];
 #pragma unroll
-        for (int c1 = 0; c1 < 8; ++c1) h[c1] = src[(int64_t)(c1 + 8 * kr) * PS];
+        for (int c1 = 0; c1 < R; ++c1) h[c1] = src[(int64_t)(c1 + R * kr) * PS];
         if (qbr != 0) {
 #pragma unroll
-            for (int c1 = 0; c1 < 8; ++c1) h[c1] = cmul<T>(h[c1], twg[((qbr * (c1 + 8 * kr)) % G) * P]);
+            for (int c1 = 0; c1 < R; ++c1) h[c1] = cmul<T>(h[c1], twg[((qbr * (c1 + R * kr)) % G) * P]);
         }
 #pragma unroll
         for (int st = 0; st < LK; ++st) {
 #pragma unroll
-            for (int c1 = 0; c1 < 8; ++c1) h[c1] = cfma<T>(h[c1], wst[st], shfl_xor_c<T>(h[c1], 1 << st));
+            for (int c1 = 0; c1 < R; ++c1) h[c1] = cfma<T>(h[c1], wst[st], shfl_xor_c<T>(h[c1], 1 << st));
         }
 #pragma unroll
-        for (int c1 = 0; c1 < 8; ++c1) h[c1] = cmul<T>(h[c1], w1[c1]);
-        RegDFT<T, 8, false>::run(h);
+        for (int c1 = 0; c1 < R; ++c1) h[c1] = cmul<T>(h[c1], w1[c1]);
+        RegDFT<T, R, false>::run(h);
         for (int i0 = 0; i0 < g.qn; i0 += G) {
-            C<T> t[8];
+            C<T> t[R];
 #pragma unroll
-            for (int m = 0; m < 8; ++m) {
+            for (int m = 0; m < R; ++m) {
                 const int i = i0 + k + K * m;
                 if (i < g.qn) t[m] = tf[(int64_t)i * M];
             }
 #pragma unroll
-            for (int m = 0; m < 8; ++m) {
+            for (int m = 0; m < R; ++m) {
                 const int i = i0 + k + K * m;
                 if (i < g.qn) {
                     C<T>* o = dst + (int64_t)i * step;
@@ -1411,16 +1412,26 @@ hipError_t launch_asr(const void* in, void* out, const AxisDev& ax, const PassGe
     return hipGetLastError();
 }
 
-template <typename T, int K>
+template <typename T, int K, int R = 8>
 hipError_t launch_ask(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
                       hipStream_t st) {
     const int64_t nthreads = g.Qin * g.A * (int64_t)ax.P * g.S * K;
     const int bs = acc_block(nthreads);
     int64_t blocks = (nthreads + bs - 1) / bs;
     if (blocks > (1 << 20)) blocks = 1 << 20;
-    hipLaunchKernelGGL((k_ASK<T, K>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(bs), 0, st,
+    hipLaunchKernelGGL((k_ASK<T, K, R>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(bs), 0, st,
                        (const C<T>*)in, (C<T>*)out, ax, g, accumulate, (T*)rho);
     return hipGetLastError();
+}
+
+// Residues per lane of the lane-group accumulate: 4 (twice the lanes of 8 for the same g, more
+// wavefronts for these latency-bound passes; C2 A passes 8.2 -> 7.6 us), FX_ASK_R=8 for 8.
+int ask_residues() {
+    static const int r = [] {
+        const char* e = std::getenv("FX_ASK_R");
+        return (e && std::atoi(e) == 8) ? 8 : 4;
+    }();
+    return r;
 }
 
 template <typename T, int G>
@@ -1435,14 +1446,14 @@ hipError_t launch_ahr(const void* in, void* out, const AxisDev& ax, const PassGe
     return hipGetLastError();
 }
 
-template <typename T, int K>
+template <typename T, int K, int R>
 hipError_t launch_ahk(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
                       hipStream_t st) {
     const int64_t nthreads = g.Qin * g.A * (int64_t)ax.P * g.S * K;
     const int bs = acc_block(nthreads);
     int64_t blocks = (nthreads + bs - 1) / bs;
     if (blocks > (1 << 20)) blocks = 1 << 20;
-    hipLaunchKernelGGL((k_AHK<T, K>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(bs), 0, st,
+    hipLaunchKernelGGL((k_AHK<T, K, R>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(bs), 0, st,
                        (const C<T>*)in, (C<T>*)out, ax, g, accumulate);
     return hipGetLastError();
 }
@@ -1451,13 +1462,19 @@ template <typename T>
 hipError_t launch_ahr_T(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
                         hipStream_t st) {
     switch (ax.g) {
-        case 64: return launch_ahk<T, 8>(in, out, ax, g, accumulate, st);
+        case 64:
+            return ask_residues() == 4 ? launch_ahk<T, 16, 4>(in, out, ax, g, accumulate, st)
+                                       : launch_ahk<T, 8, 8>(in, out, ax, g, accumulate, st);
         case 1: return launch_ahr<T, 1>(in, out, ax, g, accumulate, st);
         case 2: return launch_ahr<T, 2>(in, out, ax, g, accumulate, st);
         case 4: return launch_ahr<T, 4>(in, out, ax, g, accumulate, st);
         case 8: return launch_ahr<T, 8>(in, out, ax, g, accumulate, st);
-        case 16: return launch_ahk<T, 2>(in, out, ax, g, accumulate, st);
-        case 32: return launch_ahk<T, 4>(in, out, ax, g, accumulate, st);
+        case 16:
+            return ask_residues() == 4 ? launch_ahk<T, 4, 4>(in, out, ax, g, accumulate, st)
+                                       : launch_ahk<T, 2, 8>(in, out, ax, g, accumulate, st);
+        case 32:
+            return ask_residues() == 4 ? launch_ahk<T, 8, 4>(in, out, ax, g, accumulate, st)
+                                       : launch_ahk<T, 4, 8>(in, out, ax, g, accumulate, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1466,13 +1483,19 @@ template <typename T>
 hipError_t launch_asr_T(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
                         hipStream_t st) {
     switch (ax.g) {
-        case 64: return launch_ask<T, 8>(in, out, ax, g, accumulate, rho, st);
+        case 64:
+            return ask_residues() == 4 ? launch_ask<T, 16, 4>(in, out, ax, g, accumulate, rho, st)
+                                       : launch_ask<T, 8>(in, out, ax, g, accumulate, rho, st);
         case 1: return launch_asr<T, 1>(in, out, ax, g, accumulate, rho, st);
         case 2: return launch_asr<T, 2>(in, out, ax, g, accumulate, rho, st);
         case 4: return launch_asr<T, 4>(in, out, ax, g, accumulate, rho, st);
         case 8: return launch_asr<T, 8>(in, out, ax, g, accumulate, rho, st);
-        case 16: return launch_ask<T, 2>(in, out, ax, g, accumulate, rho, st);
-        case 32: return launch_ask<T, 4>(in, out, ax, g, accumulate, rho, st);
+        case 16:
+            return ask_residues() == 4 ? launch_ask<T, 4, 4>(in, out, ax, g, accumulate, rho, st)
+                                       : launch_ask<T, 2>(in, out, ax, g, accumulate, rho, st);
+        case 32:
+            return ask_residues() == 4 ? launch_ask<T, 8, 4>(in, out, ax, g, accumulate, rho, st)
+                                       : launch_ask<T, 4>(in, out, ax, g, accumulate, rho, st);
         default: return hipErrorInvalidValue;
     }
 }
