@@ -763,10 +763,16 @@ __global__ __launch_bounds__(kEaWaves * kWave) void k_EAS(const C<T>* __restrict
         om[st] = mk<T>(t.x, -t.y);
     }
     const int qbr = g.qb % G;
-    const int64_t total = g.Qin * g.ntiles;  // < 2^31 (host check)
-    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
-        const int64_t qi = (int64_t)((unsigned)bid / (unsigned)g.ntiles);
-        const int64_t tt = bid - qi * g.ntiles;
+    // XCD-contiguous order: workgroups are dispatched round-robin over the 8 XCDs (id mod 8), so
+    // tile (id mod 8) T8 + id / 8 gives each XCD a contiguous range of tiles, and the neighbouring
+    // tiles that share the cache lines of a strided row meet in one L2
+    const int64_t ntl = g.Qin * g.ntiles;  // < 2^31 (host check)
+    const int64_t T8 = (ntl + 7) / 8;
+    for (int64_t bid = blockIdx.x; bid < 8 * T8; bid += gridDim.x) {
+        const int64_t tile = (bid & 7) * T8 + (bid >> 3);
+        if (tile >= ntl) continue;  // uniform over the workgroup
+        const int64_t qi = (int64_t)((unsigned)tile / (unsigned)g.ntiles);
+        const int64_t tt = tile - qi * g.ntiles;
         const Tile tl = decode_tile(g, tt);
         const bool live = l < tl.nl;
         // the tile's lines into LDS (TS M = 64 P <= 2 kEaWaves kWave values: two per thread, both
@@ -1550,8 +1556,8 @@ hipError_t launch_eas(const void* in, void* out, const AxisDev& ax, const PassGe
                       hipStream_t st) {
     constexpr int G = 8 * K;
     constexpr int TS = kWave / G;
-    int64_t blocks = g.Qin * g.ntiles;
-    if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = g.max_blocks;
+    int64_t blocks = (g.Qin * g.ntiles + 7) / 8 * 8;  // the kernel's XCD-contiguous order
+    if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = (g.max_blocks + 7) / 8 * 8;
     if (blocks > (1 << 22)) blocks = 1 << 22;
     const size_t lds = ((size_t)TS * ax.M + (size_t)TS * P * G + (size_t)g.qn * P) * sizeof(C<T>);
     hipError_t e = prep_lds((const void*)k_EAS<T, P, K>, lds);
