@@ -437,10 +437,12 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
     const int n2 = (int)threadIdx.x & (G - 1);
     const int qc = g.qc;
     const int nqc = (g.qn + qc - 1) / qc;
-    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs (id mod 8), so the
-    // nqc workgroups of one tile get ids of equal residue mod 8 and share that XCD's L2 copy of it
+    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs (id mod 8); XCD x
+    // takes the contiguous tile range [x T8, (x + 1) T8) with all nqc workgroups of each tile, so
+    // a tile is read into one L2, and so are the neighbouring tiles that share its cache lines
     const int64_t ntl = g.Qin * g.ntiles;
-    const int64_t total = ((ntl + 7) / 8) * 8 * nqc;
+    const int64_t T8 = (ntl + 7) / 8;
+    const int64_t total = T8 * 8 * nqc;
     const int lk = (lgG < LP) ? lgG : LP;     // reduce-scatter steps
     const int cnt = P >> lk;                  // values a lane holds afterwards
     int base = 0;
@@ -456,7 +458,7 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
         // every id and index here is below 2^31 (checked on the host): 32-bit division
         const unsigned rr = (unsigned)bid >> 3;
         const int ci = (int)(rr % (unsigned)nqc);
-        const int64_t tile = (int64_t)((rr / (unsigned)nqc) * 8u + ((unsigned)bid & 7u));
+        const int64_t tile = ((int64_t)bid & 7) * T8 + (int64_t)(rr / (unsigned)nqc);
         if (tile >= ntl) continue;  // uniform over the workgroup
         const int64_t qi = (int64_t)((unsigned)tile / (unsigned)g.ntiles);
         const int64_t tt = tile - qi * g.ntiles;
