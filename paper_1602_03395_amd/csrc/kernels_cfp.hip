@@ -1268,10 +1268,14 @@ __global__ __launch_bounds__(kEhWaves * kWave) void k_EHR(const C<T>* __restrict
     for (int e = tid; e < g.qn * P; e += kEhWaves * kWave)
         TAs[e] = TA[(int64_t)(g.qb + e / P) * M + ((e % P) << lgG)];
     __syncthreads();
-    const int64_t total = g.Qin * g.ntiles;  // < 2^31 (host check)
-    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
-        const int64_t qo = (int64_t)((unsigned)bid / (unsigned)g.ntiles);
-        const int64_t tt = bid - qo * g.ntiles;
+    // XCD-contiguous tile order (as in k_EAS): neighbouring strided tiles meet in one L2
+    const int64_t ntl = g.Qin * g.ntiles;  // < 2^31 (host check)
+    const int64_t T8 = (ntl + 7) / 8;
+    for (int64_t bid = blockIdx.x; bid < 8 * T8; bid += gridDim.x) {
+        const int64_t tile = (bid & 7) * T8 + (bid >> 3);
+        if (tile >= ntl) continue;  // uniform over the workgroup
+        const int64_t qo = (int64_t)((unsigned)tile / (unsigned)g.ntiles);
+        const int64_t tt = tile - qo * g.ntiles;
         const Tile tl = decode_tile(g, tt);
         const bool live = l < tl.nl;
         C<T> acc[P];
@@ -1528,8 +1532,8 @@ hipError_t launch_pass_asr(Kind kind, bool dbl, const void* in, void* out, const
 template <typename T, int P>
 hipError_t launch_ehr(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
                       hipStream_t st) {
-    int64_t blocks = g.Qin * g.ntiles;
-    if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = g.max_blocks;
+    int64_t blocks = (g.Qin * g.ntiles + 7) / 8 * 8;  // the kernel's XCD-contiguous order
+    if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = (g.max_blocks + 7) / 8 * 8;
     if (blocks > (1 << 22)) blocks = 1 << 22;
     const size_t lds = ((size_t)kEhWaves * P * kWave + (size_t)g.qn * P) * sizeof(C<T>);
     hipError_t e = prep_lds((const void*)k_EHR<T, P>, lds);
