@@ -271,23 +271,27 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
             const int u = ou.axis, v = ov.axis;
             const AxisDev& au = p->ax[u];
             const AxisDev& av = p->ax[v];
-            if (u < v && aa_applicable(p->dbl, au.g, av.g) &&
-                (int64_t)aa_lds_bytes(p->dbl, au.g, av.g) <= lds_limit_bytes()) {
+            AAGeom a;
+            a.O = ov.g.Qin;
+            a.qn_u = ou.g.qn;
+            a.qb_u = ou.g.qb;
+            a.qn_v = ov.g.qn;
+            a.qb_v = ov.g.qb;
+            // lengths of the other axes as the fused pass sees them (u and v excluded)
+            a.X = ou.g.A;                               // axes before u
+            a.Z = ov.g.S;                               // axes after v
+            a.Y = u < v ? ou.g.S / ((int64_t)av.P * a.Z) : 0;  // axes between u and v
+            a.tsg = aa_tile_groups(au.g, av.g);
+            // the register form wherever it applies; the LDS form only when asked for (FX_AA=1)
+            const bool reg = u < v && aar_applicable(au.g, av.g, a);
+            const bool lds = u < v && p->use_aa == 2 && aa_applicable(p->dbl, au.g, av.g) &&
+                             (int64_t)aa_lds_bytes(p->dbl, au.g, av.g) <= lds_limit_bytes();
+            if (reg || lds) {
                 Op f = ou;
                 f.kind = Kind::AA;
                 f.axis2 = v;
                 f.out_elems = ov.out_elems;
-                AAGeom& a = f.aa;
-                a.O = ov.g.Qin;
-                a.qn_u = ou.g.qn;
-                a.qb_u = ou.g.qb;
-                a.qn_v = ov.g.qn;
-                a.qb_v = ov.g.qb;
-                // lengths of the other axes as the fused pass sees them (u and v excluded)
-                a.X = ou.g.A;                               // axes before u
-                a.Z = ov.g.S;                               // axes after v
-                a.Y = ou.g.S / ((int64_t)av.P * a.Z);       // axes between u and v
-                a.tsg = aa_tile_groups(au.g, av.g);
+                f.aa = a;
                 ops.pop_back();
                 ops.back() = f;
             }
@@ -608,7 +612,7 @@ fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_pla
     if (const char* e = std::getenv("FX_NO_P2")) p->use_p2 = (e[0] != '1');
     if (const char* e = std::getenv("FX_NO_CFP")) p->use_cfp = (e[0] != '1');
     if (const char* e = std::getenv("FX_NO_ASR")) p->use_asr = (e[0] != '1');
-    if (const char* e = std::getenv("FX_AA")) p->use_aa = (e[0] == '1');
+    if (const char* e = std::getenv("FX_AA")) p->use_aa = (e[0] == '1') ? 2 : 0;
     if (const char* e = std::getenv("FX_EAS")) p->use_eas = (e[0] == '1') ? 2 : 1;
     if (std::getenv("FX_NO_EAS")) p->use_eas = 0;
     if (const char* e = std::getenv("FX_ASR_MAXG")) p->asr_max_g = std::max(1, std::atoi(e));

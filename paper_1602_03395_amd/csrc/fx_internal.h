@@ -137,6 +137,8 @@ struct AAGeom {
     int tsg = 1;  // groups per workgroup
 };
 bool aa_applicable(bool dbl, int gu, int gv);
+// Register form of the fused pass (k_AAR): g_u = g_v = 16 or 32, axes u, v the last two (Y = Z = 1).
+bool aar_applicable(int gu, int gv, const AAGeom& g);
 int aa_tile_groups(int gu, int gv);
 size_t aa_lds_bytes(bool dbl, int gu, int gv);
 hipError_t launch_pass_aa(bool dbl, const void* in, void* out, const AxisDev& au, const AxisDev& av, const AAGeom& g,

@@ -1036,6 +1036,163 @@ __global__ __launch_bounds__(kThreads) void k_AA(const C<T>* __restrict__ in, C<
     }
 }
 
+// The last two accumulate passes (axes u < v, the last two axes: Y = Z = 1) in registers for
+// g_u = g_v = G (16 or 32). The G x G inverse transform of a group (the one k_AA does in LDS) runs
+// as two structured accumulates: G K threads per group (K = G / 4), thread (j_v, k) first holds
+// H[k + K m][j_v] (m < 4), transforms over j_u as the one-axis register accumulate does (a 4-point
+// transform in registers, a twiddle, a K-point transform across the K lanes), passes its values
+// through LDS so that thread (c_u, k) holds j_v = k + K m of row c_u, and transforms over j_v the
+// same way. Workgroups take the groups in XCD-contiguous ranges: the groups of one output line
+// (all n0_v of an n0_u) write the same cache lines.
+template <typename T, int G>
+__global__ __launch_bounds__(kThreads) void k_AAR(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev au,
+                                                  AxisDev av, AAGeom g, int accumulate, T* __restrict__ rho) {
+    constexpr int R = 4;
+    constexpr int K = G / R;
+    constexpr int LK = (K == 8) ? 3 : (K == 4) ? 2 : 1;
+    constexpr int TPG = G * K;          // threads per group
+    constexpr int NG = kThreads / TPG;  // groups per workgroup
+    constexpr int LDR = G + 1;          // LDS row stride
+    static_assert(TPG * NG == kThreads, "group size must divide the workgroup");
+    __shared__ __align__(16) unsigned char smem_aar[NG * G * LDR * sizeof(C<T>)];
+    const int Pu = au.P, Pv = av.P, Mu = au.M, Mv = av.M;
+    const int slot = (int)threadIdx.x / TPG;
+    const int tt = (int)threadIdx.x % TPG;
+    const int row = tt / K;  // j_v in the first transform, c_u in the second
+    const int k = tt % K;
+    C<T>* Sg = (C<T>*)smem_aar + slot * G * LDR;
+    int kr = 0;  // bitrev_LK(k)
+    for (int b = 0; b < LK; ++b) kr |= ((k >> b) & 1) << (LK - 1 - b);
+    const C<T>* tu = (const C<T>*)au.tw;
+    const C<T>* tv = (const C<T>*)av.tw;
+    C<T> w1u[R], w1v[R];  // exp(2 pi i k c1 / G) of each axis
+#pragma unroll
+    for (int c1 = 0; c1 < R; ++c1) {
+        const C<T> a = tu[((k * c1) % G) * Pu];
+        const C<T> b = tv[((k * c1) % G) * Pv];
+        w1u[c1] = mk<T>(a.x, -a.y);
+        w1v[c1] = mk<T>(b.x, -b.y);
+    }
+    const C<T>* Tfu = (const C<T>*)au.Tf;
+    const C<T>* Tfv = (const C<T>*)av.Tf;
+    const int qnu = g.qn_u, qnv = g.qn_v;
+    const int qru = g.qb_u % G, qrv = g.qb_v % G;
+    const int64_t X = g.X;
+    const int64_t PP = (int64_t)Pu * Pv;
+    const int64_t step_u = X * PP;              // input stride of one term along u
+    const int64_t step_v = (int64_t)qnu * step_u;  // input stride of one term along v
+    const int64_t ngroups = g.O * X * PP;
+    const int64_t ntl = (ngroups + NG - 1) / NG;
+    const int64_t T8 = (ntl + 7) / 8;
+    const int64_t total = T8 * 8;
+    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
+        const int64_t tile = (bid & 7) * T8 + (bid >> 3);
+        if (tile >= ntl) continue;  // uniform over the workgroup
+        const int64_t gid = tile * NG + slot;
+        const bool live = gid < ngroups;
+        const int64_t gq = live ? gid : 0;
+        const int n0v = (int)(gq % Pv);
+        const int n0u = (int)((gq / Pv) % Pu);
+        const int64_t ox = gq / PP;
+        const int64_t x = ox % X, o = ox / X;
+        const int ru = (int)(((int64_t)n0u * au.lg) % Pu);
+        const int rv = (int)(((int64_t)n0v * av.lg) % Pv);
+        const C<T>* src = in + ((o * qnv * qnu) * X + x) * PP + (int64_t)ru * Pv + rv;
+        const C<T>* tfu = Tfu + (int64_t)g.qb_u * Mu + n0u;
+        const C<T>* tfv = Tfv + (int64_t)g.qb_v * Mv + n0v;
+        // H[k + K m][row]: the terms i_u = j_u (mod G), i_v = row (mod G)
+        C<T> h[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) h[m] = mk<T>(0, 0);
+        if (live) {
+            for (int iv = row; iv < qnv; iv += G) {
+                const C<T> fv = tfv[(int64_t)iv * Mv];
+                const C<T>* sv = src + (int64_t)iv * step_v;
+                C<T> su[R];
+#pragma unroll
+                for (int m = 0; m < R; ++m) su[m] = mk<T>(0, 0);
+                int i0 = 0;
+                for (; i0 + G <= qnu; i0 += G) {
+                    C<T> a[R], b[R];
+#pragma unroll
+                    for (int m = 0; m < R; ++m) {
+                        const int i = i0 + k + K * m;
+                        a[m] = tfu[(int64_t)i * Mu];
+                        b[m] = sv[(int64_t)i * step_u];
+                    }
+#pragma unroll
+                    for (int m = 0; m < R; ++m) su[m] = cfma<T>(su[m], a[m], b[m]);
+                }
+#pragma unroll
+                for (int m = 0; m < R; ++m) {
+                    const int i = i0 + k + K * m;
+                    if (i < qnu) su[m] = cfma<T>(su[m], tfu[(int64_t)i * Mu], sv[(int64_t)i * step_u]);
+                }
+#pragma unroll
+                for (int m = 0; m < R; ++m) h[m] = cfma<T>(h[m], fv, su[m]);
+            }
+        }
+        // transform over j_u; lane k ends with c_u = c1 + R bitrev(k)
+        RegDFT<T, R, true>::run(h);
+#pragma unroll
+        for (int c1 = 1; c1 < R; ++c1) h[c1] = cmul<T>(h[c1], w1u[c1]);
+#pragma unroll
+        for (int st = LK - 1; st >= 0; --st) {
+            const int hh = 1 << st;
+            const bool upper = (k & hh) != 0;
+            const C<T> t = tu[(int64_t)(k & (hh - 1)) * (Mu / (2 * hh))];
+            const C<T> om = mk<T>(t.x, -t.y);
+#pragma unroll
+            for (int c1 = 0; c1 < R; ++c1) {
+                const C<T> b = shfl_xor_c<T>(h[c1], hh);
+                h[c1] = upper ? cmul<T>(csub<T>(b, h[c1]), om) : cadd<T>(h[c1], b);
+            }
+        }
+#pragma unroll
+        for (int c1 = 0; c1 < R; ++c1) Sg[(c1 + R * kr) * LDR + row] = h[c1];
+        __syncthreads();
+        // row c_u = row: j_v = k + K m
+#pragma unroll
+        for (int m = 0; m < R; ++m) h[m] = Sg[row * LDR + k + K * m];
+        RegDFT<T, R, true>::run(h);
+#pragma unroll
+        for (int c1 = 1; c1 < R; ++c1) h[c1] = cmul<T>(h[c1], w1v[c1]);
+#pragma unroll
+        for (int st = LK - 1; st >= 0; --st) {
+            const int hh = 1 << st;
+            const bool upper = (k & hh) != 0;
+            const C<T> t = tv[(int64_t)(k & (hh - 1)) * (Mv / (2 * hh))];
+            const C<T> om = mk<T>(t.x, -t.y);
+#pragma unroll
+            for (int c1 = 0; c1 < R; ++c1) {
+                const C<T> b = shfl_xor_c<T>(h[c1], hh);
+                h[c1] = upper ? cmul<T>(csub<T>(b, h[c1]), om) : cadd<T>(h[c1], b);
+            }
+        }
+        if (live) {
+            const int cu = row;
+            C<T> fu = mk<T>(1, 0);
+            if (qru != 0) {  // exp(+2 pi i qb_u c_u / G)
+                const C<T> t = tu[((qru * cu) % G) * Pu];
+                fu = mk<T>(t.x, -t.y);
+            }
+            C<T>* dst = out + ((o * X + x) * Mu + n0u + (int64_t)Pu * cu) * Mv + n0v;
+            T* drho = rho ? rho + ((o * X + x) * Mu + n0u + (int64_t)Pu * cu) * Mv + n0v : nullptr;
+#pragma unroll
+            for (int c1 = 0; c1 < R; ++c1) {
+                const int cv = c1 + R * kr;
+                C<T> v = cmul<T>(h[c1], fu);
+                if (qrv != 0) v = cmulc<T>(v, tv[((qrv * cv) % G) * Pv]);  // exp(+2 pi i qb_v c_v / G)
+                const int64_t oi = (int64_t)Pv * cv;
+                if (accumulate) v = cadd<T>(v, dst[oi]);
+                dst[oi] = v;
+                if (drho) drho[oi] = v.x * v.x + v.y * v.y;
+            }
+        }
+        __syncthreads();  // the next tile overwrites the LDS rows
+    }
+}
+
 // Structured accumulate for g = R K (K lanes per group, R = 8 or 4 residues per lane): lane k of a
 // group keeps the residues j = k + K m (m < R). With c = c1 + R c2 the g-point inverse transform
 // splits as
@@ -1649,8 +1806,33 @@ size_t aa_lds_bytes(bool dbl, int gu, int gv) {
     return (2 * tsg * gu * gv + gu + gv) * (dbl ? 16 : 8);
 }
 
+bool aar_applicable(int gu, int gv, const AAGeom& g) {
+    return gu == gv && (gu == 16 || gu == 32) && g.Y == 1 && g.Z == 1;
+}
+
+template <typename T, int G>
+static void launch_aar(const void* in, void* out, const AxisDev& au, const AxisDev& av, const AAGeom& g,
+                       int accumulate, void* rho, hipStream_t st) {
+    constexpr int NG = kThreads / (G * G / 4);
+    const int64_t ngroups = g.O * g.X * au.P * av.P;
+    const int64_t ntl = (ngroups + NG - 1) / NG;
+    const int64_t blocks = std::min<int64_t>(((ntl + 7) / 8) * 8, int64_t(1) << 24);
+    hipLaunchKernelGGL((k_AAR<T, G>), dim3((unsigned)blocks), dim3(kThreads), 0, st, (const C<T>*)in, (C<T>*)out, au,
+                       av, g, accumulate, (T*)rho);
+}
+
 hipError_t launch_pass_aa(bool dbl, const void* in, void* out, const AxisDev& au, const AxisDev& av, const AAGeom& g,
                           int accumulate, void* rho, hipStream_t st) {
+    if (aar_applicable(au.g, av.g, g)) {
+        if (dbl) {
+            if (au.g == 32) launch_aar<double, 32>(in, out, au, av, g, accumulate, rho, st);
+            else launch_aar<double, 16>(in, out, au, av, g, accumulate, rho, st);
+        } else {
+            if (au.g == 32) launch_aar<float, 32>(in, out, au, av, g, accumulate, rho, st);
+            else launch_aar<float, 16>(in, out, au, av, g, accumulate, rho, st);
+        }
+        return hipGetLastError();
+    }
     if (!aa_applicable(dbl, au.g, av.g) || g.tsg != aa_tile_groups(au.g, av.g)) return hipErrorInvalidValue;
     const int64_t ngroups = g.O * g.X * au.P * g.Y * av.P * g.Z;
     const int64_t tiles = (ngroups + g.tsg - 1) / g.tsg;

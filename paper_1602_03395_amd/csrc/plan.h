@@ -63,8 +63,9 @@ struct fx_plan {
     void* bf_state = nullptr;      // brute-force comparator: tables and buffers (built on first use)
     bool use_cfp = true;           // register E kernel where the pruned length allows it
     bool use_asr = true;           // register structured accumulate (k_ASR) for g <= asr_max_g
-    bool use_aa = false;           // fuse the last two accumulate passes (FX_AA=1; slower on the
-                                   // measured workloads, kept as an option)
+    int use_aa = 1;                // fuse the last two accumulate passes: 0 never (FX_AA=0), 1 in
+                                   // registers where g_u = g_v is 16 or 32 and they are the last two
+                                   // axes, 2 also through the LDS form elsewhere (FX_AA=1)
     int use_eas = 1;               // EA through the structured register kernel: 0 never (FX_NO_EAS),
                                    // 1 where it applies with P >= 8 and g <= 16 (smaller transforms
                                    // are dominated by the per-wave overheads; its table-row traffic

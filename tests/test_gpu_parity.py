@@ -355,6 +355,81 @@ def test_batch_rejects_bad_arguments(fx):
         b.run([torch.zeros(9, dtype=torch.complex128, device="cuda")])
 
 
+REG_AA_CASES = [
+    # shape, lam, dtype: the last two axes with g_u = g_v = 16 or 32 take the register form of
+    # the fused accumulate (k_AAR) by default
+    ((64, 64), (32, 32), torch.complex128),     # g = 32, P = 2
+    ((64, 64), (32, 32), torch.complex64),
+    ((128, 128), (16, 16), torch.complex128),   # g = 16, P = 8, four groups per workgroup
+    ((128, 128), (16, 16), torch.complex64),
+    ((64, 128), (16, 48), torch.complex128),    # P_u = 4, P_v = 8, three terms per residue on v
+    ((6, 64, 64), (3, 32, 32), torch.complex128),  # an axis before the fused pair
+    ((512, 512), (32, 32), torch.complex64),    # the 512^2, lambda 32 workload
+]
+
+
+@pytest.mark.parametrize("case", range(len(REG_AA_CASES)))
+def test_register_two_axis_accumulate_matches_oracle(fx, case, monkeypatch):
+    monkeypatch.setenv("FX_NO_EAS", "1")
+    shape, lam, dtype = REG_AA_CASES[case]
+    dx = (1.0,) * len(shape)
+    say("register fused accumulate", shape, lam, dtype)
+    psi_np = workloads.random_field(shape, 950 + case)
+    if dtype == torch.complex64:
+        psi_np = psi_np.astype(np.complex64).astype(np.complex128)
+    a, abar = oracle.default_offsets(shape, dx, lam)
+    abar = abar + 0.3
+    ref = oracle.expand(psi_np, dx, 1.0, 17.0, lam, a, abar)
+    plan = fx.Plan(shape, dx, 1.0, 17.0, lam, list(a), list(abar), dtype)
+    import json
+    ops = json.loads(plan.describe())["passes"]
+    assert ops[-1]["kind"] == "AA" and ops[-1]["g"] == ops[-1]["g2"] == max(np.gcd(lam[-1], shape[-1]), 1)
+    out, rho = plan.expand(torch.from_numpy(psi_np).to(dtype).cuda())
+    torch.cuda.synchronize()
+    if dtype == torch.complex128:
+        assert rel(out.cpu().numpy(), ref) <= TOL64
+        assert rel(rho.cpu().numpy(), oracle.density(ref)) <= TOL64
+    else:
+        assert rel(rho.cpu().numpy(), oracle.density(ref)) <= TOL32_RHO
+
+
+def test_register_two_axis_accumulate_blocked(fx, monkeypatch):
+    # a tiny workspace splits the outer magnification index into blocks: the fused pass then runs
+    # per block with fewer than g terms on v, a first index that is not a multiple of g, accumulating
+    monkeypatch.setenv("FX_WORKSPACE_MB", "1")
+    monkeypatch.setenv("FX_NO_EAS", "1")
+    shape, lam, dx = (256, 512), (32, 32), (1.0, 1.0)
+    say("register fused accumulate blocked", shape, lam)
+    psi_np = workloads.random_field(shape, 961)
+    ref = oracle.expand(psi_np, dx, 1.0, 13.0, lam)
+    plan = fx.Plan(shape, dx, 1.0, 13.0, lam)
+    import json
+    d = json.loads(plan.describe())
+    assert d["outer_block"] < 32
+    assert d["passes"][-1]["kind"] == "AA"
+    out, rho = plan.expand(torch.from_numpy(psi_np).cuda())
+    torch.cuda.synchronize()
+    assert rel(out.cpu().numpy(), ref) <= TOL64
+    assert rel(rho.cpu().numpy(), oracle.density(ref)) <= TOL64
+
+
+def test_register_two_axis_accumulate_term_ranges(fx, monkeypatch):
+    # ranges of the flat term index decompose into blocks whose first indices on both axes are not
+    # multiples of g = 32 and that hold 1..32 terms per axis
+    monkeypatch.setenv("FX_NO_EAS", "1")
+    shape, lam, dx, t = (64, 64), (32, 32), (1.0, 1.0), 9.0
+    say("register fused accumulate ranges", shape, lam)
+    psi_np = workloads.random_field(shape, 962)
+    psi = torch.from_numpy(psi_np).cuda()
+    plan = fx.Plan(shape, dx, 1.0, t, lam)
+    acc = torch.zeros_like(psi)
+    cuts = [0, 5, 37, 100, 640, 1000, 1024]
+    for b, e in zip(cuts[:-1], cuts[1:]):
+        plan.expand_range(psi, acc, b, e, accumulate=True)
+    torch.cuda.synchronize()
+    assert rel(acc.cpu().numpy(), oracle.expand(psi_np, dx, 1.0, t, lam)) <= TOL64
+
+
 @pytest.mark.parametrize("case", [5, 7, 9, 15, 19, 22])
 def test_fused_two_axis_accumulate_fp64(fx, case, monkeypatch):
     # the optional fused form of the last two accumulate passes (FX_AA=1), read at plan creation;
