@@ -45,8 +45,8 @@ def pass_cost(p: dict, csize: int, outer_chunks: int = 1):
       EA adds 8M (the twiddle multiply-accumulate of every output point), or with the structured
       accumulate (EA with "eas") 8P (one twiddle product per pruned output) per line and term plus
       a g-point inverse transform (5 g log2 g) per output group (P groups per line).
-    A: 8 flops per output and term; AA (two fused accumulates): 16 per input sample plus a
-    g_u x g_v inverse transform per output group.
+    A: 8 flops per output and term; AA (two fused accumulates) and its adjoint AAH: 16 per
+    term sample plus a g_u x g_v transform per output group.
     """
     kind, M, P, lam = p["kind"], p["M"], p["P"], p["lam"]
     qn = p.get("qn", lam)
@@ -66,7 +66,7 @@ def pass_cost(p: dict, csize: int, outer_chunks: int = 1):
         else:
             flops = lines * qn * (e_line + 8 * M) + lines * M * 2
         byts = 2 * lines * M * csize
-    elif kind == "AA":
+    elif kind in ("AA", "AAH"):
         nin = p["O"] * p["qn2"] * qn * p["X"] * P * p["Y"] * p["P2"] * p["Z"]
         nout = p["O"] * p["X"] * M * p["Y"] * p["M2"] * p["Z"]
         flops = nin * 16 + nout * 5 * lg(p["g"] * p["g2"])

@@ -300,6 +300,33 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
         for (int i = k - 1; i >= 1; --i) do_AH(p->act[i]);
         do_EAH(p->act[0]);
         for (int i = 1; i < k; ++i) do_EH(p->act[i]);
+        // the adjoint of the fused accumulate: the first two AH passes (axes v > u), register form
+        if (p->use_aa && ops.size() >= 2 && ops[0].kind == Kind::AH && ops[1].kind == Kind::AH &&
+            ops[1].axis < ops[0].axis) {
+            const Op& ov = ops[0];
+            const Op& ou = ops[1];
+            const int u = ou.axis, v = ov.axis;
+            AAGeom a;
+            a.O = ov.g.Qin;
+            a.qn_u = ou.g.qn;
+            a.qb_u = ou.g.qb;
+            a.qn_v = ov.g.qn;
+            a.qb_v = ov.g.qb;
+            a.X = ou.g.A;
+            a.Z = ov.g.S;
+            a.Y = ou.g.S / ((int64_t)p->ax[v].P * a.Z);
+            a.tsg = 1;
+            if (aar_applicable(p->ax[u].g, p->ax[v].g, a)) {
+                Op f = ou;
+                f.kind = Kind::AAH;
+                f.axis = u;
+                f.axis2 = v;
+                f.in_elems = ov.in_elems;
+                f.aa = a;
+                ops.erase(ops.begin());
+                ops[0] = f;
+            }
+        }
     }
     return ops;
 }
@@ -413,6 +440,9 @@ fx_status run_ops(fx_plan* p, const std::vector<Op>& ops, const void* src, void*
         hipError_t e = (o.kind == Kind::AA)
                            ? launch_pass_aa(p->dbl, cur, out, p->ax[o.axis], p->ax[o.axis2], o.aa,
                                             last ? accumulate : 0, last ? rho : nullptr, st)
+                       : (o.kind == Kind::AAH)
+                           ? launch_pass_aah(p->dbl, cur, out, p->ax[o.axis], p->ax[o.axis2], o.aa,
+                                             last ? accumulate : 0, st)
                            : launch_pass(o.kind, p->dbl, cur, out, p->ax[o.axis], o.g, last ? accumulate : 0,
                                          last ? rho : nullptr, st);
         if (p->timing) {
@@ -875,7 +905,7 @@ fx_status fx_plan_describe(const fx_plan* p, char* buf, size_t len) {
         s += j ? "," : "";
         s += p->spectrum[3 - p->ndim + j] ? "\"table\"" : "\"free\"";
     }
-    static const char* names[] = {"E", "A", "EA", "EH", "AH", "EAH", "AA"};
+    static const char* names[] = {"E", "A", "EA", "EH", "AH", "EAH", "AA", "AAH"};
     for (int adj = 0; adj < 2; ++adj) {
     std::vector<Op> ops = build_ops(p, qb, qn, p->slices, adj != 0);
     s += adj ? "],\"adjoint_passes\":[" : "],\"passes\":[";
@@ -891,7 +921,7 @@ fx_status fx_plan_describe(const fx_plan* p, char* buf, size_t len) {
                       (o.g.qc > 0 || o.g.reg_a || o.g.eas) ? 1 : 0);
         s += tmp;
         if (o.g.eas) s += ",\"eas\":1";
-        if (o.kind == Kind::AA) {
+        if (o.kind == Kind::AA || o.kind == Kind::AAH) {
             const AxisDev& b = p->ax[o.axis2];
             std::snprintf(tmp, sizeof(tmp),
                           ",\"axis2\":%d,\"M2\":%d,\"P2\":%d,\"lam2\":%d,\"qn2\":%d,\"O\":%lld,\"X\":%lld,"

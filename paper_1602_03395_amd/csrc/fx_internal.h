@@ -67,7 +67,7 @@ struct PassGeom {
     bool eas = false;    // EA pass: waves share the terms of 64 / g lines, structured accumulate
 };
 
-enum class Kind { E, A, EA, EH, AH, EAH, AA };
+enum class Kind { E, A, EA, EH, AH, EAH, AA, AAH };
 
 // Groups per tile of the structured accumulate (A via a g-point transform over q mod g).
 int as_tile_groups(int g);
@@ -139,6 +139,9 @@ struct AAGeom {
 bool aa_applicable(bool dbl, int gu, int gv);
 // Register form of the fused pass (k_AAR): g_u = g_v = 16 or 32, axes u, v the last two (Y = Z = 1).
 bool aar_applicable(int gu, int gv, const AAGeom& g);
+// Its adjoint (k_AAHR): the first two AH passes of the adjoint schedule fused, same conditions.
+hipError_t launch_pass_aah(bool dbl, const void* in, void* out, const AxisDev& au, const AxisDev& av,
+                           const AAGeom& g, int accumulate, hipStream_t st);
 int aa_tile_groups(int gu, int gv);
 size_t aa_lds_bytes(bool dbl, int gu, int gv);
 hipError_t launch_pass_aa(bool dbl, const void* in, void* out, const AxisDev& au, const AxisDev& av, const AAGeom& g,

@@ -1193,6 +1193,136 @@ __global__ __launch_bounds__(kThreads) void k_AAR(const C<T>* __restrict__ in, C
     }
 }
 
+// Adjoint of k_AAR (the first two AH passes of the adjoint schedule, axes v then u, fused). For
+// the group (n0_u, n0_v) the inputs y[c_u][c_v] = in[.., n0_u + P_u c_u, n0_v + P_v c_v] give every
+// term pair's output sample through one G x G forward transform,
+//   out[q_v][q_u][.., r_u, r_v] = conj(Tf_u[q_u][n0_u] Tf_v[q_v][n0_v]) Yh[(q_u - qb_u) mod G][(q_v - qb_v) mod G],
+// done as the one-axis register adjoint (k_AHK) twice: thread (c_u, k) transforms its row over c_v
+// (reading c_v = c1 + 4 bitrev(k)), the values pass through LDS to thread (j_v, k), which holds
+// c_u = c1 + 4 bitrev(k) of column j_v, and transforms over c_u, leaving Yh[k + K m][j_v].
+template <typename T, int G>
+__global__ __launch_bounds__(kThreads) void k_AAHR(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev au,
+                                                   AxisDev av, AAGeom g, int accumulate) {
+    constexpr int R = 4;
+    constexpr int K = G / R;
+    constexpr int LK = (K == 8) ? 3 : (K == 4) ? 2 : 1;
+    constexpr int TPG = G * K;
+    constexpr int NG = kThreads / TPG;
+    constexpr int LDR = G + 1;
+    static_assert(TPG * NG == kThreads, "group size must divide the workgroup");
+    __shared__ __align__(16) unsigned char smem_aahr[NG * G * LDR * sizeof(C<T>)];
+    const int Pu = au.P, Pv = av.P, Mu = au.M, Mv = av.M;
+    const int slot = (int)threadIdx.x / TPG;
+    const int tt = (int)threadIdx.x % TPG;
+    const int row = tt / K;  // c_u in the first transform, j_v in the second
+    const int k = tt % K;
+    C<T>* Sg = (C<T>*)smem_aahr + slot * G * LDR;
+    int kr = 0;  // bitrev_LK(k)
+    for (int b = 0; b < LK; ++b) kr |= ((k >> b) & 1) << (LK - 1 - b);
+    const C<T>* tu = (const C<T>*)au.tw;
+    const C<T>* tv = (const C<T>*)av.tw;
+    // cross-lane stage twiddles of each axis (select-free form; the rescale goes into w1)
+    C<T> wsu[LK], wsv[LK];
+    const C<T> finu = lane_twiddles_x<T, LK, false>(wsu, k, tu, Mu);
+    const C<T> finv = lane_twiddles_x<T, LK, false>(wsv, k, tv, Mv);
+    C<T> w1u[R], w1v[R];  // exp(-2 pi i k c1 / G) times the rescale
+#pragma unroll
+    for (int c1 = 0; c1 < R; ++c1) {
+        w1u[c1] = cmul<T>(tu[((k * c1) % G) * Pu], finu);
+        w1v[c1] = cmul<T>(tv[((k * c1) % G) * Pv], finv);
+    }
+    const C<T>* Tfu = (const C<T>*)au.Tf;
+    const C<T>* Tfv = (const C<T>*)av.Tf;
+    const int qnu = g.qn_u, qnv = g.qn_v;
+    const int qru = g.qb_u % G, qrv = g.qb_v % G;
+    const int64_t X = g.X;
+    const int64_t PP = (int64_t)Pu * Pv;
+    const int64_t step_u = X * PP;
+    const int64_t step_v = (int64_t)qnu * step_u;
+    const int64_t ngroups = g.O * X * PP;
+    const int64_t ntl = (ngroups + NG - 1) / NG;
+    const int64_t T8 = (ntl + 7) / 8;
+    const int64_t total = T8 * 8;
+    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
+        const int64_t tile = (bid & 7) * T8 + (bid >> 3);
+        if (tile >= ntl) continue;  // uniform over the workgroup
+        const int64_t gid = tile * NG + slot;
+        const bool live = gid < ngroups;
+        const int64_t gq = live ? gid : 0;
+        const int n0v = (int)(gq % Pv);
+        const int n0u = (int)((gq / Pv) % Pu);
+        const int64_t ox = gq / PP;
+        const int64_t x = ox % X, o = ox / X;
+        const int ru = (int)(((int64_t)n0u * au.lg) % Pu);
+        const int rv = (int)(((int64_t)n0v * av.lg) % Pv);
+        // row c_u of the group, c_v = c1 + R bitrev(k)
+        C<T> h[R];
+        {
+            const C<T>* src = in + ((o * X + x) * Mu + n0u + (int64_t)Pu * row) * Mv + n0v;
+#pragma unroll
+            for (int c1 = 0; c1 < R; ++c1) h[c1] = live ? src[(int64_t)Pv * (c1 + R * kr)] : mk<T>(0, 0);
+        }
+        if (qrv != 0) {  // exp(-2 pi i qb_v c_v / G)
+#pragma unroll
+            for (int c1 = 0; c1 < R; ++c1) h[c1] = cmul<T>(h[c1], tv[((qrv * (c1 + R * kr)) % G) * Pv]);
+        }
+#pragma unroll
+        for (int st = 0; st < LK; ++st) {
+#pragma unroll
+            for (int c1 = 0; c1 < R; ++c1) h[c1] = cfma<T>(h[c1], wsv[st], shfl_xor_c<T>(h[c1], 1 << st));
+        }
+#pragma unroll
+        for (int c1 = 0; c1 < R; ++c1) h[c1] = cmul<T>(h[c1], w1v[c1]);
+        RegDFT<T, R, false>::run(h);  // h[m] = Z[c_u = row][j_v = k + K m]
+#pragma unroll
+        for (int m = 0; m < R; ++m) Sg[(k + K * m) * LDR + row] = h[m];
+        __syncthreads();
+        // column j_v = row: c_u = c1 + R bitrev(k)
+#pragma unroll
+        for (int c1 = 0; c1 < R; ++c1) h[c1] = Sg[row * LDR + c1 + R * kr];
+        if (qru != 0) {  // exp(-2 pi i qb_u c_u / G)
+#pragma unroll
+            for (int c1 = 0; c1 < R; ++c1) h[c1] = cmul<T>(h[c1], tu[((qru * (c1 + R * kr)) % G) * Pu]);
+        }
+#pragma unroll
+        for (int st = 0; st < LK; ++st) {
+#pragma unroll
+            for (int c1 = 0; c1 < R; ++c1) h[c1] = cfma<T>(h[c1], wsu[st], shfl_xor_c<T>(h[c1], 1 << st));
+        }
+#pragma unroll
+        for (int c1 = 0; c1 < R; ++c1) h[c1] = cmul<T>(h[c1], w1u[c1]);
+        RegDFT<T, R, false>::run(h);  // h[m] = Yh[j_u = k + K m][j_v = row]
+        if (live) {
+            C<T>* dst = out + ((o * qnv * qnu) * X + x) * PP + (int64_t)ru * Pv + rv;
+            const C<T>* tfu = Tfu + (int64_t)g.qb_u * Mu + n0u;
+            const C<T>* tfv = Tfv + (int64_t)g.qb_v * Mv + n0v;
+            for (int iv = row; iv < qnv; iv += G) {
+                const C<T> fv = tfv[(int64_t)iv * Mv];
+                C<T>* dv = dst + (int64_t)iv * step_v;
+                for (int i0 = 0; i0 < qnu; i0 += G) {
+                    C<T> t[R];
+#pragma unroll
+                    for (int m = 0; m < R; ++m) {
+                        const int i = i0 + k + K * m;
+                        t[m] = (i < qnu) ? tfu[(int64_t)i * Mu] : mk<T>(1, 0);
+                    }
+#pragma unroll
+                    for (int m = 0; m < R; ++m) {
+                        const int i = i0 + k + K * m;
+                        if (i < qnu) {
+                            C<T>* po = dv + (int64_t)i * step_u;
+                            C<T> v = cmulc<T>(cmulc<T>(h[m], t[m]), fv);
+                            if (accumulate) v = cadd<T>(v, *po);
+                            *po = v;
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();  // the next tile overwrites the LDS rows
+    }
+}
+
 // Structured accumulate for g = R K (K lanes per group, R = 8 or 4 residues per lane): lane k of a
 // group keeps the residues j = k + K m (m < R). With c = c1 + R c2 the g-point inverse transform
 // splits as
@@ -1819,6 +1949,30 @@ static void launch_aar(const void* in, void* out, const AxisDev& au, const AxisD
     const int64_t blocks = std::min<int64_t>(((ntl + 7) / 8) * 8, int64_t(1) << 24);
     hipLaunchKernelGGL((k_AAR<T, G>), dim3((unsigned)blocks), dim3(kThreads), 0, st, (const C<T>*)in, (C<T>*)out, au,
                        av, g, accumulate, (T*)rho);
+}
+
+template <typename T, int G>
+static void launch_aahr(const void* in, void* out, const AxisDev& au, const AxisDev& av, const AAGeom& g,
+                        int accumulate, hipStream_t st) {
+    constexpr int NG = kThreads / (G * G / 4);
+    const int64_t ngroups = g.O * g.X * au.P * av.P;
+    const int64_t ntl = (ngroups + NG - 1) / NG;
+    const int64_t blocks = std::min<int64_t>(((ntl + 7) / 8) * 8, int64_t(1) << 24);
+    hipLaunchKernelGGL((k_AAHR<T, G>), dim3((unsigned)blocks), dim3(kThreads), 0, st, (const C<T>*)in, (C<T>*)out,
+                       au, av, g, accumulate);
+}
+
+hipError_t launch_pass_aah(bool dbl, const void* in, void* out, const AxisDev& au, const AxisDev& av,
+                           const AAGeom& g, int accumulate, hipStream_t st) {
+    if (!aar_applicable(au.g, av.g, g)) return hipErrorInvalidValue;
+    if (dbl) {
+        if (au.g == 32) launch_aahr<double, 32>(in, out, au, av, g, accumulate, st);
+        else launch_aahr<double, 16>(in, out, au, av, g, accumulate, st);
+    } else {
+        if (au.g == 32) launch_aahr<float, 32>(in, out, au, av, g, accumulate, st);
+        else launch_aahr<float, 16>(in, out, au, av, g, accumulate, st);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_pass_aa(bool dbl, const void* in, void* out, const AxisDev& au, const AxisDev& av, const AAGeom& g,

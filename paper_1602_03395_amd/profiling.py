@@ -72,7 +72,7 @@ def kernels_hash() -> str:
 
 # pass kernels: k_E, k_E2 (power-of-two), k_Ect (3*2^k), k_ER (register form), k_EA*, k_A,
 # k_AS / k_ASR / k_ASK (structured accumulates), k_AA (fused two-axis accumulate), adjoints
-PASS_KIND = re.compile(r"\bk_(EAH|EA|EH|AH|AA|E|A)(?:2|ct|S|R|SR|SK)?<")
+PASS_KIND = re.compile(r"\bk_(EAH|EA|EH|AH|AAH|AA|E|A)(?:2|ct|S|R|SR|SK)?<")
 
 
 def _pass_dispatches(path: str, counter: str):

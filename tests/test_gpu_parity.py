@@ -413,6 +413,39 @@ def test_register_two_axis_accumulate_blocked(fx, monkeypatch):
     assert rel(rho.cpu().numpy(), oracle.density(ref)) <= TOL64
 
 
+@pytest.mark.parametrize("case", range(len(REG_AA_CASES)))
+def test_register_two_axis_adjoint_matches_oracle(fx, case):
+    # the adjoint schedule starts with the two AH passes of the same pair, fused (k_AAHR)
+    shape, lam, dtype = REG_AA_CASES[case]
+    dx = (1.0,) * len(shape)
+    say("register fused adjoint accumulate", shape, lam, dtype)
+    y_np = workloads.random_field(shape, 970 + case)
+    if dtype == torch.complex64:
+        y_np = y_np.astype(np.complex64).astype(np.complex128)
+    plan = fx.Plan(shape, dx, 1.0, 17.0, lam, dtype=dtype)
+    import json
+    ops = json.loads(plan.describe())["adjoint_passes"]
+    assert ops[0]["kind"] == "AAH"
+    g = plan.expand_adjoint(torch.from_numpy(y_np).to(dtype).cuda()).cpu().numpy()
+    ref = oracle.expand_adjoint(y_np, dx, 1.0, 17.0, lam)
+    assert rel(g, ref) <= (TOL64 if dtype == torch.complex128 else TOL32_RHO)
+
+
+def test_register_two_axis_adjoint_blocked(fx, monkeypatch):
+    # blocks of the outer magnification index: the fused adjoint pass runs per block with fewer
+    # than g terms on v and a first index that is not a multiple of g
+    monkeypatch.setenv("FX_WORKSPACE_MB", "1")
+    shape, lam, dx = (256, 512), (32, 32), (1.0, 1.0)
+    say("register fused adjoint blocked", shape, lam)
+    y_np = workloads.random_field(shape, 980)
+    plan = fx.Plan(shape, dx, 1.0, 13.0, lam)
+    import json
+    d = json.loads(plan.describe())
+    assert d["outer_block"] < 32 and d["adjoint_passes"][0]["kind"] == "AAH"
+    g = plan.expand_adjoint(torch.from_numpy(y_np).cuda()).cpu().numpy()
+    assert rel(g, oracle.expand_adjoint(y_np, dx, 1.0, 13.0, lam)) <= TOL64
+
+
 def test_register_two_axis_accumulate_term_ranges(fx, monkeypatch):
     # ranges of the flat term index decompose into blocks whose first indices on both axes are not
     # multiples of g = 32 and that hold 1..32 terms per axis
