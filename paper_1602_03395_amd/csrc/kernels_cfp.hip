@@ -291,6 +291,32 @@ __device__ __forceinline__ void reduce_scatter_x(C<T>* v, int n2, int lgG) {
     }
 }
 
+// reduce_scatter_x for G >= P (every lane bit below log2 P is a line lane bit): all steps run,
+// with no runtime step test, so the steps of independent calls can be interleaved.
+template <typename T, int P, int S>
+__device__ __forceinline__ void reduce_step_full(C<T>* v, int n2) {
+    if constexpr ((1 << S) < P) {
+        constexpr int half = (P >> S) >> 1;
+        const bool hi = (n2 >> S) & 1;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            const C<T> keep = hi ? v[i + half] : v[i];
+            const C<T> send = hi ? v[i] : v[i + half];
+            v[i] = cadd<T>(keep, shfl_xor_c<T>(send, 1 << S));
+        }
+        reduce_step_full<T, P, S + 1>(v, n2);
+    }
+}
+template <typename T, int P>
+__device__ __forceinline__ void reduce_scatter_full(C<T>* v, int n2) {
+    if constexpr (P >= 2) {
+        constexpr int half = P / 2;
+#pragma unroll
+        for (int i = 0; i < half; ++i) v[i] = cadd<T>(v[i], shfl_xor_c<T>(v[i + half], 1));
+        reduce_step_full<T, P, 1>(v, n2);
+    }
+}
+
 // Every lane of a line ends with all P sums over the G = 2^lgG lanes (any P).
 template <typename T, int P>
 __device__ __forceinline__ void reduce_all(C<T>* v, int lgG) {
@@ -518,6 +544,47 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
                 copy_rows_to_lds<T, P>(Hs, HT + (int64_t)q * M, 0, min(kErStage, qhi - q) * M);
                 __syncthreads();
             }
+            if constexpr (LANEINV) {
+                // two terms at once (q - qlo even, so both rows are in the staged round): their
+                // lane reductions are independent chains of shuffles the scheduler interleaves
+                if (q + 1 < qhi) {
+                    const C<T>* ta0 = TAs + (q - qlo) * P;
+                    const C<T>* h0 = Hs + (((q - qlo) % kErStage) * G + n2) * (P + 1);
+                    const C<T>* h1 = h0 + G * (P + 1);
+                    C<T> va[P], vb[P];
+#pragma unroll
+                    for (int i = 0; i < P; ++i) {
+                        va[i] = cmul<T>(x[i], ta0[i]);
+                        vb[i] = cmul<T>(x[i], ta0[P + i]);
+                    }
+                    RegDFT<T, P, false>::run(va);
+                    RegDFT<T, P, false>::run(vb);
+#pragma unroll
+                    for (int r = 0; r < P; ++r) {
+                        va[r] = cmul<T>(va[r], h0[r]);
+                        vb[r] = cmul<T>(vb[r], h1[r]);
+                    }
+                    reduce_scatter_full<T, P>(va, n2);
+                    reduce_scatter_full<T, P>(vb, n2);
+                    C<T> sa = va[0], sb = vb[0];
+                    for (int s = LP; s < lgG; ++s) {
+                        sa = cadd<T>(sa, shfl_xor_c<T>(sa, 1 << s));
+                        sb = cadd<T>(sb, shfl_xor_c<T>(sb, 1 << s));
+                    }
+                    sa = lane_idft_x<T, LP>(sa, wst, fin);
+                    sb = lane_idft_x<T, LP>(sb, wst, fin);
+                    if (live && n2 < P) {
+                        const int64_t qo = qi * g.qn + (q - g.qb);
+                        const int64_t off = (g.S == 1) ? ((qo * g.A + tl.a0 + l) * P + n2)
+                                                       : (((qo * g.A + tl.a0) * P + n2) * g.S + tl.s0 + l);
+                        const int64_t dq = g.A * P * g.S;  // the next term's slice
+                        out[off] = sa;
+                        out[off + dq] = sb;
+                    }
+                    ++q;
+                    continue;
+                }
+            }
             const C<T>* ta = TAs + (q - qlo) * P;
             const C<T>* h = Hs + (((q - qlo) % kErStage) * G + n2) * (P + 1);
             C<T> v[P];
@@ -528,7 +595,7 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
             for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r]);
             if constexpr (LANEINV) {
                 // sum over the lanes first, then one inverse transform across the P lanes
-                reduce_scatter_x<T, P>(v, n2, lgG);
+                reduce_scatter_full<T, P>(v, n2);
                 C<T> s0 = v[0];
                 for (int s = LP; s < lgG; ++s) s0 = cadd<T>(s0, shfl_xor_c<T>(s0, 1 << s));
                 s0 = lane_idft_x<T, LP>(s0, wst, fin);
