@@ -283,7 +283,7 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
             a.Y = u < v ? ou.g.S / ((int64_t)av.P * a.Z) : 0;  // axes between u and v
             a.tsg = aa_tile_groups(au.g, av.g);
             // the register form wherever it applies; the LDS form only when asked for (FX_AA=1)
-            const bool reg = u < v && aar_applicable(au.g, av.g, a);
+            const bool reg = u < v && aar_applicable(au.g, av.g, au.P, av.P, a);
             const bool lds = u < v && p->use_aa == 2 && aa_applicable(p->dbl, au.g, av.g) &&
                              (int64_t)aa_lds_bytes(p->dbl, au.g, av.g) <= lds_limit_bytes();
             if (reg || lds) {
@@ -316,7 +316,7 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
             a.Z = ov.g.S;
             a.Y = ou.g.S / ((int64_t)p->ax[v].P * a.Z);
             a.tsg = 1;
-            if (aar_applicable(p->ax[u].g, p->ax[v].g, a)) {
+            if (aar_applicable(p->ax[u].g, p->ax[v].g, p->ax[u].P, p->ax[v].P, a)) {
                 Op f = ou;
                 f.kind = Kind::AAH;
                 f.axis = u;

@@ -138,7 +138,7 @@ struct AAGeom {
 };
 bool aa_applicable(bool dbl, int gu, int gv);
 // Register form of the fused pass (k_AAR): g_u = g_v = 16 or 32, axes u, v the last two (Y = Z = 1).
-bool aar_applicable(int gu, int gv, const AAGeom& g);
+bool aar_applicable(int gu, int gv, int Pu, int Pv, const AAGeom& g);
 // Its adjoint (k_AAHR): the first two AH passes of the adjoint schedule fused, same conditions.
 hipError_t launch_pass_aah(bool dbl, const void* in, void* out, const AxisDev& au, const AxisDev& av,
                            const AAGeom& g, int accumulate, hipStream_t st);

@@ -1144,36 +1144,49 @@ __global__ __launch_bounds__(kThreads) void k_AAR(const C<T>* __restrict__ in, C
     const C<T>* Tfv = (const C<T>*)av.Tf;
     const int qnu = g.qn_u, qnv = g.qn_v;
     const int qru = g.qb_u % G, qrv = g.qb_v % G;
+    // cross-lane stage twiddles exp(2 pi i (k mod h) / (2 h)), h = 2^st (M / 2h = P G / 2h)
+    C<T> omu[LK], omv[LK];
+#pragma unroll
+    for (int st = 0; st < LK; ++st) {
+        const int hh = 1 << st;
+        const C<T> a = tu[(k & (hh - 1)) * (Pu * (G / (2 * hh)))];
+        const C<T> b = tv[(k & (hh - 1)) * (Pv * (G / (2 * hh)))];
+        omu[st] = mk<T>(a.x, -a.y);
+        omv[st] = mk<T>(b.x, -b.y);
+    }
     const int64_t X = g.X;
     const int64_t PP = (int64_t)Pu * Pv;
     const int64_t step_u = X * PP;              // input stride of one term along u
     const int64_t step_v = (int64_t)qnu * step_u;  // input stride of one term along v
-    const int64_t ngroups = g.O * X * PP;
-    const int64_t ntl = (ngroups + NG - 1) / NG;
-    const int64_t T8 = (ntl + 7) / 8;
-    const int64_t total = T8 * 8;
-    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
-        const int64_t tile = (bid & 7) * T8 + (bid >> 3);
+    // group indices are below 2^31 (aar_applicable): 32-bit decode
+    const unsigned ngroups = (unsigned)(g.O * X * PP);
+    const unsigned ntl = (ngroups + NG - 1) / NG;
+    const unsigned T8 = (ntl + 7) / 8;
+    const unsigned total = T8 * 8;
+    for (unsigned bid = blockIdx.x; bid < total; bid += gridDim.x) {
+        const unsigned tile = (bid & 7) * T8 + (bid >> 3);
         if (tile >= ntl) continue;  // uniform over the workgroup
-        const int64_t gid = tile * NG + slot;
+        const unsigned gid = tile * NG + slot;
         const bool live = gid < ngroups;
-        const int64_t gq = live ? gid : 0;
-        const int n0v = (int)(gq % Pv);
-        const int n0u = (int)((gq / Pv) % Pu);
-        const int64_t ox = gq / PP;
-        const int64_t x = ox % X, o = ox / X;
-        const int ru = (int)(((int64_t)n0u * au.lg) % Pu);
-        const int rv = (int)(((int64_t)n0v * av.lg) % Pv);
-        const C<T>* src = in + ((o * qnv * qnu) * X + x) * PP + (int64_t)ru * Pv + rv;
-        const C<T>* tfu = Tfu + (int64_t)g.qb_u * Mu + n0u;
-        const C<T>* tfv = Tfv + (int64_t)g.qb_v * Mv + n0v;
+        const unsigned gq = live ? gid : 0;
+        const unsigned t1 = gq / (unsigned)Pv;
+        const int n0v = (int)(gq - t1 * (unsigned)Pv);
+        const unsigned ox = t1 / (unsigned)Pu;
+        const int n0u = (int)(t1 - ox * (unsigned)Pu);
+        const unsigned o32 = ox / (unsigned)X;
+        const int64_t x = (int64_t)(ox - o32 * (unsigned)X), o = o32;
+        const int ru = (n0u * au.lg) % Pu;  // n0 lg < P^2 <= 2^16
+        const int rv = (n0v * av.lg) % Pv;
+        const C<T>* src = in + ((o * qnv * qnu) * X + x) * PP + (int64_t)(ru * Pv + rv);
+        const C<T>* tfu = Tfu + (g.qb_u * Mu + n0u);  // lambda M <= 2^26
+        const C<T>* tfv = Tfv + (g.qb_v * Mv + n0v);
         // H[k + K m][row]: the terms i_u = j_u (mod G), i_v = row (mod G)
         C<T> h[R];
 #pragma unroll
         for (int m = 0; m < R; ++m) h[m] = mk<T>(0, 0);
         if (live) {
             for (int iv = row; iv < qnv; iv += G) {
-                const C<T> fv = tfv[(int64_t)iv * Mv];
+                const C<T> fv = tfv[iv * Mv];
                 const C<T>* sv = src + (int64_t)iv * step_v;
                 C<T> su[R];
 #pragma unroll
@@ -1184,7 +1197,7 @@ __global__ __launch_bounds__(kThreads) void k_AAR(const C<T>* __restrict__ in, C
 #pragma unroll
                     for (int m = 0; m < R; ++m) {
                         const int i = i0 + k + K * m;
-                        a[m] = tfu[(int64_t)i * Mu];
+                        a[m] = tfu[i * Mu];
                         b[m] = sv[(int64_t)i * step_u];
                     }
 #pragma unroll
@@ -1193,7 +1206,7 @@ __global__ __launch_bounds__(kThreads) void k_AAR(const C<T>* __restrict__ in, C
 #pragma unroll
                 for (int m = 0; m < R; ++m) {
                     const int i = i0 + k + K * m;
-                    if (i < qnu) su[m] = cfma<T>(su[m], tfu[(int64_t)i * Mu], sv[(int64_t)i * step_u]);
+                    if (i < qnu) su[m] = cfma<T>(su[m], tfu[i * Mu], sv[(int64_t)i * step_u]);
                 }
 #pragma unroll
                 for (int m = 0; m < R; ++m) h[m] = cfma<T>(h[m], fv, su[m]);
@@ -1207,12 +1220,10 @@ __global__ __launch_bounds__(kThreads) void k_AAR(const C<T>* __restrict__ in, C
         for (int st = LK - 1; st >= 0; --st) {
             const int hh = 1 << st;
             const bool upper = (k & hh) != 0;
-            const C<T> t = tu[(int64_t)(k & (hh - 1)) * (Mu / (2 * hh))];
-            const C<T> om = mk<T>(t.x, -t.y);
 #pragma unroll
             for (int c1 = 0; c1 < R; ++c1) {
                 const C<T> b = shfl_xor_c<T>(h[c1], hh);
-                h[c1] = upper ? cmul<T>(csub<T>(b, h[c1]), om) : cadd<T>(h[c1], b);
+                h[c1] = upper ? cmul<T>(csub<T>(b, h[c1]), omu[st]) : cadd<T>(h[c1], b);
             }
         }
 #pragma unroll
@@ -1228,12 +1239,10 @@ __global__ __launch_bounds__(kThreads) void k_AAR(const C<T>* __restrict__ in, C
         for (int st = LK - 1; st >= 0; --st) {
             const int hh = 1 << st;
             const bool upper = (k & hh) != 0;
-            const C<T> t = tv[(int64_t)(k & (hh - 1)) * (Mv / (2 * hh))];
-            const C<T> om = mk<T>(t.x, -t.y);
 #pragma unroll
             for (int c1 = 0; c1 < R; ++c1) {
                 const C<T> b = shfl_xor_c<T>(h[c1], hh);
-                h[c1] = upper ? cmul<T>(csub<T>(b, h[c1]), om) : cadd<T>(h[c1], b);
+                h[c1] = upper ? cmul<T>(csub<T>(b, h[c1]), omv[st]) : cadd<T>(h[c1], b);
             }
         }
         if (live) {
@@ -1306,22 +1315,25 @@ __global__ __launch_bounds__(kThreads) void k_AAHR(const C<T>* __restrict__ in, 
     const int64_t PP = (int64_t)Pu * Pv;
     const int64_t step_u = X * PP;
     const int64_t step_v = (int64_t)qnu * step_u;
-    const int64_t ngroups = g.O * X * PP;
-    const int64_t ntl = (ngroups + NG - 1) / NG;
-    const int64_t T8 = (ntl + 7) / 8;
-    const int64_t total = T8 * 8;
-    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
-        const int64_t tile = (bid & 7) * T8 + (bid >> 3);
+    // group indices are below 2^31 (aar_applicable): 32-bit decode
+    const unsigned ngroups = (unsigned)(g.O * X * PP);
+    const unsigned ntl = (ngroups + NG - 1) / NG;
+    const unsigned T8 = (ntl + 7) / 8;
+    const unsigned total = T8 * 8;
+    for (unsigned bid = blockIdx.x; bid < total; bid += gridDim.x) {
+        const unsigned tile = (bid & 7) * T8 + (bid >> 3);
         if (tile >= ntl) continue;  // uniform over the workgroup
-        const int64_t gid = tile * NG + slot;
+        const unsigned gid = tile * NG + slot;
         const bool live = gid < ngroups;
-        const int64_t gq = live ? gid : 0;
-        const int n0v = (int)(gq % Pv);
-        const int n0u = (int)((gq / Pv) % Pu);
-        const int64_t ox = gq / PP;
-        const int64_t x = ox % X, o = ox / X;
-        const int ru = (int)(((int64_t)n0u * au.lg) % Pu);
-        const int rv = (int)(((int64_t)n0v * av.lg) % Pv);
+        const unsigned gq = live ? gid : 0;
+        const unsigned t1 = gq / (unsigned)Pv;
+        const int n0v = (int)(gq - t1 * (unsigned)Pv);
+        const unsigned ox = t1 / (unsigned)Pu;
+        const int n0u = (int)(t1 - ox * (unsigned)Pu);
+        const unsigned o32 = ox / (unsigned)X;
+        const int64_t x = (int64_t)(ox - o32 * (unsigned)X), o = o32;
+        const int ru = (n0u * au.lg) % Pu;  // n0 lg < P^2 <= 2^16
+        const int rv = (n0v * av.lg) % Pv;
         // row c_u of the group, c_v = c1 + R bitrev(k)
         C<T> h[R];
         {
@@ -1360,18 +1372,18 @@ __global__ __launch_bounds__(kThreads) void k_AAHR(const C<T>* __restrict__ in, 
         for (int c1 = 0; c1 < R; ++c1) h[c1] = cmul<T>(h[c1], w1u[c1]);
         RegDFT<T, R, false>::run(h);  // h[m] = Yh[j_u = k + K m][j_v = row]
         if (live) {
-            C<T>* dst = out + ((o * qnv * qnu) * X + x) * PP + (int64_t)ru * Pv + rv;
-            const C<T>* tfu = Tfu + (int64_t)g.qb_u * Mu + n0u;
-            const C<T>* tfv = Tfv + (int64_t)g.qb_v * Mv + n0v;
+            C<T>* dst = out + ((o * qnv * qnu) * X + x) * PP + (int64_t)(ru * Pv + rv);
+            const C<T>* tfu = Tfu + (g.qb_u * Mu + n0u);  // lambda M <= 2^26
+            const C<T>* tfv = Tfv + (g.qb_v * Mv + n0v);
             for (int iv = row; iv < qnv; iv += G) {
-                const C<T> fv = tfv[(int64_t)iv * Mv];
+                const C<T> fv = tfv[iv * Mv];
                 C<T>* dv = dst + (int64_t)iv * step_v;
                 for (int i0 = 0; i0 < qnu; i0 += G) {
                     C<T> t[R];
 #pragma unroll
                     for (int m = 0; m < R; ++m) {
                         const int i = i0 + k + K * m;
-                        t[m] = (i < qnu) ? tfu[(int64_t)i * Mu] : mk<T>(1, 0);
+                        t[m] = (i < qnu) ? tfu[i * Mu] : mk<T>(1, 0);
                     }
 #pragma unroll
                     for (int m = 0; m < R; ++m) {
@@ -2003,8 +2015,9 @@ size_t aa_lds_bytes(bool dbl, int gu, int gv) {
     return (2 * tsg * gu * gv + gu + gv) * (dbl ? 16 : 8);
 }
 
-bool aar_applicable(int gu, int gv, const AAGeom& g) {
-    return gu == gv && (gu == 16 || gu == 32) && g.Y == 1 && g.Z == 1;
+bool aar_applicable(int gu, int gv, int Pu, int Pv, const AAGeom& g) {
+    return gu == gv && (gu == 16 || gu == 32) && g.Y == 1 && g.Z == 1 &&
+           g.O * g.X * Pu * Pv + kThreads * 8 < (int64_t(1) << 31);
 }
 
 template <typename T, int G>
@@ -2031,7 +2044,7 @@ static void launch_aahr(const void* in, void* out, const AxisDev& au, const Axis
 
 hipError_t launch_pass_aah(bool dbl, const void* in, void* out, const AxisDev& au, const AxisDev& av,
                            const AAGeom& g, int accumulate, hipStream_t st) {
-    if (!aar_applicable(au.g, av.g, g)) return hipErrorInvalidValue;
+    if (!aar_applicable(au.g, av.g, au.P, av.P, g)) return hipErrorInvalidValue;
     if (dbl) {
         if (au.g == 32) launch_aahr<double, 32>(in, out, au, av, g, accumulate, st);
         else launch_aahr<double, 16>(in, out, au, av, g, accumulate, st);
@@ -2044,7 +2057,7 @@ hipError_t launch_pass_aah(bool dbl, const void* in, void* out, const AxisDev& a
 
 hipError_t launch_pass_aa(bool dbl, const void* in, void* out, const AxisDev& au, const AxisDev& av, const AAGeom& g,
                           int accumulate, void* rho, hipStream_t st) {
-    if (aar_applicable(au.g, av.g, g)) {
+    if (aar_applicable(au.g, av.g, au.P, av.P, g)) {
         if (dbl) {
             if (au.g == 32) launch_aar<double, 32>(in, out, au, av, g, accumulate, rho, st);
             else launch_aar<double, 16>(in, out, au, av, g, accumulate, rho, st);
