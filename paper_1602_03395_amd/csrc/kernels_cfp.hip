@@ -1105,22 +1105,26 @@ __global__ __launch_bounds__(kThreads) void k_AA(const C<T>* __restrict__ in, C<
 
 // The last two accumulate passes (axes u < v, the last two axes: Y = Z = 1) in registers for
 // g_u = g_v = G (16 or 32). The G x G inverse transform of a group (the one k_AA does in LDS) runs
-// as two structured accumulates: G K threads per group (K = G / 4), thread (j_v, k) first holds
-// H[k + K m][j_v] (m < 4), transforms over j_u as the one-axis register accumulate does (a 4-point
-// transform in registers, a twiddle, a K-point transform across the K lanes), passes its values
-// through LDS so that thread (c_u, k) holds j_v = k + K m of row c_u, and transforms over j_v the
-// same way. Workgroups take the groups in XCD-contiguous ranges: the groups of one output line
+// as two structured accumulates: G K threads per group (K = G / R), thread (j_v, k) first holds
+// H[k + K m][j_v] (m < R), transforms over j_u as the one-axis register accumulate does (an
+// R-point transform in registers, a twiddle, a K-point transform across the K lanes), passes its
+// values through LDS so that thread (c_u, k) holds j_v = k + K m of row c_u, and transforms over
+// j_v the same way. Workgroups take the groups in XCD-contiguous ranges: the groups of one output line
 // (all n0_v of an n0_u) write the same cache lines.
-template <typename T, int G>
-__global__ __launch_bounds__(kThreads) void k_AAR(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev au,
-                                                  AxisDev av, AAGeom g, int accumulate, T* __restrict__ rho) {
-    constexpr int R = 4;
+constexpr int aar_threads(int G, int R) { return (G * G / R > kThreads) ? G * G / R : kThreads; }
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+
+template <typename T, int G, int R>
+__global__ __launch_bounds__(2 * kThreads) void k_AAR(const C<T>* __restrict__ in, C<T>* __restrict__ out,
+                                                      AxisDev au, AxisDev av, AAGeom g, int accumulate,
+                                                      T* __restrict__ rho) {
     constexpr int K = G / R;
-    constexpr int LK = (K == 8) ? 3 : (K == 4) ? 2 : 1;
-    constexpr int TPG = G * K;          // threads per group
-    constexpr int NG = kThreads / TPG;  // groups per workgroup
-    constexpr int LDR = G + 1;          // LDS row stride
-    static_assert(TPG * NG == kThreads, "group size must divide the workgroup");
+    constexpr int LK = ilog2c(K);
+    constexpr int TPG = G * K;                 // threads per group
+    constexpr int WG = aar_threads(G, R);      // threads per workgroup
+    constexpr int NG = WG / TPG;               // groups per workgroup
+    constexpr int LDR = G + 1;                 // LDS row stride
+    static_assert(TPG * NG == WG && WG <= 2 * kThreads, "group size must divide the workgroup");
     __shared__ __align__(16) unsigned char smem_aar[NG * G * LDR * sizeof(C<T>)];
     const int Pu = au.P, Pv = av.P, Mu = au.M, Mv = av.M;
     const int slot = (int)threadIdx.x / TPG;
@@ -2020,15 +2024,23 @@ bool aar_applicable(int gu, int gv, int Pu, int Pv, const AAGeom& g) {
            g.O * g.X * Pu * Pv + kThreads * 8 < (int64_t(1) << 31);
 }
 
-template <typename T, int G>
-static void launch_aar(const void* in, void* out, const AxisDev& au, const AxisDev& av, const AAGeom& g,
-                       int accumulate, void* rho, hipStream_t st) {
-    constexpr int NG = kThreads / (G * G / 4);
+template <typename T, int G, int R>
+static void launch_aar_r(const void* in, void* out, const AxisDev& au, const AxisDev& av, const AAGeom& g,
+                         int accumulate, void* rho, hipStream_t st) {
+    constexpr int WG = aar_threads(G, R);
+    constexpr int NG = WG / (G * G / R);
     const int64_t ngroups = g.O * g.X * au.P * av.P;
     const int64_t ntl = (ngroups + NG - 1) / NG;
     const int64_t blocks = std::min<int64_t>(((ntl + 7) / 8) * 8, int64_t(1) << 24);
-    hipLaunchKernelGGL((k_AAR<T, G>), dim3((unsigned)blocks), dim3(kThreads), 0, st, (const C<T>*)in, (C<T>*)out, au,
+    hipLaunchKernelGGL((k_AAR<T, G, R>), dim3((unsigned)blocks), dim3(WG), 0, st, (const C<T>*)in, (C<T>*)out, au,
                        av, g, accumulate, (T*)rho);
+}
+template <typename T, int G>
+static void launch_aar(const void* in, void* out, const AxisDev& au, const AxisDev& av, const AAGeom& g,
+                       int accumulate, void* rho, hipStream_t st) {
+    // two residues per lane: twice the waves of four per lane (one group per CU on the 512^2
+    // workload), which hides more of the scattered loads' latency
+    launch_aar_r<T, G, 2>(in, out, au, av, g, accumulate, rho, st);
 }
 
 template <typename T, int G>
