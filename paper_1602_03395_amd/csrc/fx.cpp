@@ -165,6 +165,7 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
                 (p->use_eas == 2 || (p->use_eas == 1 && p->ax[ax].P >= 8 && p->ax[ax].g <= 16)) &&
                 eas_applicable(p->dbl, p->ax[ax].M, p->ax[ax].g, qn[ax]);
         const bool reg = !g.eas && (use_cfp(p, kind, p->ax[ax]) || reg_eh);
+        g.eh2 = kind == Kind::EH && !reg_eh && p->use_eh2 && eh2_applicable(p->ax[ax].M, p->ax[ax].P);
         g.TS = g.eas ? eas_tile_lines(p->ax[ax].g)
                      : reg_eh ? ehr_tile_lines(p->ax[ax].g)
                               : reg ? cfp_tile_lines(p->ax[ax].g) : choose_ts(p, kind, p->ax[ax].M, g.A, g.S);
@@ -246,7 +247,10 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
                qn[ax] <= 64 && ehr_applicable(a.M, a.g);
     };
     auto do_EAH = [&](int ax) {
-        if (reg_adjoint(ax) || split(Kind::EAH, ax)) { do_AH(ax); do_EH(ax); return; }
+        // also split where EH has its compile-time power-of-two kernel (the fused generic pass
+        // runs one transform chain per term and workgroup)
+        const bool eh2 = p->use_eh2 && eh2_applicable(p->ax[ax].M, p->ax[ax].P);
+        if (reg_adjoint(ax) || eh2 || split(Kind::EAH, ax)) { do_AH(ax); do_EH(ax); return; }
         emit(Kind::EAH, ax, geom(Kind::EAH, ax, slices), vol());
     };
     const int k = p->nact;
@@ -645,6 +649,7 @@ fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_pla
     if (const char* e = std::getenv("FX_AA")) p->use_aa = (e[0] == '1') ? 2 : 0;
     if (const char* e = std::getenv("FX_EAS")) p->use_eas = (e[0] == '1') ? 2 : 1;
     if (std::getenv("FX_NO_EAS")) p->use_eas = 0;
+    if (std::getenv("FX_NO_EH2")) p->use_eh2 = false;
     if (const char* e = std::getenv("FX_ASR_MAXG")) p->asr_max_g = std::max(1, std::atoi(e));
     p->cfp_blocks = 2 * num_cus();
     if (const char* e = std::getenv("FX_CFP_BLOCKS")) p->cfp_blocks = std::max(1, std::atoi(e));
@@ -921,6 +926,7 @@ fx_status fx_plan_describe(const fx_plan* p, char* buf, size_t len) {
                       (o.g.qc > 0 || o.g.reg_a || o.g.eas) ? 1 : 0);
         s += tmp;
         if (o.g.eas) s += ",\"eas\":1";
+        if (o.g.eh2) s += ",\"eh2\":1";
         if (o.kind == Kind::AA || o.kind == Kind::AAH) {
             const AxisDev& b = p->ax[o.axis2];
             std::snprintf(tmp, sizeof(tmp),

@@ -65,6 +65,7 @@ struct PassGeom {
     int qc = 0;        // > 0: register E kernel, magnification indices per workgroup
     bool reg_a = false;  // A pass: register structured accumulate
     bool eas = false;    // EA pass: waves share the terms of 64 / g lines, structured accumulate
+    bool eh2 = false;    // EH pass: compile-time power-of-two kernel, one output line per workgroup
 };
 
 enum class Kind { E, A, EA, EH, AH, EAH, AA, AAH };
@@ -95,6 +96,12 @@ int p2_tile_lines(int M);
 size_t p2_lds_bytes(Kind kind, bool dbl, int M);
 hipError_t launch_pass_p2(Kind kind, bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g,
                           int accumulate, void* rho, hipStream_t st);
+// Compile-time EH (adjoint of E) for power-of-two axes of 256..2048 points (kernels_p2.hip): one
+// output line per workgroup, 2048 / M terms transformed together.
+bool eh2_applicable(int M, int P);
+size_t eh2_lds_bytes(bool dbl, int M);
+hipError_t launch_pass_eh2(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g,
+                           int accumulate, hipStream_t st);
 // Compile-time E / EA kernels for axis lengths 3 * 2^k, 12..1536 (kernels_ct.hip), tiles of
 // ct_tile_lines(M) lines.
 bool ct_applicable(Kind kind, int M);

@@ -740,6 +740,7 @@ hipError_t launch_pass(Kind kind, bool dbl, const void* in, void* out, const Axi
     if (((g.Qin * g.ntiles + 7) / 8) * 8 * g.qn >= (int64_t(1) << 31)) return hipErrorInvalidValue;
     if (kind == Kind::EA && g.eas) return launch_pass_eas(dbl, in, out, ax, g, accumulate, rho, st);
     if (g.qc > 0 && kind == Kind::EH) return launch_pass_ehr(dbl, in, out, ax, g, accumulate, st);
+    if (kind == Kind::EH && g.eh2) return launch_pass_eh2(dbl, in, out, ax, g, accumulate, st);
     if (g.qc > 0) return launch_pass_cfp(kind, dbl, in, out, ax, g, accumulate, rho, st);
     // the register accumulates decode their groups (up to 8 lanes each) with 32-bit integers
     if ((kind == Kind::A || kind == Kind::AH) && g.reg_a && g.Qin * g.A * (int64_t)ax.P * g.S * 8 < (int64_t(1) << 31))

@@ -282,6 +282,90 @@ __global__ __launch_bounds__(kThreads) void k_E2(const C<T>* __restrict__ in, C<
 }
 
 // ------------------------------------------------------------------------------------
+// EH (adjoint of E, summed over the terms) for M = 2^LM >= kThreads: in [Qo*qn][A][P][S] ->
+// out [Qo][A][M][S],
+//   out = (1/M) sum_i conj(TA_q) IFFT_M( conj(TB_q) unfold( DFT_P(in_i) ) ),
+// the conjugate transpose of every step of E in reverse order. One output line per workgroup:
+// the rows of the 2048-point tile are 2048 / M terms of that line, transformed together, and
+// each thread sums its M / kThreads output points over the rows and all terms in registers.
+// ------------------------------------------------------------------------------------
+template <typename T, int LM>
+__global__ __launch_bounds__(kThreads) void k_EH2(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
+                                                  PassGeom g, int accumulate, int LP) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int M = 1 << LM;
+    constexpr int TS = kTilePoints2 / M;  // terms per round
+    constexpr int ACC = M / kThreads;     // output points per thread
+    constexpr int PT = padded_tile(sizeof(T) == 8);
+    static_assert(ACC >= 1 && ACC * kThreads == M, "one line spans the workgroup");
+    const int P = ax.P;
+    C<T>* B0 = (C<T>*)smem;
+    C<T>* B1 = B0 + PT;
+    const C<T>* tw = stage_roots_p2<T, LM>(B1 + PT, (const C<T>*)ax.tw);
+    TwReg<T, LM> tr;
+    tr.load(tw);
+    const C<T>* TA = (const C<T>*)ax.TA;
+    const C<T>* TB = (const C<T>*)ax.TB;
+    const T scale = (T)ax.scale;
+    const int64_t S = g.S;
+    const int64_t lines = g.Qin * g.A * S;  // Qin = output slices
+    const int t = (int)threadIdx.x;
+    for (int64_t L = blockIdx.x; L < lines; L += gridDim.x) {
+        const int64_t s = L % S;
+        const int64_t t2 = L / S;
+        const int64_t a = t2 % g.A;
+        const int64_t qo = t2 / g.A;
+        C<T> acc[ACC];
+#pragma unroll
+        for (int j = 0; j < ACC; ++j) acc[j] = mk<T>(0, 0);
+        for (int i0 = 0; i0 < g.qn; i0 += TS) {
+            // row r: the P inputs of term i0 + r (zero past the last term)
+            for (int e = t; e < TS * P; e += kThreads) {
+                const int r = e >> LP, u = e & (P - 1);
+                const int i = i0 + r;
+                C<T> v = mk<T>(0, 0);
+                if (i < g.qn) v = in[(((qo * g.qn + i) * g.A + a) * P + u) * S + s];
+                B0[px<T>(r * M + u)] = v;
+            }
+            __syncthreads();
+            // forward P-point transform of every row (roots tw[k g])
+            C<T>* Z = p2_fft_rt<T>(B0, B1, TS, M, LP, tw, ax.g, false);
+            C<T>* Yb = (Z == B0) ? B1 : B0;
+            // unfold with the conjugate chirp
+#pragma unroll
+            for (int k = 0; k < kTilePoints2 / kThreads; ++k) {
+                const int e = t + k * kThreads;
+                const int r = e >> LM, m = e & (M - 1);
+                const int q = g.qb + min(i0 + r, g.qn - 1);
+                Yb[px<T>(e)] = cmulc<T>(Z[px<T>(r * M + (m & (P - 1)))], TB[q * M + m]);
+            }
+            __syncthreads();
+            const C<T>* Y = P2Run<T, LM, 0, true>::run(Yb, Z, tr, nullptr);
+#pragma unroll
+            for (int r = 0; r < TS; ++r) {
+                if (i0 + r < g.qn) {
+                    const int q = g.qb + i0 + r;
+#pragma unroll
+                    for (int j = 0; j < ACC; ++j) {
+                        const int n = t + j * kThreads;
+                        acc[j] = cfmac<T>(acc[j], Y[px<T>(r * M + n)], TA[q * M + n]);
+                    }
+                }
+            }
+            __syncthreads();  // the next round overwrites both buffers
+        }
+#pragma unroll
+        for (int j = 0; j < ACC; ++j) {
+            const int n = t + j * kThreads;
+            const int64_t off = ((qo * g.A + a) * M + n) * S + s;
+            C<T> v = cscale<T>(acc[j], scale);
+            if (accumulate) v = cadd<T>(v, out[off]);
+            out[off] = v;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
 // EA for M = 2^LM: the 1-D prescription on every line, q loop inside the workgroup.
 // ------------------------------------------------------------------------------------
 template <typename T, int LM>
@@ -432,7 +516,49 @@ hipError_t launch_p2_T(Kind kind, const void* in, void* out, const AxisDev& ax, 
     }
 }
 
+template <typename T, int LM>
+hipError_t launch_eh2_lm(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
+                         hipStream_t st) {
+    const int LP = ilog2(ax.P);
+    const size_t lds = eh2_lds_bytes(sizeof(T) == 8, ax.M);
+    auto k = k_EH2<T, LM>;
+    hipError_t e = prep_lds2(k, lds);
+    if (e != hipSuccess) return e;
+    int64_t blocks = g.Qin * g.A * g.S;
+    if (blocks > (1 << 22)) blocks = 1 << 22;
+    hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), lds, st, (const C<T>*)in,
+                       (C<T>*)out, ax, g, accumulate, LP);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_eh2_T(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
+                        hipStream_t st) {
+    switch (ilog2(ax.M)) {
+        case 8: return launch_eh2_lm<T, 8>(in, out, ax, g, accumulate, st);
+        case 9: return launch_eh2_lm<T, 9>(in, out, ax, g, accumulate, st);
+        case 10: return launch_eh2_lm<T, 10>(in, out, ax, g, accumulate, st);
+        case 11: return launch_eh2_lm<T, 11>(in, out, ax, g, accumulate, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
+
+bool eh2_applicable(int M, int P) {
+    return M >= kThreads && M <= kTilePoints2 && (M & (M - 1)) == 0 && P >= 1 && M % P == 0;
+}
+
+size_t eh2_lds_bytes(bool dbl, int M) {
+    return (2 * (size_t)padded_tile(dbl) + (size_t)M) * (dbl ? 16 : 8);
+}
+
+hipError_t launch_pass_eh2(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g,
+                           int accumulate, hipStream_t st) {
+    if (!eh2_applicable(ax.M, ax.P)) return hipErrorInvalidValue;
+    return dbl ? launch_eh2_T<double>(in, out, ax, g, accumulate, st)
+               : launch_eh2_T<float>(in, out, ax, g, accumulate, st);
+}
 
 bool p2_applicable(Kind kind, int M) {
     if (kind != Kind::E && kind != Kind::EA) return false;

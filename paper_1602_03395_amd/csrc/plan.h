@@ -63,6 +63,7 @@ struct fx_plan {
     void* bf_state = nullptr;      // brute-force comparator: tables and buffers (built on first use)
     bool use_cfp = true;           // register E kernel where the pruned length allows it
     bool use_asr = true;           // register structured accumulate (k_ASR) for g <= asr_max_g
+    bool use_eh2 = true;           // compile-time power-of-two EH kernel (FX_NO_EH2 disables)
     int use_aa = 1;                // fuse the last two accumulate passes: 0 never (FX_AA=0), 1 in
                                    // registers where g_u = g_v is 16 or 32 and they are the last two
                                    // axes, 2 also through the LDS form elsewhere (FX_AA=1)

@@ -201,6 +201,35 @@ def test_adjoint_fp32_form_matches_oracle(fx, shape, lam):
     assert rel(g, oracle.expand_adjoint(y_np, dx, 1.0, 9.0, lam)) <= TOL32_RHO
 
 
+EH2_CASES = [
+    # shape, lam, dtype: adjoint passes along power-of-two axes of 256..2048 points whose pruned
+    # length exceeds the register forms take the compile-time kernel (k_EH2)
+    ((256,), (5,), torch.complex128),            # g = 1, P = 256, 1-D
+    ((2048,), (3,), torch.complex128),           # one term per round
+    ((8, 512), (3, 6), torch.complex128),        # g = 2, P = 256, contiguous lines
+    ((256, 64), (20, 4), torch.complex128),      # strided lines (S = 16) after the split AH
+    ((1024, 16), (4, 2), torch.complex128),      # P = 256 of M = 1024, strided
+    ((256, 256), (20, 20), torch.complex128),    # one field of the gradient workload
+    ((256, 256), (20, 20), torch.complex64),
+]
+
+
+@pytest.mark.parametrize("case", range(len(EH2_CASES)))
+def test_adjoint_power_of_two_kernel_matches_oracle(fx, case):
+    shape, lam, dtype = EH2_CASES[case]
+    dx = (1.0,) * len(shape)
+    say("adjoint eh2", shape, lam, dtype)
+    y_np = workloads.random_field(shape, 990 + case)
+    if dtype == torch.complex64:
+        y_np = y_np.astype(np.complex64).astype(np.complex128)
+    plan = fx.Plan(shape, dx, 1.0, 23.0, lam, dtype=dtype)
+    import json
+    assert any(o.get("eh2") for o in json.loads(plan.describe())["adjoint_passes"])
+    g = plan.expand_adjoint(torch.from_numpy(y_np).to(dtype).cuda()).cpu().numpy()
+    ref = oracle.expand_adjoint(y_np, dx, 1.0, 23.0, lam)
+    assert rel(g, ref) <= (TOL64 if dtype == torch.complex128 else TOL32_RHO)
+
+
 def test_adjoint_blocked_outer_axis_matches_oracle(fx, monkeypatch):
     # a tiny workspace splits the outer magnification index into blocks whose first index is not
     # a multiple of g = 32: every block's adjoint accumulate carries the phase of its offset
