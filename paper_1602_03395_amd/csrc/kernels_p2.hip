@@ -310,7 +310,13 @@ __global__ __launch_bounds__(kThreads) void k_EH2(const C<T>* __restrict__ in, C
     const int64_t S = g.S;
     const int64_t lines = g.Qin * g.A * S;  // Qin = output slices
     const int t = (int)threadIdx.x;
-    for (int64_t L = blockIdx.x; L < lines; L += gridDim.x) {
+    // XCD-contiguous line order: workgroups are dispatched round-robin over the 8 XCDs (id mod 8),
+    // so line (id mod 8) L8 + id / 8 gives each XCD a contiguous range, and the strided lines
+    // (consecutive s) that share cache lines are read through one L2
+    const int64_t L8 = (lines + 7) / 8;
+    for (int64_t bid = blockIdx.x; bid < 8 * L8; bid += gridDim.x) {
+        const int64_t L = (bid & 7) * L8 + (bid >> 3);
+        if (L >= lines) continue;  // uniform over the workgroup
         const int64_t s = L % S;
         const int64_t t2 = L / S;
         const int64_t a = t2 % g.A;
@@ -524,7 +530,7 @@ hipError_t launch_eh2_lm(const void* in, void* out, const AxisDev& ax, const Pas
     auto k = k_EH2<T, LM>;
     hipError_t e = prep_lds2(k, lds);
     if (e != hipSuccess) return e;
-    int64_t blocks = g.Qin * g.A * g.S;
+    int64_t blocks = (g.Qin * g.A * g.S + 7) / 8 * 8;  // the kernel's XCD-aware order
     if (blocks > (1 << 22)) blocks = 1 << 22;
     hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), lds, st, (const C<T>*)in,
                        (C<T>*)out, ax, g, accumulate, LP);
