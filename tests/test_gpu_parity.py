@@ -230,6 +230,46 @@ def test_adjoint_power_of_two_kernel_matches_oracle(fx, case):
     assert rel(g, ref) <= (TOL64 if dtype == torch.complex128 else TOL32_RHO)
 
 
+MAX_AXIS_CASES = [
+    # the longest supported axes: 4096 points in the FP32 form; in plain FP64 the fused pass's
+    # LDS ((4 M + 256) 16 bytes <= 160 KiB) allows M <= 2496 (here 2496 = 2^6 3 13, runtime radices)
+    ((4096,), (3,), torch.complex64),
+    ((48, 4096), (2, 4), torch.complex64),
+    ((2496,), (3,), torch.complex128),
+    ((2048,), (5,), torch.complex128),
+]
+
+
+def test_fp64_axis_beyond_lds_is_rejected(fx):
+    from paper_1602_03395_amd._lib import FxError
+    with pytest.raises(FxError) as e:
+        fx.Plan((4096,), (1.0,), 1.0, 50.0, (3,), dtype=torch.complex128)
+    assert "axis too long" in str(e.value)
+
+
+@pytest.mark.parametrize("case", range(len(MAX_AXIS_CASES)))
+def test_maximum_axis_length_matches_oracle(fx, case):
+    shape, lam, dtype = MAX_AXIS_CASES[case]
+    dx = (1.0,) * len(shape)
+    say("maximum axis", shape, lam, dtype)
+    psi_np = workloads.random_field(shape, 1000 + case)
+    if dtype == torch.complex64:
+        psi_np = psi_np.astype(np.complex64).astype(np.complex128)
+    ref = oracle.expand(psi_np, dx, 1.0, 50.0, lam)
+    plan = fx.Plan(shape, dx, 1.0, 50.0, lam, dtype=dtype)
+    out, rho = plan.expand(torch.from_numpy(psi_np).to(dtype).cuda())
+    torch.cuda.synchronize()
+    if dtype == torch.complex128:
+        assert rel(out.cpu().numpy(), ref) <= TOL64
+        assert rel(rho.cpu().numpy(), oracle.density(ref)) <= TOL64
+        if len(shape) == 1:
+            y_np = workloads.random_field(shape, 1010 + case)
+            g = plan.expand_adjoint(torch.from_numpy(y_np).cuda()).cpu().numpy()
+            assert rel(g, oracle.expand_adjoint(y_np, dx, 1.0, 50.0, lam)) <= TOL64
+    else:
+        assert rel(rho.cpu().numpy(), oracle.density(ref)) <= TOL32_RHO
+
+
 def test_adjoint_blocked_outer_axis_matches_oracle(fx, monkeypatch):
     # a tiny workspace splits the outer magnification index into blocks whose first index is not
     # a multiple of g = 32: every block's adjoint accumulate carries the phase of its offset
