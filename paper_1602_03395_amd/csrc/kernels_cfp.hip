@@ -784,7 +784,12 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
 // one g-point inverse per (line, n0), computed by K = g / 8 lanes as in k_ASK.
 constexpr int kEaWaves = 8;
 
-template <typename T, int P, int K>
+// The table rows HT_q of the pass's terms (qn M values) are staged in LDS once per workgroup when
+// they fit kEasStageBytes (HST); the grid is then persistent, so every workgroup reuses them over
+// many tiles and each term reads its row from LDS instead of global memory.
+constexpr size_t kEasStageBytes = 32768;
+
+template <typename T, int P, int K, bool HST>
 __global__ __launch_bounds__(kEaWaves * kWave) void k_EAS(const C<T>* __restrict__ in, C<T>* __restrict__ out,
                                                          AxisDev ax, PassGeom g, int accumulate, T* __restrict__ rho,
                                                          int lgG, const C<T>* __restrict__ TA,
@@ -807,6 +812,11 @@ __global__ __launch_bounds__(kEaWaves * kWave) void k_EAS(const C<T>* __restrict
     const int n2 = lane % G;
     for (int e = tid; e < g.qn * P; e += kEaWaves * kWave)
         TAs[e] = TA[(int64_t)(g.qb + e / P) * M + ((e % P) << lgG)];
+    C<T>* Hst = TAs + g.qn * P;  // [q - qb][M] table rows (HST)
+    if constexpr (HST) {
+        const C<T>* hsrc = HT + (int64_t)g.qb * M;
+        for (int e = tid; e < g.qn * M; e += kEaWaves * kWave) Hst[e] = hsrc[e];
+    }
     // E part: lane twiddles, the odd lane's spectrum exchange, the lane's accumulate target
     const bool odd_flip = (n2 & 1) && lgG >= 1;
     C<T> wst[LP > 0 ? LP : 1];
@@ -877,13 +887,19 @@ __global__ __launch_bounds__(kEaWaves * kWave) void k_EAS(const C<T>* __restrict
         for (int qq = w; qq < g.qn; qq += kEaWaves) {
             const int q = g.qb + qq;
             const C<T>* ta = TAs + qq * P;
-            const C<T>* h = HT + (int64_t)q * M + n2;
             C<T> v[P];
 #pragma unroll
             for (int i = 0; i < P; ++i) v[i] = cmul<T>(x[i], ta[i]);
             RegDFT<T, P, false>::run(v);
+            if constexpr (HST) {
+                const C<T>* h = Hst + qq * M + n2;
 #pragma unroll
-            for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r << lgG]);
+                for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r << lgG]);
+            } else {
+                const C<T>* h = HT + (int64_t)q * M + n2;
+#pragma unroll
+                for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r << lgG]);
+            }
             reduce_scatter_x<T, P>(v, n2, lgG);
             C<T> s0 = v[0];
             for (int s = LP; s < lgG; ++s) s0 = cadd<T>(s0, shfl_xor_c<T>(s0, 1 << s));
@@ -1696,6 +1712,19 @@ __global__ __launch_bounds__(kEhWaves * kWave) void k_EHR(const C<T>* __restrict
     }
 }
 
+int cu_count() {
+    static int cached = -1;
+    if (cached < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cached = v;
+        else
+            cached = 256;
+    }
+    return cached;
+}
+
 hipError_t prep_lds(const void* k, size_t lds) {
     static std::mutex mu;
     static std::set<const void*> done;
@@ -1932,14 +1961,18 @@ hipError_t launch_eas(const void* in, void* out, const AxisDev& ax, const PassGe
                       hipStream_t st) {
     constexpr int G = 8 * K;
     constexpr int TS = kWave / G;
+    const size_t stage = (size_t)g.qn * ax.M * sizeof(C<T>);
+    const bool hst = stage <= kEasStageBytes;
     int64_t blocks = (g.Qin * g.ntiles + 7) / 8 * 8;  // the kernel's XCD-contiguous order
+    if (hst) blocks = std::min<int64_t>(blocks, (int64_t)(2 * cu_count() + 7) / 8 * 8);  // persistent
     if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = (g.max_blocks + 7) / 8 * 8;
     if (blocks > (1 << 22)) blocks = 1 << 22;
-    const size_t lds = ((size_t)TS * ax.M + (size_t)TS * P * G + (size_t)g.qn * P) * sizeof(C<T>);
-    hipError_t e = prep_lds((const void*)k_EAS<T, P, K>, lds);
+    const size_t lds = ((size_t)TS * ax.M + (size_t)TS * P * G + (size_t)g.qn * P) * sizeof(C<T>) + (hst ? stage : 0);
+    auto k = hst ? k_EAS<T, P, K, true> : k_EAS<T, P, K, false>;
+    hipError_t e = prep_lds((const void*)k, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_EAS<T, P, K>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kEaWaves * kWave), lds,
-                       st, (const C<T>*)in, (C<T>*)out, ax, g, accumulate, (T*)rho, ilog2i(ax.g), (const C<T>*)ax.TA,
+    hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kEaWaves * kWave), lds, st,
+                       (const C<T>*)in, (C<T>*)out, ax, g, accumulate, (T*)rho, ilog2i(ax.g), (const C<T>*)ax.TA,
                        (const C<T>*)ax.HTx);
     return hipGetLastError();
 }
