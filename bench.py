@@ -34,7 +34,7 @@ ADJOINT_SLOT0 = 32  # first pass-timing slot of the adjoint schedule (FX_ADJOINT
 
 
 def pass_cost(p: dict, csize: int, outer_chunks: int = 1):
-    """Algorithmic flops and unique bytes of one launch of a pass (roofline model).
+    """Algorithmic flops and unique bytes of one launch of a pass (the roofline model).
 
     Counting convention: complex multiply 6 flops, complex add 2, complex
     multiply-add 8, a length-N transform 5 N log2 N. Per line and magnification index:
@@ -214,8 +214,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(sharding over q-terms is described in DESIGN.md)"}), flush=True)
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 "
+                                   "(sharding the magnification terms over GPUs is not implemented)"}), flush=True)
         sys.exit(2)
 
     import numpy as np

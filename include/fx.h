@@ -54,7 +54,7 @@ typedef enum fx_status {
     FX_EINVAL = -1,        /* invalid argument (shape, lambda, dx, t, pointers, ...) */
     FX_ENOMEM = -2,        /* device or host allocation failed, or workspace too small */
     FX_EDEVICE = -3,       /* a HIP runtime call or kernel launch failed */
-    FX_EUNSUPPORTED = -4   /* valid problem outside what this build supports (e.g. too long an axis) */
+    FX_EUNSUPPORTED = -4   /* valid problem outside what this library supports (e.g. too long an axis) */
 } fx_status;
 
 typedef enum fx_precision {
@@ -113,7 +113,7 @@ fx_status fx_problem_init(fx_problem* p);
  * precision, uploads them to the current HIP device and chooses the kernel
  * tiling. Allocates no workspace yet. *out is set only on FX_OK.
  * Errors: FX_EINVAL (bad problem or NULL pointers), FX_EUNSUPPORTED (an axis
- * longer than this build's in-LDS transform allows), FX_ENOMEM, FX_EDEVICE.
+ * longer than the library's in-LDS transform allows), FX_ENOMEM, FX_EDEVICE.
  */
 fx_status fx_plan_create(const fx_problem* prob, fx_plan** out);
 

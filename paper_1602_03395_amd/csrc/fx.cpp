@@ -954,7 +954,7 @@ const char* fx_status_string(fx_status s) {
         case FX_EINVAL: return "FX_EINVAL: invalid argument";
         case FX_ENOMEM: return "FX_ENOMEM: out of memory or workspace too small";
         case FX_EDEVICE: return "FX_EDEVICE: HIP runtime or kernel error";
-        case FX_EUNSUPPORTED: return "FX_EUNSUPPORTED: outside what this build supports";
+        case FX_EUNSUPPORTED: return "FX_EUNSUPPORTED: outside what this library supports";
     }
     return "unknown fx_status";
 }
