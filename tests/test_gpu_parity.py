@@ -230,6 +230,21 @@ def test_adjoint_power_of_two_kernel_matches_oracle(fx, case):
     assert rel(g, ref) <= (TOL64 if dtype == torch.complex128 else TOL32_RHO)
 
 
+def test_adjoint_power_of_two_kernel_blocked(fx, monkeypatch):
+    # a tiny workspace splits the outer magnification index into blocks: the compile-time adjoint
+    # pass then starts at a term index qb > 0 and accumulates into the output
+    monkeypatch.setenv("FX_WORKSPACE_MB", "1")
+    shape, lam, dx = (256, 256), (20, 20), (1.0, 1.0)
+    say("adjoint eh2 blocked", shape, lam)
+    y_np = workloads.random_field(shape, 999)
+    plan = fx.Plan(shape, dx, 1.0, 23.0, lam)
+    import json
+    d = json.loads(plan.describe())
+    assert d["outer_block"] < 20 and any(o.get("eh2") for o in d["adjoint_passes"])
+    g = plan.expand_adjoint(torch.from_numpy(y_np).cuda()).cpu().numpy()
+    assert rel(g, oracle.expand_adjoint(y_np, dx, 1.0, 23.0, lam)) <= TOL64
+
+
 MAX_AXIS_CASES = [
     # the longest supported axes: 4096 points in the FP32 form; in plain FP64 the fused pass's
     # LDS ((4 M + 256) 16 bytes <= 160 KiB) allows M <= 2496 (here 2496 = 2^6 3 13, runtime radices)
