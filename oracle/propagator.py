@@ -375,7 +375,7 @@ def expand_pair(psi: np.ndarray, psi_plus: np.ndarray, dx, m_over_hbar: float, t
 
 
 # ----------------------------------------------------------------------------------------
-# Far-field estimate (section 2.2, eqs. (farfieldk), (FT), (Psiwtm)): the comparator the
+# Far-field estimate (section 2.3, eqs. (farfieldk), (FT), (Psiwtm)): the comparator the
 # finite-time expansion replaces.
 # ----------------------------------------------------------------------------------------
 

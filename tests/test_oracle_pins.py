@@ -308,12 +308,6 @@ def test_linearity():
     assert rel(lhs, rhs) <= 1e-14
 
 
-def test_column_density_is_weighted_axis_sum():
-    rho = np.arange(24, dtype=float).reshape(2, 3, 4)
-    img = oracle.column_density(rho, 0, (5, 1, 1), (0.5, 1.0, 1.0))
-    assert np.allclose(img, (rho[0] + rho[1]) * 2.5)
-
-
 # ---------------------------------------------------------------------------------------
 # Planted mistakes: copies of the oracle arithmetic with one error each must fail a pin.
 # ---------------------------------------------------------------------------------------
