@@ -1,17 +1,20 @@
 #!/usr/bin/env python3
 """Throughput of the free-flight expansion (prescription (FF), section 5.2) on one MI355X.
 
-A step is one whole expansion of the workload's field: every q-term of (FFpsi)
+A step is one whole expansion of the workload: every q-term of (FFpsi)
 (premultiply, forward transform, chirp, pruned inverse, twiddle-gather-
-accumulate) and the density |Psibar|^2, with the input already resident in
-device memory. The default workload is the 2D 512x512 elongated
-quasicondensate, magnification 32 per axis (1024 terms), FP32 data with
-FP64-built phase tables.
+accumulate) and the density |Psibar|^2 of every field, with the inputs already
+resident in device memory. The default workload is the ragged ensemble of 768
+3-D realizations (256 each of 32x32x256, 48x48x384 and 64x64x512, magnification
+40 per axis, 64000 terms each), expanded by one HIP graph launch per step, in
+the FP32 form (FP32 data, FP64-built phase tables: the headline value) and in
+plain FP64 on the same ensemble; --config selects the single-field workloads.
 
 Prints one JSON line with the throughput in output lattice points per second,
-the roofline of the dominant pass (timed with HIP events on its own launch
-stream inside the timed region) and the CPU oracle timed on the host as a
-baseline.
+the FP64 line and the speedup between the two, the roofline of the dominant
+kernel (its launches timed with HIP events on the stream they run on), the
+relative L2 error of one realization per shape class against the oracle, and
+the CPU oracle timed on the host as a baseline.
 """
 
 from __future__ import annotations
@@ -119,82 +122,202 @@ def cpu_baseline(wl, field, lam, dx, t):
                                 f"long-double kernel tables + FP64 per-axis contraction"}
 
 
-def bench_batch(args):
-    """Ragged ensemble: every realization of the workload expanded by one graph launch per step."""
+def _time_batch(b, psis, outs, rhos, steps, warmup, stream):
+    """Warmup, then EXACTLY `steps` graph launches bracketed by synchronisations; returns ms per step."""
+    import torch
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            b.run(psis, psi_outs=outs, rho_outs=rhos)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(steps):
+            b.run(psis, psi_outs=outs, rho_outs=rhos)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / max(steps, 1)
+
+
+def _batch_pass_rows(b, psis, outs, rhos, stream, csize):
+    """Per-pass kernel durations of one ensemble run, per class: HIP events the library records on
+    the stream every launch goes to (the class's lane) while timing is on (the run is then issued
+    eagerly, launch by launch, in the configuration the graph holds). Flops of a pass over the whole
+    class: the per-launch count of one work item (G realizations, one q-block) times the items."""
+    import torch
+    classes = b.classes()
+    for c in classes:
+        c["plan"].set_timing(True)
+        c["plan"].pass_times()
+    with torch.cuda.stream(stream):
+        b.run(psis, psi_outs=outs, rho_outs=rhos)
+    torch.cuda.synchronize()
+    rows = []
+    for c in classes:
+        plan = c["plan"]
+        times = plan.pass_times()
+        plan.set_timing(False)
+        desc = json.loads(plan.describe())
+        G = desc["slices"]
+        nmem = len(c["members"])
+        seen = {}
+        for i, (n_launch, tot_ms) in enumerate(times):
+            if n_launch == 0 or i >= len(desc["passes"]):
+                continue
+            pdesc = desc["passes"][i]
+            key = f'{pdesc["kind"]}#{seen.get(pdesc["kind"], 0)}'
+            seen[pdesc["kind"]] = seen.get(pdesc["kind"], 0) + 1
+            f_launch, b_launch = pass_cost(pdesc, csize)
+            # every pass is linear in the slices (G realizations) and in the q-block of the outer
+            # index: scale one item's count to the whole class
+            lam_outer = desc["passes"][0]["lam"]
+            scale = (nmem / G) * (lam_outer / desc["outer_block"])
+            rows.append({"class": "x".join(str(x) for x in plan.shape), "pass": f'{pdesc["kind"]}(axis{pdesc["axis"]})',
+                         "key": key, "kernel": pdesc.get("kernel", "?"), "launches": n_launch, "ms": tot_ms,
+                         "avg_ms": tot_ms / n_launch, "flops": f_launch * scale, "bytes": b_launch * scale,
+                         "tflops": f_launch * scale / (tot_ms * 1e-3) / 1e12,
+                         "gbs": b_launch * scale / (tot_ms * 1e-3) / 1e9,
+                         "group": G, "q_block": desc["outer_block"], "lane": c["lane"]})
+    return classes, rows
+
+
+def bench_c4(args, fields):
+    """The ragged ensemble: every realization expanded by one graph launch per step, FP32 form
+    (headline) and plain FP64 on the same ensemble."""
     import numpy as np
     import torch
 
     import paper_1602_03395_amd as fx
     import workloads
 
-    n = args.members
-    dtype_name = args.dtype or "c64"
-    dtype = torch.complex64 if dtype_name == "c64" else torch.complex128
-    npdt = np.complex64 if dtype_name == "c64" else np.complex128
-    seqs = np.random.SeedSequence(3).spawn(768)
     dev = torch.device("cuda:0")
-    psis = []
-    t_gen = time.perf_counter()
-    for i in range(n):
-        f = workloads.ensemble_member_3d(workloads.C4_SHAPES[i % 3], seqs[i]).astype(npdt)
-        psis.append(torch.from_numpy(f).to(dev))
-    t_gen = time.perf_counter() - t_gen
-    specs = [dict(shape=tuple(p.shape), dx=(1.0, 1.0, 1.0), lam=(40, 40, 40), t=400.0) for p in psis]
-    t0 = time.perf_counter()
-    b = fx.Batch(specs, dtype=dtype, schedule=args.schedule)
-    t_create = time.perf_counter() - t0
-    outs = [torch.empty_like(p) for p in psis]
-    rhos = [torch.empty(p.shape, dtype=torch.float32 if dtype == torch.complex64 else torch.float64, device=dev)
-            for p in psis]
+    n = len(fields)
+    lam, t, dx = (40, 40, 40), 400.0, (1.0, 1.0, 1.0)
+    specs = [dict(shape=tuple(f.shape), dx=dx, lam=lam, t=t) for f in fields]
+    npts = sum(int(f.size) for f in fields)
     stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            b.run(psis, psi_outs=outs, rho_outs=rhos)
-        stream.synchronize()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
-        for _ in range(args.steps):
-            b.run(psis, psi_outs=outs, rho_outs=rhos)
-        ev1.record(stream)
-        stream.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
-    npts = sum(int(np.prod(p.shape)) for p in psis)
     result = {
         "metric": "expanded lattice pts/s + HBM roofline %, FP32/FP64-phase vs FP64 at 1e-5 err",
-        "value": npts / (ms * 1e-3), "unit": "output lattice pts/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32" if dtype == torch.complex64 else "f64", "data": "synthetic",
-        "config": {"workload": "c4_ragged_ensemble", "members": n, "shapes": [list(s) for s in workloads.C4_SHAPES],
-                   "lam": [40, 40, 40], "t": 400.0, "terms_per_member": 64000, "schedule": args.schedule,
-                   "precision": "c64_phase64" if dtype == torch.complex64 else "c128"},
-        "q_term_pts_per_s": npts * 64000 / (ms * 1e-3),
-        "batch_create_s": t_create, "input_generation_s": t_gen, "roofline": None, "cpu_baseline": None,
+        "unit": "output lattice pts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c4_ragged_ensemble", "members": n,
+                   "shapes": [list(s) for s in workloads.C4_SHAPES], "lam": list(lam), "t": t, "dx": list(dx),
+                   "terms_per_member": 64000, "schedule": args.schedule, "precision": "c64_phase64",
+                   "launch": "one HIP graph launch per ensemble"},
     }
+    # parity members: the first realization of every shape class
+    par_idx = sorted({min(i for i in range(n) if fields[i].shape == shp) for shp in {f.shape for f in fields}})
+
+    # ---- FP32 data, FP64-built phase tables (the headline) ----
+    psis = [torch.from_numpy(f).to(dev) for f in fields]
+    outs = [torch.empty_like(x) for x in psis]
+    rhos = [torch.empty(x.shape, dtype=torch.float32, device=dev) for x in psis]
+    tc = time.perf_counter()
+    b = fx.Batch(specs, dtype=torch.complex64, schedule=args.schedule)
+    create32 = time.perf_counter() - tc
+    w0 = time.perf_counter()
+    ms32 = _time_batch(b, psis, outs, rhos, args.steps, args.warmup, stream)
+    wall32 = time.perf_counter() - w0
+    result.update({"value": npts / (ms32 * 1e-3), "ms_per_step": ms32,
+                   "q_term_pts_per_s": npts * 64000 / (ms32 * 1e-3)})
+    got32 = {i: (rhos[i].cpu().numpy().astype(np.float64), outs[i].cpu().numpy().astype(np.complex128))
+             for i in par_idx}
+    classes, rows = ([], [])
+    if not args.no_pass_timing:
+        classes, rows = _batch_pass_rows(b, psis, outs, rhos, stream, 8)
+    cls_info = [{"shape": list(c["plan"].shape), "members": len(c["members"]), "group": c["group"],
+                 "lane": c["lane"], "passes": [{"kind": p["kind"], "axis": p["axis"], "kernel": p.get("kernel"),
+                                               "qn": p["qn"]} for p in json.loads(c["plan"].describe())["passes"]]}
+                for c in (classes or b.classes())]
+    result["config"]["classes"] = cls_info
+    roofline = None
+    if rows:
+        dom = max(rows, key=lambda r: r["ms"])
+        roofline = {"bound": "alu", "achieved": dom["tflops"], "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                    "frac": dom["tflops"] / PEAK_FP32_TFLOPS, "traffic": None,
+                    "kernel": f'{dom["kernel"]} ({dom["pass"]}, class {dom["class"]})',
+                    "flops_per_step": dom["flops"], "ms_per_step": dom["ms"],
+                    "launches_per_step": dom["launches"], "avg_launch_ms": dom["avg_ms"]}
+        ai = dom["flops"] / max(dom["bytes"], 1)
+        if ai < PEAK_FP32_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9):
+            roofline.update({"bound": "hbm", "achieved": dom["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                             "frac": dom["gbs"] / PEAK_HBM_GBS})
+        tr = load_traffic(f"c4_ragged_ensemble/c64/{args.schedule}", f'{dom["class"]}/{dom["key"]}')
+        if tr is not None:
+            roofline["traffic"] = tr * dom["launches"]  # bytes per step of that kernel
+        result["passes"] = rows
+    result["roofline"] = roofline
+    del b, psis, outs, rhos
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+    # ---- plain FP64 on the same ensemble (inputs upcast exactly) ----
+    fp64 = None
+    got64 = {}
+    if not args.no_fp64:
+        psis = [torch.from_numpy(f).to(dev).to(torch.complex128) for f in fields]
+        outs = [torch.empty_like(x) for x in psis]
+        rhos = [torch.empty(x.shape, dtype=torch.float64, device=dev) for x in psis]
+        tc = time.perf_counter()
+        b = fx.Batch(specs, dtype=torch.complex128, schedule=args.schedule)
+        create64 = time.perf_counter() - tc
+        steps64 = args.fp64_steps if args.fp64_steps is not None else args.steps
+        warm64 = min(args.warmup, 2)
+        ms64 = _time_batch(b, psis, outs, rhos, steps64, warm64, stream)
+        got64 = {i: (rhos[i].cpu().numpy(), outs[i].cpu().numpy()) for i in par_idx}
+        fp64 = {"ms_per_step": ms64, "value": npts / (ms64 * 1e-3), "steps": steps64, "warmup": warm64,
+                "batch_create_s": create64}
+        del b, psis, outs, rhos
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    result["fp64"] = fp64
+    result["speedup_fp32_vs_fp64"] = (fp64["ms_per_step"] / ms32) if fp64 else None
+    result["batch_create_s"] = create32
+    result["wall_s_timed_fp32"] = wall32
+
+    # ---- the oracle on one realization per class: CPU baseline and parity of the batched outputs ----
+    cpu = None
+    parity = {}
     if not args.no_cpu_baseline:
         import oracle
         from oracle import propagator as OP
-        OP._axis_matrix_cached.cache_clear()
-        f0 = psis[0].cpu().numpy().astype(np.complex128)
-        tc = time.perf_counter()
-        ref = oracle.expand(f0, (1.0, 1.0, 1.0), 1.0, 400.0, (40, 40, 40))
-        dt = time.perf_counter() - tc
         threads = min(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1)
-        result["cpu_baseline"] = {"value": f0.size / dt, "unit": "output lattice pts/s", "cores": threads,
-                                  "kind": "oracle", "seconds": dt,
-                                  "sample": "realization 0 (32x32x256) of the ensemble, full oracle solve"}
-        got = rhos[0].cpu().numpy().astype(np.float64)
-        rr = oracle.density(ref)
-        result["rel_l2_rho_vs_oracle_member0"] = float(np.linalg.norm(got - rr) / np.linalg.norm(rr))
+        secs = 0.0
+        pts = 0
+        for i in par_idx:
+            OP._axis_matrix_cached.cache_clear()
+            f = fields[i].astype(np.complex128)
+            tc = time.perf_counter()
+            ref = oracle.expand(f, dx, 1.0, t, lam)
+            secs += time.perf_counter() - tc
+            pts += f.size
+            rr = oracle.density(ref)
+            name = "x".join(str(x) for x in f.shape)
+            ent = {"member": i, "fp32_rho_rel_l2": float(np.linalg.norm(got32[i][0] - rr) / np.linalg.norm(rr)),
+                   "fp32_psi_rel_l2": float(np.linalg.norm(got32[i][1] - ref) / np.linalg.norm(ref))}
+            if i in got64:
+                ent["fp64_rho_rel_l2"] = float(np.linalg.norm(got64[i][0] - rr) / np.linalg.norm(rr))
+                ent["fp64_psi_rel_l2"] = float(np.linalg.norm(got64[i][1] - ref) / np.linalg.norm(ref))
+            parity[name] = ent
+        cpu = {"value": pts / secs, "unit": "output lattice pts/s", "cores": threads, "kind": "oracle",
+               "seconds": secs,
+               "sample": f"the first realization of each of the {len(par_idx)} shape classes ({pts} output points), "
+                         "full oracle solves: per-axis long-double kernel tables + FP64 per-axis contraction"}
+    result["cpu_baseline"] = cpu
+    result["speedup_gpu_vs_cpu_oracle"] = (result["value"] / cpu["value"]) if cpu else None
+    result["parity_vs_oracle"] = parity or None
     print(json.dumps(result), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c4", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--fp64-steps", type=int, default=None,
+                    help="c4 ensemble: timed steps of the plain FP64 run (default: --steps)")
+    ap.add_argument("--no-fp64", action="store_true", help="c4 ensemble: skip the plain FP64 run")
     ap.add_argument("--members", type=int, default=768, help="c4 only: number of realizations")
     ap.add_argument("--member", type=int, default=None,
                     help="c4 only: expand this single realization through one plan (per-pass timing)")
@@ -219,17 +342,25 @@ def main():
         sys.exit(2)
 
     import numpy as np
+
+    import workloads
+
+    c4_fields = None
+    if args.config == "c4" and args.member is None:
+        # host generation in forked workers, before this process touches the GPU
+        workers = max(1, min(16, os.cpu_count() or 1))
+        c4_fields = workloads.c4_fields_c64(range(args.members), workers=workers)
+
     import torch
 
     import paper_1602_03395_amd as fx
-    import workloads
 
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}), flush=True)
         sys.exit(3)
 
-    if args.config == "c4" and args.member is None:
-        return bench_batch(args)
+    if c4_fields is not None:
+        return bench_c4(args, c4_fields)
 
     if args.config == "c4":
         wl = workloads.make_c4(members=[args.member])
@@ -362,14 +493,10 @@ def main():
         tag = f"{wl.name}/{dtype_name}/{args.schedule}" + ("" if args.variant == "free" else f"/{args.variant}")
         roofline["traffic"] = load_traffic(tag, dom["key"])
 
-    # Whole-step HBM view: (1) measured bytes (copy-calibrated counters of every pass, while they
-    # match the kernel sources) over the step time, (2) the per-term streaming model (two M-point
-    # round trips per term: 2 Q M complex per solve) over the step time, which the shared per-axis
-    # prefixes and the register-resident transforms beat, so it exceeds 1 (the passes are bound by
-    # VALU issue, see roofline).
+    # Whole-step HBM view: measured bytes (copy-calibrated counters of every pass, while they match
+    # the kernel sources) over the step time, as a fraction of the HBM peak.
     step_s = ms_per_step * 1e-3
-    hbm = {"peak_GBs": PEAK_HBM_GBS, "stream_model_bytes_per_step": 2.0 * terms * int(np.prod(psi.shape)) * csize}
-    hbm["stream_model_frac"] = hbm["stream_model_bytes_per_step"] / step_s / 1e9 / PEAK_HBM_GBS
+    hbm = {"peak_GBs": PEAK_HBM_GBS}
     measured = [load_traffic(tag, r["key"]) for r in pass_rows] if pass_rows else []
     if measured and all(m is not None for m in measured):
         tot = sum(m * r["launches_per_step"] for m, r in zip(measured, pass_rows))

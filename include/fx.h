@@ -26,7 +26,9 @@
  *    float64 resp. float32.
  *  - Every data pointer is a DEVICE pointer owned by the caller. The library
  *    never frees, retains or aliases caller memory beyond the call. Inputs
- *    and outputs must not overlap.
+ *    and outputs must not overlap: every call checks the byte ranges on the
+ *    host and returns FX_EINVAL when an output intersects an input or
+ *    another output.
  *  - `stream` is a hipStream_t (NULL = the legacy default stream). Work is
  *    enqueued on it and the call returns without synchronising; outputs are
  *    valid once the stream reaches that point. A plan must not be used on
@@ -206,6 +208,23 @@ fx_status fx_density_adjoint(fx_plan* plan, const void* psibar, const void* grad
                              void* stream);
 
 /*
+ * Stacks of fields (ensembles of realizations, section 1; batches of fields fitted to images):
+ * `count` fields of the plan's shape stored back to back ([count][shape], C order), each
+ * expanded independently, so fx_expand_many(p, count, psi0, psi_out, rho_out, s) gives for every
+ * i < count the result fx_expand would give for field i, and fx_density_adjoint_many the gradient
+ * fx_density_adjoint would give for field i (psibar, grad_rho, grad_psi0 all stacked alike).
+ * The fields run as the leading slice dimension of every pass, in chunks of as many fields as
+ * the plan's workspace budget (or the caller's workspace, fx_plan_set_workspace) holds.
+ * count >= 1; pointers and outputs as for the single-field calls (psi_out or rho_out may be NULL,
+ * not both). Errors: FX_EINVAL (count < 1, NULL arguments, overlapping inputs and outputs),
+ * FX_EUNSUPPORTED (a single field's pass tensors reach 2^31 elements), FX_ENOMEM, FX_EDEVICE.
+ */
+fx_status fx_expand_many(fx_plan* plan, int64_t count, const void* psi0, void* psi_out, void* rho_out,
+                         void* stream);
+fx_status fx_density_adjoint_many(fx_plan* plan, int64_t count, const void* psibar, const void* grad_rho,
+                                  void* grad_psi0, void* stream);
+
+/*
  * Positive-P pairs (section 7.4, generalisations): the two independent fields
  * psi and psi^+ that stand for the annihilation and creation operators are
  * expanded together, as two slices of one run of the plan's passes. psi follows
@@ -230,7 +249,7 @@ fx_status fx_expand_pair(fx_plan* plan, const void* psi, const void* psi_plus, v
 fx_status fx_plan_pair_workspace_size(const fx_plan* plan, size_t* bytes);
 
 /*
- * Far-field estimate (section 2.2, eq. (farfieldk)) on the plan's magnified output
+ * Far-field estimate (section 2.3, eq. (farfieldk)) on the plan's magnified output
  * lattice, the comparator the finite-time expansion replaces:
  *   amp[nbar] = (m / hbar t)^(d/2) Psi~(m xbar(nbar) / hbar t),   rho_ff = |amp|^2,
  * with Psi~ the norm-preserving transform of eq. (FT) summed over the input lattice as
@@ -263,12 +282,19 @@ fx_status fx_far_field(fx_plan* plan, const void* psi0, void* amp_out, void* rho
 fx_status fx_brute_force(fx_plan* plan, const void* psi0, void* psi_out, void* rho_out, void* stream);
 
 /*
- * Ragged batch of problems (ensembles of realizations, section 1): problems
- * with equal shape, spacing, offsets, magnification, flight and precision
- * share one plan and run as one batched pass sequence; different shape
- * classes follow each other. The kernel sequence of a run is captured once
- * into a HIP graph and replayed with a single launch per fx_batch_run.
- * All problems must have the same precision.
+ * Ragged batch of problems (ensembles of realizations, section 1; the terms q of each are
+ * independent, section 7.1): problems equal up to their input field form a shape class with
+ * one plan. A class is cut into work items of G realizations and one block of the outermost
+ * magnification index (the q-block): the G fields run as the leading slice dimension of every
+ * pass and the q-blocks accumulate into the item's output. Each class runs on a stream of its
+ * own, forked from and joined back into the caller's stream, largest class first, so the
+ * kernels of different classes overlap on the device. fx_batch_create autotunes each class
+ * (G and the q-block, register or LDS transform family, fused or split accumulate, tile size,
+ * persistent grids) and the class concurrency by timing eager runs, then launches every kernel
+ * once; the first fx_batch_run on a stream captures the whole fork-join sequence into a HIP
+ * graph, replayed with a single graph launch per run. All problems must have the same
+ * precision. Errors: FX_EINVAL (NULL, n < 1, an invalid problem, mixed precisions),
+ * FX_EUNSUPPORTED, FX_ENOMEM, FX_EDEVICE.
  */
 fx_status fx_batch_create(const fx_problem* probs, int32_t n, fx_batch** out);
 fx_status fx_batch_destroy(fx_batch* batch);
@@ -277,11 +303,29 @@ fx_status fx_batch_destroy(fx_batch* batch);
  * Runs the batch: for each i < n, psi_out[i] = Psibar_i and rho_out[i] =
  * |Psibar_i|^2 (either array, or any entry of psi_out, may be NULL; rho_out
  * entries may be NULL only when psi_out[i] is not). The pointer arrays are
- * HOST arrays of DEVICE pointers. The first run on a stream, or a run with
- * different pointers, re-captures the graph.
+ * HOST arrays of DEVICE pointers; inputs may be shared between realizations,
+ * outputs must be disjoint from each other and from every input (checked on
+ * the host). The first run on a stream, or a run with different pointers,
+ * re-captures the graph. While per-pass timing is enabled on a class plan
+ * (fx_plan_set_timing on the plan from fx_batch_class), runs are issued
+ * eagerly instead, so that the plan's events time every launch.
  */
 fx_status fx_batch_run(fx_batch* batch, const void* const* psi0, void* const* psi_out,
                        void* const* rho_out, void* stream);
+
+/*
+ * Introspection of a created batch (profiling, tests). Classes are numbered in issue order
+ * (largest first). fx_batch_class returns the class plan (owned by the batch: never destroy
+ * it; it may be used with fx_plan_describe, fx_plan_set_timing and fx_plan_pass_times), the
+ * number of realizations, the realizations per work item and the lane the class runs on; any
+ * output pointer may be NULL. fx_batch_class_members writes the first min(max, members) batch
+ * indices of the class's realizations (host array). Errors: FX_EINVAL (NULL batch, index out
+ * of range).
+ */
+fx_status fx_batch_num_classes(const fx_batch* batch, int32_t* n);
+fx_status fx_batch_class(fx_batch* batch, int32_t i, fx_plan** plan, int32_t* members, int64_t* group,
+                         int32_t* lane);
+fx_status fx_batch_class_members(const fx_batch* batch, int32_t i, int32_t* members, int32_t max);
 
 /*
  * Per-pass timing (profiling aid). With enable != 0 every pass launch of this

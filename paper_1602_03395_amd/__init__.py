@@ -18,7 +18,8 @@ from .api import (  # noqa: F401
     expand_density,
     fine_wavenumbers,
     get_plan,
+    real_dtype,
 )
 
 __all__ = ["Plan", "Batch", "expand_batch", "expand", "expand_adjoint", "expand_density", "ExpandDensity", "column_density", "get_plan",
-           "fine_wavenumbers"]
+           "fine_wavenumbers", "real_dtype"]

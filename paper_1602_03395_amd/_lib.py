@@ -81,6 +81,8 @@ def _load():
         "fx_column_density": (ctypes.c_int, [vp, vp, ctypes.c_int, vp, vp]),
         "fx_expand_adjoint": (ctypes.c_int, [vp, vp, vp, vp]),
         "fx_density_adjoint": (ctypes.c_int, [vp, vp, vp, vp, vp]),
+        "fx_expand_many": (ctypes.c_int, [vp, ctypes.c_int64, vp, vp, vp, vp]),
+        "fx_density_adjoint_many": (ctypes.c_int, [vp, ctypes.c_int64, vp, vp, vp, vp]),
         "fx_expand_pair": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "fx_plan_pair_workspace_size": (ctypes.c_int, [vp, P(ctypes.c_size_t)]),
         "fx_far_field": (ctypes.c_int, [vp, vp, vp, vp, vp]),
@@ -88,6 +90,10 @@ def _load():
         "fx_batch_create": (ctypes.c_int, [P(fx_problem), ctypes.c_int32, P(vp)]),
         "fx_batch_destroy": (ctypes.c_int, [vp]),
         "fx_batch_run": (ctypes.c_int, [vp, P(vp), P(vp), P(vp), vp]),
+        "fx_batch_num_classes": (ctypes.c_int, [vp, P(ctypes.c_int32)]),
+        "fx_batch_class": (ctypes.c_int, [vp, ctypes.c_int32, P(vp), P(ctypes.c_int32), P(ctypes.c_int64),
+                                          P(ctypes.c_int32)]),
+        "fx_batch_class_members": (ctypes.c_int, [vp, ctypes.c_int32, P(ctypes.c_int32), ctypes.c_int32]),
         "fx_plan_describe": (ctypes.c_int, [vp, ctypes.c_char_p, ctypes.c_size_t]),
         "fx_plan_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
         "fx_plan_pass_times": (ctypes.c_int, [vp, P(ctypes.c_int32), P(ctypes.c_int64), P(ctypes.c_double),

@@ -146,6 +146,45 @@ class Plan:
                                 _ptr(rho_out) if want_rho else None, _stream_ptr()), "fx_expand")
         return (psi_out if want_psi else None), (rho_out if want_rho else None)
 
+    def expand_many(self, psi0: torch.Tensor, want_psi: bool = True, want_rho: bool = True,
+                    psi_out: Optional[torch.Tensor] = None, rho_out: Optional[torch.Tensor] = None):
+        """A stack [count, *shape] of independent fields: returns (psi or None, rho or None), see
+        ``fx_expand_many``."""
+        _check_field(psi0, "psi0")
+        count = self._check_stack(psi0)
+        if want_psi and psi_out is None:
+            psi_out = torch.empty_like(psi0)
+        if want_rho and rho_out is None:
+            rho_out = torch.empty(psi0.shape, dtype=real_dtype(psi0.dtype), device=psi0.device)
+        L.check(L.lib.fx_expand_many(self._h, count, _ptr(psi0), _ptr(psi_out) if want_psi else None,
+                                     _ptr(rho_out) if want_rho else None, _stream_ptr()), "fx_expand_many")
+        return (psi_out if want_psi else None), (rho_out if want_rho else None)
+
+    def density_adjoint_many(self, psibar: torch.Tensor, grad_rho: torch.Tensor,
+                             grad_in: Optional[torch.Tensor] = None):
+        """Stacked form of ``density_adjoint`` ([count, *shape]), see ``fx_density_adjoint_many``."""
+        _check_field(psibar, "psibar")
+        count = self._check_stack(psibar)
+        if grad_rho.dtype != real_dtype(self.dtype) or grad_rho.device.type != "cuda":
+            raise ValueError("grad_rho must be a device tensor of the plan's real dtype")
+        grad_rho = grad_rho.contiguous()
+        if tuple(grad_rho.shape) != tuple(psibar.shape):
+            raise ValueError("grad_rho has the wrong shape")
+        if grad_in is None:
+            grad_in = torch.empty_like(psibar)
+        L.check(L.lib.fx_density_adjoint_many(self._h, count, _ptr(psibar), _ptr(grad_rho), _ptr(grad_in),
+                                              _stream_ptr()), "fx_density_adjoint_many")
+        return grad_in
+
+    def _check_stack(self, x: torch.Tensor) -> int:
+        if x.dim() != len(self.shape) + 1 or tuple(x.shape[1:]) != self.shape:
+            raise ValueError(f"a stack of fields must have shape [count, *{self.shape}] (got {tuple(x.shape)})")
+        if x.dtype != self.dtype:
+            raise ValueError(f"tensor dtype {x.dtype} does not match the plan's {self.dtype}")
+        if x.shape[0] < 1:
+            raise ValueError("a stack needs at least one field")
+        return int(x.shape[0])
+
     def expand_range(self, psi0: torch.Tensor, psi_acc: torch.Tensor, q_begin: int, q_end: int,
                      accumulate: bool = False):
         _check_field(psi0, "psi0")
@@ -339,6 +378,26 @@ class Batch:
     def __len__(self):
         return len(self.shapes)
 
+    def classes(self):
+        """Shape classes in issue order: dicts with the class plan (owned by the batch), the
+        batch indices of its realizations, the realizations per work item and the lane."""
+        n = ctypes.c_int32()
+        L.check(L.lib.fx_batch_num_classes(self._h, ctypes.byref(n)), "fx_batch_num_classes")
+        out = []
+        for i in range(n.value):
+            h = ctypes.c_void_p()
+            mem = ctypes.c_int32()
+            grp = ctypes.c_int64()
+            lane = ctypes.c_int32()
+            L.check(L.lib.fx_batch_class(self._h, i, ctypes.byref(h), ctypes.byref(mem), ctypes.byref(grp),
+                                         ctypes.byref(lane)), "fx_batch_class")
+            idx = (ctypes.c_int32 * max(1, mem.value))()
+            L.check(L.lib.fx_batch_class_members(self._h, i, idx, mem.value), "fx_batch_class_members")
+            members = [int(idx[k]) for k in range(mem.value)]
+            plan = _BatchClassPlan(h, self.shapes[members[0]], self.dtype, self)
+            out.append({"plan": plan, "members": members, "group": int(grp.value), "lane": int(lane.value)})
+        return out
+
     def run(self, psis, psi_outs=None, rho_outs=None, want_psi=True, want_rho=True):
         n = len(self.shapes)
         if len(psis) != n:
@@ -359,6 +418,20 @@ class Batch:
         return (psi_outs if want_psi else None), (rho_outs if want_rho else None)
 
 
+class _BatchClassPlan(Plan):
+    """A class plan owned by a ``Batch`` (describe, per-pass timing); never destroyed here."""
+
+    def __init__(self, handle, shape, dtype, owner):
+        self.shape = tuple(int(x) for x in shape)
+        self.dtype = dtype
+        self._h = handle
+        self._ws = None
+        self._owner = owner  # keeps the batch, and so the plan, alive
+
+    def __del__(self):
+        pass
+
+
 def expand_batch(psis, specs, schedule: str = "paper"):
     """Expands a ragged list of fields; ``specs`` is one dict (shared) or one per field."""
     if isinstance(specs, dict):
@@ -368,18 +441,39 @@ def expand_batch(psis, specs, schedule: str = "paper"):
     return b.run(psis)
 
 
+def _problem_ndim(x: torch.Tensor, lam) -> int:
+    """Number of lattice axes: len(lam) when lam is a sequence, else every axis of x."""
+    if isinstance(lam, (int, float, np.integer, np.floating)):
+        return x.dim()
+    return len(lam)
+
+
 class ExpandDensity(torch.autograd.Function):
     """rho = |U psi0|^2 with the hand-written adjoint U^H for the backward pass.
 
     For a real loss L(rho), PyTorch's complex gradient convention
     (dL/dRe + i dL/dIm) gives grad_psi0 = U^H (2 * grad_rho * Psibar).
+
+    psi0 holds one field of d = len(lam) axes, or a stack [count, *shape] of independent
+    fields (one more leading axis than lam has entries), which forward and backward each
+    process in one library call. A scalar lam means one field over every axis of psi0.
     """
 
     @staticmethod
     def forward(ctx, psi0, dx, m_over_hbar, t, lam, a=None, abar=None, schedule="paper"):
         psi0 = psi0.contiguous()
-        plan = get_plan(psi0.shape, dx, m_over_hbar, t, lam, a, abar, psi0.dtype, schedule)
-        psi, rho = plan.expand(psi0, want_psi=True, want_rho=True)
+        d = _problem_ndim(psi0, lam)
+        if psi0.dim() == d:
+            plan = get_plan(psi0.shape, dx, m_over_hbar, t, lam, a, abar, psi0.dtype, schedule)
+            psi, rho = plan.expand(psi0, want_psi=True, want_rho=True)
+            ctx.stacked = False
+        elif psi0.dim() == d + 1:
+            plan = get_plan(psi0.shape[1:], dx, m_over_hbar, t, lam, a, abar, psi0.dtype, schedule)
+            psi, rho = plan.expand_many(psi0, want_psi=True, want_rho=True)
+            ctx.stacked = True
+        else:
+            raise ValueError(f"psi0 must have {d} axes (one field) or {d + 1} (a stack of fields), "
+                             f"got {psi0.dim()}")
         ctx.plan = plan
         ctx.save_for_backward(psi)
         return rho
@@ -387,7 +481,11 @@ class ExpandDensity(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_rho):
         (psi,) = ctx.saved_tensors
-        grad = ctx.plan.density_adjoint(psi, grad_rho.to(psi.real.dtype))
+        g = grad_rho.to(psi.real.dtype)
+        if ctx.stacked:
+            grad = ctx.plan.density_adjoint_many(psi, g)
+        else:
+            grad = ctx.plan.density_adjoint(psi, g)
         return grad, None, None, None, None, None, None, None
 
 

@@ -2,20 +2,33 @@
 // samples, section 1) of possibly different lattice shapes, expanded in one go.
 //
 // Problems that are identical up to their input field form a shape class and
-// share one plan; a class runs in groups of G realizations stacked as the
-// leading slice dimension of the pass tensors, so every pass of the schedule
-// covers G fields at once. Per group: gather the caller's G input pointers
-// into a contiguous staging tensor, run the plan's passes, scatter the field
-// and density to the caller's outputs. The whole sequence over all classes
-// and groups is captured once into a HIP graph and replayed with a single
-// graph launch per run; the transform passes inside run as persistent grids
-// (a capped number of workgroups looping over the tile list) when the
-// autotuner finds that faster.
+// share one plan. A class is cut into work items of G realizations by one block
+// of the outermost magnification index (the q-block): an item stacks its G
+// fields as the leading slice dimension of every pass of the schedule, so each
+// kernel launch of the item covers G fields and a range of terms q at once, and
+// the q-blocks of an item accumulate into its output (the sequential
+// accumulation over q of section 7.1). Per item group: gather the caller's G
+// input pointers into the class's staging tensor, run the passes over every
+// q-block, scatter the field and density to the caller's outputs.
 //
-// Autotuning (per class, at batch creation): every candidate (preferred tile
-// size, persistent grid or not, fused or split 1-D expansion passes) runs one
-// group eagerly, timed with HIP events; the fastest is kept. Results are cached
-// per process and, with FX_AUTOTUNE_CACHE=<file>, on disk.
+// Classes are independent, so each class runs on a lane stream of its own: the
+// run forks from the caller's stream into the lanes and joins back, and the
+// largest classes (by terms x points x members) are issued first. The whole
+// fork-join sequence is captured once into a HIP graph, whose parallel branches
+// let the device interleave the kernels of different classes (one class's tail
+// waves fill with another's work), and replayed with a single graph launch per
+// run. Inside a class the transform passes run as persistent grids where the
+// tuner finds that faster.
+//
+// Autotuning (per class, at batch creation, coordinate descent from the
+// defaults): the realizations per item G and the q-block, the transform family
+// (register-resident lane transforms or LDS Stockham radix-8/4/2 stages), the
+// fused or split structured accumulate, the LDS tile size and persistent grids;
+// each candidate runs one full item eagerly, timed with HIP events, and the
+// choice with the best time per realization is kept. Then the lane concurrency
+// (all classes in parallel, or one after the other) is timed on one item of
+// every class. Results are cached per process and, with FX_AUTOTUNE_CACHE=<file>,
+// on disk.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -38,17 +51,26 @@ struct Tune {
     int ts_target = 2048;
     int persist = 0;
     bool allow_split = true;
+    bool use_cfp = true;
+    int use_eas = 1;
+    int64_t group = 0;  // realizations per item (0: the largest that fits the workspace budget)
+    int64_t qblock = 0; // outermost magnification indices per q-block (0: as the budget allows)
+    bool operator==(const Tune& o) const {
+        return ts_target == o.ts_target && persist == o.persist && allow_split == o.allow_split &&
+               use_cfp == o.use_cfp && use_eas == o.use_eas && group == o.group && qblock == o.qblock;
+    }
 };
 
 std::mutex g_tune_mu;
 std::map<std::string, Tune> g_tune;
+std::map<std::string, int> g_conc;
 bool g_tune_loaded = false;
 
-std::string class_key(const fx_problem& p, int64_t group) {
+std::string class_key(const fx_problem& p, size_t members) {
     std::ostringstream o;
     o << p.ndim << ":";
     for (int j = 0; j < p.ndim; ++j) o << p.shape[j] << "x" << p.lambda[j] << ",";
-    o << "prec" << p.precision << ":sched" << p.schedule << ":G" << group;
+    o << "prec" << p.precision << ":sched" << p.schedule << ":n" << members;
     return o.str();
 }
 
@@ -58,12 +80,25 @@ void load_tune_cache() {
     const char* path = std::getenv("FX_AUTOTUNE_CACHE");
     if (!path) return;
     std::ifstream f(path);
-    std::string key;
-    Tune t;
-    int split = 1;
-    while (f >> key >> t.ts_target >> t.persist >> split) {
-        t.allow_split = split != 0;
-        g_tune[key] = t;
+    std::string kind, key;
+    while (f >> kind >> key) {
+        if (kind == "class") {
+            Tune t;
+            int split = 1, cfp = 1;
+            long long g = 0, qb = 0;
+            if (!(f >> t.ts_target >> t.persist >> split >> cfp >> t.use_eas >> g >> qb)) break;
+            t.allow_split = split != 0;
+            t.use_cfp = cfp != 0;
+            t.group = g;
+            t.qblock = qb;
+            g_tune[key] = t;
+        } else if (kind == "batch") {
+            int c = 1;
+            if (!(f >> c)) break;
+            g_conc[key] = c;
+        } else {
+            break;
+        }
     }
 }
 
@@ -72,8 +107,10 @@ void save_tune_cache() {
     if (!path) return;
     std::ofstream f(path);
     for (const auto& kv : g_tune)
-        f << kv.first << " " << kv.second.ts_target << " " << kv.second.persist << " "
-          << (kv.second.allow_split ? 1 : 0) << "\n";
+        f << "class " << kv.first << " " << kv.second.ts_target << " " << kv.second.persist << " "
+          << (kv.second.allow_split ? 1 : 0) << " " << (kv.second.use_cfp ? 1 : 0) << " " << kv.second.use_eas << " "
+          << kv.second.group << " " << kv.second.qblock << "\n";
+    for (const auto& kv : g_conc) f << "batch " << kv.first << " " << kv.second << "\n";
 }
 
 bool same_problem(const fx_problem& a, const fx_problem& b) {
@@ -93,14 +130,20 @@ struct fx_batch {
     struct Class {
         fx_plan* plan = nullptr;
         std::vector<int> members;
-        int64_t group = 1;
+        int64_t group = 1;      // realizations per item
         Tune tune;
+        void* stage = nullptr;  // gather target: group * M input values
+        size_t stage_bytes = 0;
+        int lane = 0;
+        double cost = 0;        // terms x points x members (issue order)
     };
     int n = 0;
     bool dbl = false;
-    std::vector<Class> classes;
-    void* stage_in = nullptr;  // max group * M of any class
-    size_t stage_bytes = 0;
+    std::vector<Class> classes;  // in issue order (largest cost first)
+    int concurrency = 1;         // lanes in use (1: every class on the caller's stream)
+    std::vector<hipStream_t> lanes;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> joins;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t g_stream = nullptr;
@@ -112,13 +155,38 @@ namespace {
 
 size_t cbytes(const fx_batch* b) { return b->dbl ? 16 : 8; }
 
-void apply_tune(fx_plan* p, const Tune& t) {
+// Applies the tuning knobs to the class plan and lays out its workspace for G realizations.
+void apply_tune(fx_plan* p, const Tune& t, int64_t G) {
     p->ts_target = t.ts_target;
     p->persist = t.persist;
     p->allow_split = t.allow_split;
+    p->use_cfp = t.use_cfp;
+    p->use_eas = t.use_eas;
+    p->nb_fixed = t.qblock;
+    plan_setup_workspace(p, G);
 }
 
-// Enqueues one class group: gather -> passes -> scatter.
+fx_status ensure_stage(fx_batch* b, fx_batch::Class& c, int64_t G) {
+    const size_t need = (size_t)(G * c.plan->M) * cbytes(b);
+    if (c.stage && c.stage_bytes >= need) return FX_OK;
+    if (c.stage) (void)hipFree(c.stage);
+    c.stage = nullptr;
+    c.stage_bytes = 0;
+    if (hipMalloc(&c.stage, need) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of batch staging failed");
+        return FX_ENOMEM;
+    }
+    c.stage_bytes = need;
+    // the tuner reads the staging tensor as every realization's input: give it defined values
+    if (hipMemset(c.stage, 0, need) != hipSuccess) {
+        set_error("clearing the batch staging failed");
+        return FX_EDEVICE;
+    }
+    return FX_OK;
+}
+
+// Enqueues one item group: gather -> passes over every q-block -> scatter.
 fx_status run_group(fx_batch* b, fx_batch::Class& c, size_t first, size_t count, const void* const* psi0,
                     void* const* psi_out, void* const* rho_out, hipStream_t st) {
     fx_plan* p = c.plan;
@@ -128,14 +196,14 @@ fx_status run_group(fx_batch* b, fx_batch::Class& c, size_t first, size_t count,
         const int cnt = (int)std::min<size_t>(64, count - off);
         const void* srcs[64];
         for (int i = 0; i < cnt; ++i) srcs[i] = psi0[c.members[first + off + i]];
-        if (launch_gather(b->dbl, srcs, (char*)b->stage_in + off * M * cs, M, cnt, st) != hipSuccess) {
+        if (launch_gather(b->dbl, srcs, (char*)c.stage + off * M * cs, M, cnt, st) != hipSuccess) {
             set_error("gather launch failed");
             return FX_EDEVICE;
         }
     }
     void* dst = (char*)p->ws + (size_t)2 * p->buf_elems * cs;  // the plan's output staging region
     int qb[3] = {0, 0, 0}, qn[3] = {p->ax[0].lam, p->ax[1].lam, p->ax[2].lam};
-    fx_status s = run_box(p, qb, qn, b->stage_in, dst, 0, nullptr, false, st);
+    fx_status s = run_box(p, qb, qn, c.stage, dst, 0, nullptr, false, st);
     if (s != FX_OK) return s;
     for (size_t off = 0; off < count; off += 64) {
         const int cnt = (int)std::min<size_t>(64, count - off);
@@ -155,16 +223,55 @@ fx_status run_group(fx_batch* b, fx_batch::Class& c, size_t first, size_t count,
     return FX_OK;
 }
 
-fx_status run_all(fx_batch* b, const void* const* psi0, void* const* psi_out, void* const* rho_out, hipStream_t st) {
-    for (auto& c : b->classes) {
-        for (size_t first = 0; first < c.members.size(); first += (size_t)c.group) {
-            const size_t count = std::min<size_t>((size_t)c.group, c.members.size() - first);
-            if ((int64_t)count != c.plan->slices) plan_setup_workspace(c.plan, (int64_t)count);
-            fx_status s = run_group(b, c, first, count, psi0, psi_out, rho_out, st);
-            if (s != FX_OK) return s;
-        }
+// Every item of one class, in member order, on stream st.
+fx_status run_class(fx_batch* b, fx_batch::Class& c, const void* const* psi0, void* const* psi_out,
+                    void* const* rho_out, hipStream_t st) {
+    for (size_t first = 0; first < c.members.size(); first += (size_t)c.group) {
+        const size_t count = std::min<size_t>((size_t)c.group, c.members.size() - first);
+        if ((int64_t)count != c.plan->slices) plan_setup_workspace(c.plan, (int64_t)count);
+        fx_status s = run_group(b, c, first, count, psi0, psi_out, rho_out, st);
+        if (s != FX_OK) return s;
+    }
+    if (c.plan->slices != c.group) plan_setup_workspace(c.plan, c.group);
+    return FX_OK;
+}
+
+// Forks the lanes from st (every lane waits for what st holds so far).
+fx_status fork_lanes(fx_batch* b, int L, hipStream_t st) {
+    FX_TRY_HIP(hipEventRecord(b->fork, st));
+    for (int k = 0; k < L; ++k) FX_TRY_HIP(hipStreamWaitEvent(b->lanes[k], b->fork, 0));
+    return FX_OK;
+}
+
+// Joins the lanes back into st (st waits for everything the lanes hold).
+fx_status join_lanes(fx_batch* b, int L, hipStream_t st) {
+    for (int k = 0; k < L; ++k) {
+        FX_TRY_HIP(hipEventRecord(b->joins[k], b->lanes[k]));
+        FX_TRY_HIP(hipStreamWaitEvent(st, b->joins[k], 0));
     }
     return FX_OK;
+}
+
+// The classes on their lanes: fork from st, one lane per class (classes beyond the lane count share
+// lanes round-robin in issue order), join back into st. With one lane every class runs on st.
+fx_status run_all(fx_batch* b, const void* const* psi0, void* const* psi_out, void* const* rho_out, hipStream_t st) {
+    if (b->concurrency <= 1) {
+        for (auto& c : b->classes) {
+            fx_status s = run_class(b, c, psi0, psi_out, rho_out, st);
+            if (s != FX_OK) return s;
+        }
+        return FX_OK;
+    }
+    const int L = b->concurrency;
+    fx_status s = fork_lanes(b, L, st);
+    if (s != FX_OK) return s;
+    for (auto& c : b->classes) {
+        s = run_class(b, c, psi0, psi_out, rho_out, b->lanes[c.lane % L]);
+        if (s != FX_OK) break;
+    }
+    // join even after a failed enqueue, so that st never runs ahead of work already on the lanes
+    fx_status sj = join_lanes(b, L, st);
+    return s != FX_OK ? s : sj;
 }
 
 void drop_graph(fx_batch* b) {
@@ -174,30 +281,177 @@ void drop_graph(fx_batch* b) {
     b->graph = nullptr;
 }
 
-// Times a group of `count` realizations of class c with tuning t (eager launches, HIP events).
-// Returns ms or -1.
-double time_group(fx_batch* b, fx_batch::Class& c, const Tune& t, size_t count, hipStream_t st) {
-    apply_tune(c.plan, t);
-    plan_setup_workspace(c.plan, (int64_t)count);
-    if (c.plan->ws_need > c.plan->ws_bytes) return -1.0;
-    std::vector<const void*> in(b->n, b->stage_in);
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return -1.0;
-    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return -1.0; }
-    // the staging input doubles as every member's source; outputs are not written (nullptr)
-    double best = -1.0;
-    for (int rep = 0; rep < 2; ++rep) {
-        (void)hipEventRecord(e0, st);
-        fx_status s = run_group(b, c, 0, count, in.data(), nullptr, nullptr, st);
-        (void)hipEventRecord(e1, st);
-        if (s != FX_OK || hipEventSynchronize(e1) != hipSuccess) { best = -1.0; break; }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (rep == 1) best = ms;  // first repetition warms caches and LDS attributes
+struct Timer {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool ok = false;
+    Timer() { ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess; }
+    ~Timer() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+};
+
+// Times one item of class c (G realizations, every q-block) with tuning t; returns ms per
+// realization or -1 when the tuning does not fit (workspace budget, 32-bit indexing) or fails.
+double time_item(fx_batch* b, fx_batch::Class& c, const Tune& t, hipStream_t st) {
+    const int64_t G = t.group;
+    apply_tune(c.plan, t, G);
+    if (!c.plan->index_ok || c.plan->ws_need > c.plan->budget) return -1.0;
+    if (ensure_workspace(c.plan) != FX_OK || ensure_stage(b, c, G) != FX_OK) return -1.0;
+    std::vector<const void*> in(b->n, c.stage);  // the staging tensor doubles as every input
+    Timer tm;
+    double best = -1.0;
+    if (tm.ok) {
+        for (int rep = 0; rep < 2; ++rep) {
+            (void)hipEventRecord(tm.e0, st);
+            fx_status s = run_group(b, c, 0, (size_t)G, in.data(), nullptr, nullptr, st);
+            (void)hipEventRecord(tm.e1, st);
+            if (s != FX_OK || hipEventSynchronize(tm.e1) != hipSuccess) { best = -1.0; break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, tm.e0, tm.e1);
+            if (rep == 1) best = ms / (double)G;  // the first repetition sets LDS attributes, warms caches
+        }
+    }
+    (void)hipGetLastError();
     return best;
+}
+
+// The largest item (<= members) whose workspace fits the budget at the tuning's q-block.
+int64_t largest_group(fx_batch::Class& c, Tune t) {
+    int64_t G = (int64_t)c.members.size();
+    while (G > 1) {
+        apply_tune(c.plan, t, G);
+        if (c.plan->ws_need <= c.plan->budget && c.plan->index_ok) break;
+        G = (G + 1) / 2;
+    }
+    return G;
+}
+
+// The largest item (<= members) whose workspace fits the budget at q-block qb.
+int64_t largest_group_at(fx_batch::Class& c, Tune t, int64_t qb) {
+    t.qblock = qb;
+    return largest_group(c, t);
+}
+
+// Autotuning of one class. First the item shape: the workspace holds G realizations times a
+// q-block of the outermost magnification index, so the candidates are the points of that frontier
+// (for every q-block lam, lam/2, ..., 1 the largest G that fits, and half of it), from one
+// realization with every term in one block (the single-field layout) to many realizations with
+// short blocks. Then coordinate descent over the kernel knobs from the best item shape.
+Tune tune_class(fx_batch* b, fx_batch::Class& c, hipStream_t st) {
+    const int k = c.plan->nact;
+    const int64_t lam_outer = k > 0 ? c.plan->ax[c.plan->act[k - 1]].lam : 1;
+    Tune best;
+    double best_ms = -1.0;
+    auto consider = [&](Tune t) {
+        if (t.group < 1) return;
+        if (best_ms >= 0 && t == best) return;
+        const double ms = time_item(b, c, t, st);
+        if (ms >= 0 && (best_ms < 0 || ms < best_ms * 0.995)) {
+            best_ms = ms;
+            best = t;
+        }
+    };
+    std::vector<int64_t> qbs;
+    for (int64_t qb = lam_outer; qb >= 1; qb = (qb > 1) ? (qb + 1) / 2 : 0) {
+        if (qbs.empty() || qbs.back() != qb) qbs.push_back(qb);
+        if (qb == 1) break;
+    }
+    for (int64_t qb : qbs) {
+        Tune t;
+        t.qblock = qb;
+        t.group = largest_group_at(c, t, qb);
+        apply_tune(c.plan, t, t.group);
+        if (c.plan->nb_outer != qb && qb != lam_outer) continue;  // the budget cut the block: a smaller one follows
+        consider(t);
+        if (t.group > 1) {
+            t.group = (t.group + 1) / 2;
+            consider(t);
+        }
+    }
+    for (int sweep = 0; sweep < 2; ++sweep) {
+        for (bool v : {true, false}) { Tune t = best; t.use_cfp = v; consider(t); }
+        for (int v : {0, 1, 2}) { Tune t = best; t.use_eas = v; consider(t); }
+        for (bool v : {true, false}) { Tune t = best; t.allow_split = v; consider(t); }
+        for (int v : {0, 4}) { Tune t = best; t.persist = v; consider(t); }
+        for (int v : {1024, 2048, 4096}) { Tune t = best; t.ts_target = v; consider(t); }
+    }
+    if (best.group < 1) {
+        best = Tune();
+        best.group = largest_group(c, best);
+    }
+    if (best.qblock == 0) {
+        apply_tune(c.plan, best, best.group);
+        best.qblock = c.plan->nb_outer;
+    }
+    return best;
+}
+
+// ms of one item of every class, one after the other (lanes = 1) or forked over the lanes.
+double time_round(fx_batch* b, int lanes, hipStream_t st) {
+    std::vector<const void*> in(b->n, nullptr);
+    Timer tm;
+    double best = -1.0;
+    if (tm.ok) {
+        for (int rep = 0; rep < 2; ++rep) {
+            (void)hipEventRecord(tm.e0, st);
+            fx_status s = lanes > 1 ? fork_lanes(b, lanes, st) : FX_OK;
+            for (auto& c : b->classes) {
+                if (s != FX_OK) break;
+                for (size_t i = 0; i < in.size(); ++i) in[i] = c.stage;
+                s = run_group(b, c, 0, (size_t)c.group, in.data(), nullptr, nullptr,
+                              lanes > 1 ? b->lanes[c.lane % lanes] : st);
+            }
+            if (lanes > 1) (void)join_lanes(b, lanes, st);
+            (void)hipEventRecord(tm.e1, st);
+            if (s != FX_OK || hipEventSynchronize(tm.e1) != hipSuccess) { best = -1.0; break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, tm.e0, tm.e1);
+            if (rep == 1) best = ms;
+        }
+    }
+    (void)hipGetLastError();
+    return best;
+}
+
+// Every output range (psi_out[i], rho_out[i]) must be disjoint from every other output range and
+// from every input; inputs may be shared between realizations. Sort-and-sweep over the ranges.
+fx_status check_batch_disjoint(const fx_batch* b, const void* const* psi0, void* const* psi_out,
+                               void* const* rho_out) {
+    struct Range { uintptr_t lo, hi; int member; };
+    std::vector<Range> outs, ins;
+    const size_t cs = cbytes(b);
+    std::vector<int64_t> M(b->n, 0);
+    for (const auto& c : b->classes)
+        for (int m : c.members) M[m] = c.plan->M;
+    for (int i = 0; i < b->n; ++i) {
+        const size_t cb = (size_t)M[i] * cs;
+        ins.push_back({(uintptr_t)psi0[i], (uintptr_t)psi0[i] + cb, i});
+        if (psi_out && psi_out[i]) outs.push_back({(uintptr_t)psi_out[i], (uintptr_t)psi_out[i] + cb, i});
+        if (rho_out && rho_out[i]) outs.push_back({(uintptr_t)rho_out[i], (uintptr_t)rho_out[i] + cb / 2, i});
+    }
+    auto by_lo = [](const Range& x, const Range& y) { return x.lo < y.lo; };
+    std::sort(outs.begin(), outs.end(), by_lo);
+    for (size_t k = 1; k < outs.size(); ++k)
+        if (outs[k].lo < outs[k - 1].hi) {
+            set_error("output buffers of realizations " + std::to_string(outs[k - 1].member) + " and " +
+                      std::to_string(outs[k].member) + " overlap");
+            return FX_EINVAL;
+        }
+    for (const Range& r : ins) {
+        // outputs are sorted and disjoint, so their ends ascend too: the last output starting below
+        // r.hi has the largest end of all outputs that could reach into r
+        auto it = std::lower_bound(outs.begin(), outs.end(), Range{r.hi, 0, 0}, by_lo);
+        if (it != outs.begin()) {
+            const Range& o = *(it - 1);
+            if (o.hi > r.lo) {
+                set_error("input of realization " + std::to_string(r.member) + " overlaps an output of realization " +
+                          std::to_string(o.member));
+                return FX_EINVAL;
+            }
+        }
+    }
+    return FX_OK;
 }
 
 }  // namespace
@@ -239,76 +493,64 @@ fx_status fx_batch_create(const fx_problem* probs, int32_t n, fx_batch** out) {
         c.members.push_back(i);
         b->classes.push_back(c);
     }
-    // group sizes: as many realizations per group as fit the plan's workspace budget
-    const size_t cs = cbytes(b);
-    size_t stage_elems = 0;
-    for (auto& c : b->classes) {
-        int64_t G = (int64_t)c.members.size();
-        while (G > 1) {
-            plan_setup_workspace(c.plan, G);
-            if (c.plan->ws_need <= c.plan->budget) break;
-            G = (G + 1) / 2;
+    // issue order: largest classes first (terms x points x members)
+    for (auto& c : b->classes) c.cost = (double)c.plan->Q * (double)c.plan->M * (double)c.members.size();
+    std::stable_sort(b->classes.begin(), b->classes.end(),
+                     [](const fx_batch::Class& x, const fx_batch::Class& y) { return x.cost > y.cost; });
+    const int ncls = (int)b->classes.size();
+    for (int k = 0; k < ncls; ++k) b->classes[k].lane = k;
+    b->lanes.assign(ncls, nullptr);
+    b->joins.assign(ncls, nullptr);
+    for (int k = 0; k < ncls; ++k) {
+        if (hipStreamCreateWithFlags(&b->lanes[k], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->joins[k], hipEventDisableTiming) != hipSuccess) {
+            set_error("creating the batch lanes failed");
+            fx_batch_destroy(b);
+            return FX_EDEVICE;
         }
-        c.group = G;
-        plan_setup_workspace(c.plan, G);
-        c.plan->nb_fixed = c.plan->nb_outer;
-        fx_status s = ensure_workspace(c.plan);
-        if (s != FX_OK) { fx_batch_destroy(b); return s; }
-        stage_elems = std::max(stage_elems, (size_t)(G * c.plan->M));
     }
-    if (hipMalloc(&b->stage_in, stage_elems * cs) != hipSuccess) {
-        (void)hipGetLastError();
-        set_error("hipMalloc of batch staging failed");
+    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
+        set_error("creating the batch lanes failed");
         fx_batch_destroy(b);
-        return FX_ENOMEM;
+        return FX_EDEVICE;
     }
-    b->stage_bytes = stage_elems * cs;
-    if (hipMemset(b->stage_in, 0, b->stage_bytes) != hipSuccess) { fx_batch_destroy(b); return FX_EDEVICE; }
-    // autotune per class (eager runs), then keep the winner
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_cache();
     const bool tune = std::getenv("FX_NO_AUTOTUNE") == nullptr;
     hipStream_t st = nullptr;
     if (hipStreamCreate(&st) != hipSuccess) { fx_batch_destroy(b); return FX_EDEVICE; }
+    auto fail = [&](fx_status s) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+        fx_batch_destroy(b);
+        return s;
+    };
     bool dirty = false;
+    std::string bkey;
     for (auto& c : b->classes) {
-        const std::string key = class_key(c.plan->prob, c.group);
+        const std::string key = class_key(c.plan->prob, c.members.size());
+        bkey += key + ";";
         auto it = g_tune.find(key);
         Tune best;
         if (it != g_tune.end()) {
             best = it->second;
         } else if (tune) {
-            double best_ms = -1.0;
-            // a few realizations per timing run keep the search short; the choice only concerns
-            // tile shapes and grid sizes, which depend on the lattice, not on the group size
-            const size_t tune_count = (size_t)std::min<int64_t>(c.group, 2);
-            const int ts_c[] = {1024, 2048, 4096};
-            const int pe_c[] = {0, 4};
-            const bool sp_c[] = {true, false};
-            for (int ts : ts_c)
-                for (int pe : pe_c)
-                    for (bool sp : sp_c) {
-                        Tune t;
-                        t.ts_target = ts;
-                        t.persist = pe;
-                        t.allow_split = sp;
-                        const double ms = time_group(b, c, t, tune_count, st);
-                        if (ms >= 0 && (best_ms < 0 || ms < best_ms)) {
-                            best_ms = ms;
-                            best = t;
-                        }
-                    }
+            best = tune_class(b, c, st);
             g_tune[key] = best;
             dirty = true;
+        } else {
+            best.group = largest_group(c, best);
         }
+        if (best.group < 1) best.group = 1;
         c.tune = best;
-        apply_tune(c.plan, best);
-        plan_setup_workspace(c.plan, c.group);
+        c.group = best.group;
+        apply_tune(c.plan, best, c.group);
         fx_status s = ensure_workspace(c.plan);
-        if (s != FX_OK) { (void)hipStreamDestroy(st); fx_batch_destroy(b); return s; }
-        // eager runs (full group and the last partial one) so that every kernel the graph will hold
+        if (s == FX_OK) s = ensure_stage(b, c, c.group);
+        if (s != FX_OK) return fail(s);
+        // eager runs (a full item and the last partial one) so that every kernel the graph will hold
         // has been launched once before any capture
-        std::vector<const void*> in(n, b->stage_in);
+        std::vector<const void*> in(n, c.stage);
         s = run_group(b, c, 0, (size_t)c.group, in.data(), nullptr, nullptr, st);
         const size_t rem = c.members.size() % (size_t)c.group;
         if (s == FX_OK && rem) {
@@ -316,13 +558,28 @@ fx_status fx_batch_create(const fx_problem* probs, int32_t n, fx_batch** out) {
             s = run_group(b, c, 0, rem, in.data(), nullptr, nullptr, st);
             plan_setup_workspace(c.plan, c.group);
         }
-        if (s != FX_OK) { (void)hipStreamDestroy(st); fx_batch_destroy(b); return s; }
+        if (s != FX_OK) return fail(s);
     }
+    // lane concurrency: every class on its own lane, or all on the caller's stream
+    b->concurrency = 1;
+    if (ncls > 1) {
+        auto it = g_conc.find(bkey);
+        if (it != g_conc.end()) {
+            b->concurrency = std::min(it->second, ncls);
+        } else if (tune) {
+            const double t1 = time_round(b, 1, st);
+            const double tn = time_round(b, ncls, st);
+            b->concurrency = (tn >= 0 && (t1 < 0 || tn < t1)) ? ncls : 1;
+            g_conc[bkey] = b->concurrency;
+            dirty = true;
+        } else {
+            b->concurrency = ncls;
+        }
+    }
+    if (const char* e = std::getenv("FX_BATCH_LANES")) b->concurrency = std::max(1, std::min(ncls, std::atoi(e)));
     if (hipStreamSynchronize(st) != hipSuccess) {
         set_error("batch set-up run failed");
-        (void)hipStreamDestroy(st);
-        fx_batch_destroy(b);
-        return FX_EDEVICE;
+        return fail(FX_EDEVICE);
     }
     (void)hipStreamDestroy(st);
     if (dirty) save_tune_cache();
@@ -333,8 +590,15 @@ fx_status fx_batch_create(const fx_problem* probs, int32_t n, fx_batch** out) {
 fx_status fx_batch_destroy(fx_batch* b) {
     if (!b) return FX_OK;
     drop_graph(b);
-    for (auto& c : b->classes) fx_plan_destroy(c.plan);
-    if (b->stage_in) (void)hipFree(b->stage_in);
+    for (auto& c : b->classes) {
+        fx_plan_destroy(c.plan);
+        if (c.stage) (void)hipFree(c.stage);
+    }
+    for (hipStream_t s : b->lanes)
+        if (s) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : b->joins)
+        if (e) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
     delete b;
     return FX_OK;
 }
@@ -350,8 +614,14 @@ fx_status fx_batch_run(fx_batch* b, const void* const* psi0, void* const* psi_ou
         const bool has_rho = rho_out && rho_out[i];
         if (!has_psi && !has_rho) { set_error("realization without any output"); return FX_EINVAL; }
     }
+    fx_status ov = check_batch_disjoint(b, psi0, psi_out, rho_out);
+    if (ov != FX_OK) return ov;
     hipStream_t st = (hipStream_t)stream;
-    if (st == nullptr || std::getenv("FX_NO_GRAPH")) return run_all(b, psi0, psi_out, rho_out, st);
+    bool timing = false;
+    for (auto& c : b->classes) timing = timing || c.plan->timing;
+    // per-pass timing records events around every launch, which a captured graph would not replay:
+    // such runs (and runs on the legacy default stream, which cannot be captured) go out eagerly
+    if (st == nullptr || timing || std::getenv("FX_NO_GRAPH")) return run_all(b, psi0, psi_out, rho_out, st);
     std::vector<const void*> in(psi0, psi0 + b->n);
     std::vector<void*> o(b->n, nullptr), r(b->n, nullptr);
     for (int i = 0; i < b->n; ++i) {
@@ -361,7 +631,6 @@ fx_status fx_batch_run(fx_batch* b, const void* const* psi0, void* const* psi_ou
     const bool same = b->exec && st == b->g_stream && in == b->g_in && o == b->g_out && r == b->g_rho;
     if (!same) {
         drop_graph(b);
-        for (auto& c : b->classes) c.plan->timing = false;
         FX_TRY_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         fx_status s = run_all(b, psi0, psi_out, rho_out, st);
         hipGraph_t g = nullptr;
@@ -382,6 +651,32 @@ fx_status fx_batch_run(fx_batch* b, const void* const* psi0, void* const* psi_ou
         b->g_rho = r;
     }
     FX_TRY_HIP(hipGraphLaunch(b->exec, st));
+    return FX_OK;
+}
+
+fx_status fx_batch_num_classes(const fx_batch* b, int32_t* n) {
+    if (!b || !n) { set_error("NULL argument"); return FX_EINVAL; }
+    *n = (int32_t)b->classes.size();
+    return FX_OK;
+}
+
+fx_status fx_batch_class(fx_batch* b, int32_t i, fx_plan** plan, int32_t* members, int64_t* group,
+                         int32_t* lane) {
+    if (!b) { set_error("batch is NULL"); return FX_EINVAL; }
+    if (i < 0 || i >= (int32_t)b->classes.size()) { set_error("class index out of range"); return FX_EINVAL; }
+    const auto& c = b->classes[i];
+    if (plan) *plan = c.plan;
+    if (members) *members = (int32_t)c.members.size();
+    if (group) *group = c.group;
+    if (lane) *lane = b->concurrency > 1 ? c.lane % b->concurrency : 0;
+    return FX_OK;
+}
+
+fx_status fx_batch_class_members(const fx_batch* b, int32_t i, int32_t* members, int32_t max) {
+    if (!b || !members) { set_error("NULL argument"); return FX_EINVAL; }
+    if (i < 0 || i >= (int32_t)b->classes.size()) { set_error("class index out of range"); return FX_EINVAL; }
+    const auto& c = b->classes[i];
+    for (int32_t k = 0; k < max && k < (int32_t)c.members.size(); ++k) members[k] = c.members[k];
     return FX_OK;
 }
 

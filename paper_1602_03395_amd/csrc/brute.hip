@@ -235,6 +235,12 @@ extern "C" fx_status fx_brute_force(fx_plan* p, const void* psi0, void* psi_out,
     fx_status s = check_ptr(psi0, "psi0");
     if (s != FX_OK) return s;
     if (!psi_out && !rho_out) { set_error("psi_out and rho_out are both NULL"); return FX_EINVAL; }
+    {
+        const size_t cb = (size_t)p->M * csize(p);
+        if ((s = check_disjoint(psi0, cb, "psi0", psi_out, cb, "psi_out")) != FX_OK) return s;
+        if ((s = check_disjoint(psi0, cb, "psi0", rho_out, cb / 2, "rho_out")) != FX_OK) return s;
+        if ((s = check_disjoint(psi_out, cb, "psi_out", rho_out, cb / 2, "rho_out")) != FX_OK) return s;
+    }
     for (int pa = 0; pa < 3; ++pa)
         if (p->spectrum[pa]) {
             set_error("the brute-force comparator is built for the free-particle spectrum only");

@@ -172,6 +172,12 @@ extern "C" fx_status fx_far_field(fx_plan* p, const void* psi0, void* amp_out, v
     if (s != FX_OK) return s;
     if (!amp_out && !rho_out) { set_error("amp_out and rho_out are both NULL"); return FX_EINVAL; }
     if (p->prob.t_flight == 0.0) { set_error("the far-field estimate needs t_flight != 0"); return FX_EINVAL; }
+    {
+        const size_t cb = (size_t)p->M * csize(p);
+        if ((s = check_disjoint(psi0, cb, "psi0", amp_out, cb, "amp_out")) != FX_OK) return s;
+        if ((s = check_disjoint(psi0, cb, "psi0", rho_out, cb / 2, "rho_out")) != FX_OK) return s;
+        if ((s = check_disjoint(amp_out, cb, "amp_out", rho_out, cb / 2, "rho_out")) != FX_OK) return s;
+    }
     for (int pa = 0; pa < 3; ++pa)
         if (p->spectrum[pa]) {
             set_error("the far-field estimate is defined for the free-particle spectrum only");

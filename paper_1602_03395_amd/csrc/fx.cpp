@@ -387,20 +387,34 @@ void workspace_layout(const fx_plan* p, int64_t slices, int64_t* nb_out, int64_t
     if (p->schedule == FX_SCHED_PAPER) {
         if (p->nb_fixed > 0) nb = std::min<int64_t>(p->nb_fixed, outer_lam);
         else
-            while (nb > 1 && (size_t)need(nb) * 2 * cs > p->budget) nb = (nb + 1) / 2;
+            while (nb > 1 && ((size_t)need(nb) * 2 * cs > p->budget || need(nb) >= kIndexLimit)) nb = (nb + 1) / 2;
     }
     *nb_out = std::max<int64_t>(1, nb);
     *buf_out = need(*nb_out);
     *need_out = (size_t)(2 * *buf_out + slices * p->M) * cs + 1024;
 }
 
+// The kernels decode tiles, groups and grid positions in 32-bit arithmetic: every pass tensor
+// (input, intermediates, output) must stay below kIndexLimit elements. Checked here, before any
+// launch, so that an oversized layout fails as a whole instead of after some passes ran.
+static bool layout_indexes_in_32_bits(const fx_plan* p) {
+    if (p->slices * p->M >= kIndexLimit) return false;
+    return p->buf_elems < kIndexLimit;
+}
+
 fx_status plan_setup_workspace(fx_plan* p, int64_t slices) {
     p->slices = slices;
     workspace_layout(p, slices, &p->nb_outer, &p->buf_elems, &p->ws_need);
+    p->index_ok = layout_indexes_in_32_bits(p);
     return FX_OK;
 }
 
 fx_status ensure_workspace(fx_plan* p) {
+    if (!p->index_ok) {
+        set_error("a pass tensor of this problem (times its batch) reaches 2^31 elements, beyond the "
+                  "kernels' 32-bit tile and grid indexing");
+        return FX_EUNSUPPORTED;
+    }
     if (p->ws && p->ws_bytes >= p->ws_need) return FX_OK;
     if (p->ws && !p->ws_owned) {
         set_error("caller workspace smaller than this call needs (fx_plan_workspace_size, "
@@ -497,6 +511,33 @@ fx_status run_box(fx_plan* p, const int qb[3], const int qn[3], const void* src,
 fx_status check_ptr(const void* ptr, const char* what) {
     if (!ptr) {
         set_error(std::string(what) + " is NULL");
+        return FX_EINVAL;
+    }
+    return FX_OK;
+}
+
+// Fields per chunk of a stacked call: the largest chunk (<= count) whose pass layout indexes in
+// 32 bits and whose workspace fits the plan's budget, or the caller's workspace when one was set.
+// Leaves the plan set up for that chunk.
+int64_t stack_chunk(fx_plan* p, int64_t count, size_t extra_bytes_per_field) {
+    const bool caller_ws = p->ws && !p->ws_owned;
+    const size_t cap = caller_ws ? p->ws_bytes : p->budget;
+    int64_t c = count;
+    while (c > 1) {
+        plan_setup_workspace(p, c);
+        if (p->index_ok && p->ws_need + (size_t)c * extra_bytes_per_field <= cap) break;
+        c = (c + 1) / 2;
+    }
+    plan_setup_workspace(p, c);
+    return c;
+}
+
+
+fx_status check_disjoint(const void* a, size_t na, const char* an, const void* b, size_t nb, const char* bn) {
+    if (!a || !b || na == 0 || nb == 0) return FX_OK;
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    if (a0 < b0 + nb && b0 < a0 + na) {
+        set_error(std::string(an) + " and " + bn + " overlap; inputs and outputs must be disjoint");
         return FX_EINVAL;
     }
     return FX_OK;
@@ -734,11 +775,41 @@ fx_status fx_expand(fx_plan* p, const void* psi0, void* psi_out, void* rho_out, 
     fx_status s = check_ptr(psi0, "psi0");
     if (s != FX_OK) return s;
     if (!psi_out && !rho_out) { set_error("psi_out and rho_out are both NULL"); return FX_EINVAL; }
+    const size_t cb = (size_t)p->M * csize(p), rb = cb / 2;
+    if ((s = check_disjoint(psi0, cb, "psi0", psi_out, cb, "psi_out")) != FX_OK) return s;
+    if ((s = check_disjoint(psi0, cb, "psi0", rho_out, rb, "rho_out")) != FX_OK) return s;
+    if ((s = check_disjoint(psi_out, cb, "psi_out", rho_out, rb, "rho_out")) != FX_OK) return s;
     if (p->slices != 1) plan_setup_workspace(p, 1);
     if ((s = ensure_workspace(p)) != FX_OK) return s;
     void* dst = psi_out ? psi_out : (char*)p->ws + (size_t)2 * p->buf_elems * csize(p);
     int qb[3] = {0, 0, 0}, qn[3] = {p->ax[0].lam, p->ax[1].lam, p->ax[2].lam};
     return run_box(p, qb, qn, psi0, dst, 0, rho_out, false, (hipStream_t)stream);
+}
+
+
+fx_status fx_expand_many(fx_plan* p, int64_t count, const void* psi0, void* psi_out, void* rho_out, void* stream) {
+    if (!p) { set_error("plan is NULL"); return FX_EINVAL; }
+    if (count < 1) { set_error("count must be >= 1"); return FX_EINVAL; }
+    fx_status s = check_ptr(psi0, "psi0");
+    if (s != FX_OK) return s;
+    if (!psi_out && !rho_out) { set_error("psi_out and rho_out are both NULL"); return FX_EINVAL; }
+    const size_t cb = (size_t)p->M * csize(p), rb = cb / 2;
+    if ((s = check_disjoint(psi0, count * cb, "psi0", psi_out, count * cb, "psi_out")) != FX_OK) return s;
+    if ((s = check_disjoint(psi0, count * cb, "psi0", rho_out, count * rb, "rho_out")) != FX_OK) return s;
+    if ((s = check_disjoint(psi_out, count * cb, "psi_out", rho_out, count * rb, "rho_out")) != FX_OK) return s;
+    const int64_t chunk = stack_chunk(p, count, 0);
+    if ((s = ensure_workspace(p)) != FX_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    int qb[3] = {0, 0, 0}, qn[3] = {p->ax[0].lam, p->ax[1].lam, p->ax[2].lam};
+    for (int64_t f = 0; f < count; f += chunk) {
+        const int64_t c = std::min(chunk, count - f);
+        if (c != p->slices) plan_setup_workspace(p, c);  // the last, shorter chunk needs less
+        const char* src = (const char*)psi0 + (size_t)f * cb;
+        void* dst = psi_out ? (char*)psi_out + (size_t)f * cb : (char*)p->ws + (size_t)2 * p->buf_elems * csize(p);
+        void* rho = rho_out ? (char*)rho_out + (size_t)f * rb : nullptr;
+        if ((s = run_box(p, qb, qn, src, dst, 0, rho, false, st)) != FX_OK) return s;
+    }
+    return FX_OK;
 }
 
 fx_status fx_expand_range(fx_plan* p, const void* psi0, void* psi_acc, int64_t q_begin, int64_t q_end,
@@ -749,6 +820,8 @@ fx_status fx_expand_range(fx_plan* p, const void* psi0, void* psi_acc, int64_t q
     if ((s = check_ptr(psi_acc, "psi_acc")) != FX_OK) return s;
     if (q_begin < 0 || q_end < q_begin || q_end > p->Q) { set_error("need 0 <= q_begin <= q_end <= terms"); return FX_EINVAL; }
     if (p->schedule != FX_SCHED_PAPER) { set_error("term ranges exist only for the paper schedule"); return FX_EUNSUPPORTED; }
+    if ((s = check_disjoint(psi0, (size_t)p->M * csize(p), "psi0", psi_acc, (size_t)p->M * csize(p), "psi_acc")) != FX_OK)
+        return s;
     if (p->slices != 1) plan_setup_workspace(p, 1);
     if ((s = ensure_workspace(p)) != FX_OK) return s;
     hipStream_t st = (hipStream_t)stream;
@@ -827,6 +900,8 @@ fx_status fx_density(fx_plan* p, const void* psi, void* rho, void* stream) {
     fx_status s = check_ptr(psi, "psi");
     if (s != FX_OK) return s;
     if ((s = check_ptr(rho, "rho")) != FX_OK) return s;
+    if ((s = check_disjoint(psi, (size_t)p->M * csize(p), "psi", rho, (size_t)p->M * csize(p) / 2, "rho")) != FX_OK)
+        return s;
     if (launch_density(p->dbl, psi, rho, p->M, (hipStream_t)stream) != hipSuccess) {
         set_error("density launch failed");
         return FX_EDEVICE;
@@ -845,6 +920,8 @@ fx_status fx_column_density(fx_plan* p, const void* rho, int axis, void* image, 
     for (int i = 0; i < pa; ++i) A *= p->len[i];
     for (int i = pa + 1; i < 3; ++i) S *= p->len[i];
     const double w = (double)p->par[pa].lam * p->par[pa].dx;
+    const size_t rs = csize(p) / 2;
+    if ((s = check_disjoint(rho, (size_t)p->M * rs, "rho", image, (size_t)(A * S) * rs, "image")) != FX_OK) return s;
     if (launch_column(p->dbl, rho, image, A, p->len[pa], S, w, (hipStream_t)stream) != hipSuccess) {
         set_error("column density launch failed");
         return FX_EDEVICE;
@@ -857,6 +934,9 @@ fx_status fx_expand_adjoint(fx_plan* p, const void* grad_out, void* grad_in, voi
     fx_status s = check_ptr(grad_out, "grad_psi_out");
     if (s != FX_OK) return s;
     if ((s = check_ptr(grad_in, "grad_psi0")) != FX_OK) return s;
+    if ((s = check_disjoint(grad_out, (size_t)p->M * csize(p), "grad_psi_out", grad_in, (size_t)p->M * csize(p),
+                            "grad_psi0")) != FX_OK)
+        return s;
     if (p->slices != 1) plan_setup_workspace(p, 1);
     if ((s = ensure_workspace(p)) != FX_OK) return s;
     int qb[3] = {0, 0, 0}, qn[3] = {p->ax[0].lam, p->ax[1].lam, p->ax[2].lam};
@@ -896,6 +976,40 @@ fx_status fx_plan_pass_times(fx_plan* p, int32_t* n_passes, int64_t* launches, d
     return FX_OK;
 }
 
+namespace {
+
+// The kernel family launch_pass / launch_pass_aa dispatch an op to (same order of tests).
+const char* kernel_of(const fx_plan* p, const Op& o) {
+    const AxisDev& ax = p->ax[o.axis];
+    const PassGeom& g = o.g;
+    switch (o.kind) {
+        case Kind::AA: return aar_applicable(ax.g, p->ax[o.axis2].g, ax.P, p->ax[o.axis2].P, o.aa) ? "k_AAR" : "k_AA";
+        case Kind::AAH: return "k_AAHR";
+        default: break;
+    }
+    if (o.kind == Kind::EA && g.eas) return "k_EAS";
+    if (g.qc > 0 && o.kind == Kind::EH) return "k_EHR";
+    if (o.kind == Kind::EH && g.eh2) return "k_EH2";
+    if (g.qc > 0) return o.kind == Kind::E ? "k_ER" : "k_EAR";
+    const bool a = o.kind == Kind::A, ah = o.kind == Kind::AH;
+    if ((a || ah) && g.reg_a && g.Qin * g.A * (int64_t)ax.P * g.S * 8 < (int64_t(1) << 31))
+        return ax.g <= 8 ? (a ? "k_ASR" : "k_AHR") : (a ? "k_ASK" : "k_AHK");
+    if (p2_applicable(o.kind, ax.M) && g.TS == p2_tile_lines(ax.M)) return o.kind == Kind::E ? "k_E2" : "k_EA2";
+    if (ct_applicable(o.kind, ax.M) && g.TS == ct_tile_lines(ax.M)) return o.kind == Kind::E ? "k_Ect" : "k_EAct";
+    switch (o.kind) {
+        case Kind::E: return "k_E";
+        case Kind::EA: return "k_EA";
+        case Kind::EH: return "k_EH";
+        case Kind::EAH: return "k_EAH";
+        case Kind::AH: return "k_AH";
+        case Kind::A:
+            return (ax.g >= 4 && g.Qin * g.A * (int64_t)ax.P * g.S < (int64_t(1) << 31)) ? "k_AS" : "k_A";
+        default: return "?";
+    }
+}
+
+}  // namespace
+
 fx_status fx_plan_describe(const fx_plan* p, char* buf, size_t len) {
     if (!p || !buf || len == 0) { set_error("NULL argument"); return FX_EINVAL; }
     int qb[3] = {0, 0, 0}, qn[3] = {p->ax[0].lam, p->ax[1].lam, p->ax[2].lam};
@@ -905,7 +1019,8 @@ fx_status fx_plan_describe(const fx_plan* p, char* buf, size_t len) {
     s += "\",\"precision\":\"";
     s += p->dbl ? "c128" : "c64_phase64";
     s += "\",\"terms\":" + std::to_string(p->Q) + ",\"outer_block\":" + std::to_string(p->nb_outer) +
-         ",\"workspace_bytes\":" + std::to_string(p->ws_need) + ",\"spectrum\":[";
+         ",\"slices\":" + std::to_string(p->slices) + ",\"workspace_bytes\":" + std::to_string(p->ws_need) +
+         ",\"spectrum\":[";
     for (int j = 0; j < p->ndim; ++j) {
         s += j ? "," : "";
         s += p->spectrum[3 - p->ndim + j] ? "\"table\"" : "\"free\"";
@@ -925,6 +1040,7 @@ fx_status fx_plan_describe(const fx_plan* p, char* buf, size_t len) {
                       (long long)o.g.Qin, (long long)o.g.A, (long long)o.g.S, o.g.TS,
                       (o.g.qc > 0 || o.g.reg_a || o.g.eas) ? 1 : 0);
         s += tmp;
+        s += std::string(",\"kernel\":\"") + kernel_of(p, o) + "\"";
         if (o.g.eas) s += ",\"eas\":1";
         if (o.g.eh2) s += ",\"eh2\":1";
         if (o.kind == Kind::AA || o.kind == Kind::AAH) {

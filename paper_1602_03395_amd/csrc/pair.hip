@@ -86,6 +86,19 @@ fx_status fx_expand_pair(fx_plan* p, const void* psi, const void* psi_plus, void
     if (s != FX_OK) return s;
     if ((s = check_ptr(psi_plus, "psi_plus")) != FX_OK) return s;
     if (!psi_out && !psi_plus_out && !n_out) { set_error("every output is NULL"); return FX_EINVAL; }
+    {
+        const size_t cb = (size_t)p->M * csize(p);
+        const void* ins[2] = {psi, psi_plus};
+        const char* in_names[2] = {"psi", "psi_plus"};
+        const void* outs[3] = {psi_out, psi_plus_out, n_out};
+        const char* out_names[3] = {"psi_out", "psi_plus_out", "n_out"};
+        for (int o = 0; o < 3; ++o) {
+            for (int i = 0; i < 2; ++i)
+                if ((s = check_disjoint(ins[i], cb, in_names[i], outs[o], cb, out_names[o])) != FX_OK) return s;
+            for (int o2 = o + 1; o2 < 3; ++o2)
+                if ((s = check_disjoint(outs[o], cb, out_names[o], outs[o2], cb, out_names[o2])) != FX_OK) return s;
+        }
+    }
     if (p->slices != 2) setup_pair(p);  // the single-field entry points reset slices to 1
     if ((s = ensure_workspace(p)) != FX_OK) return s;
     hipStream_t st = (hipStream_t)stream;
@@ -118,6 +131,9 @@ fx_status fx_density_adjoint(fx_plan* p, const void* psibar, const void* grad_rh
     if (s != FX_OK) return s;
     if ((s = check_ptr(grad_rho, "grad_rho")) != FX_OK) return s;
     if ((s = check_ptr(grad_psi0, "grad_psi0")) != FX_OK) return s;
+    const size_t cb = (size_t)p->M * csize(p);
+    if ((s = check_disjoint(psibar, cb, "psibar", grad_psi0, cb, "grad_psi0")) != FX_OK) return s;
+    if ((s = check_disjoint(grad_rho, cb / 2, "grad_rho", grad_psi0, cb, "grad_psi0")) != FX_OK) return s;
     if (p->slices != 1) plan_setup_workspace(p, 1);
     if ((s = ensure_workspace(p)) != FX_OK) return s;
     hipStream_t st = (hipStream_t)stream;
@@ -133,6 +149,43 @@ fx_status fx_density_adjoint(fx_plan* p, const void* psibar, const void* grad_rh
     FX_TRY_HIP(hipGetLastError());
     int qb[3] = {0, 0, 0}, qn[3] = {p->ax[0].lam, p->ax[1].lam, p->ax[2].lam};
     return run_box(p, qb, qn, g, grad_psi0, 0, nullptr, true, st);
+}
+
+fx_status fx_density_adjoint_many(fx_plan* p, int64_t count, const void* psibar, const void* grad_rho,
+                                  void* grad_psi0, void* stream) {
+    if (!p) { set_error("plan is NULL"); return FX_EINVAL; }
+    if (count < 1) { set_error("count must be >= 1"); return FX_EINVAL; }
+    fx_status s = check_ptr(psibar, "psibar");
+    if (s != FX_OK) return s;
+    if ((s = check_ptr(grad_rho, "grad_rho")) != FX_OK) return s;
+    if ((s = check_ptr(grad_psi0, "grad_psi0")) != FX_OK) return s;
+    const size_t cb = (size_t)p->M * csize(p);
+    if ((s = check_disjoint(psibar, count * cb, "psibar", grad_psi0, count * cb, "grad_psi0")) != FX_OK) return s;
+    if ((s = check_disjoint(grad_rho, count * cb / 2, "grad_rho", grad_psi0, count * cb, "grad_psi0")) != FX_OK)
+        return s;
+    const int64_t chunk = stack_chunk(p, count, 0);
+    if ((s = ensure_workspace(p)) != FX_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    int qb[3] = {0, 0, 0}, qn[3] = {p->ax[0].lam, p->ax[1].lam, p->ax[2].lam};
+    for (int64_t f = 0; f < count; f += chunk) {
+        const int64_t c = std::min(chunk, count - f);
+        if (c != p->slices) plan_setup_workspace(p, c);
+        const int64_t n = c * p->M;
+        // 2 grad_rho psibar of the chunk goes to the output staging region (c fields), which the
+        // adjoint passes do not use
+        void* g = (char*)p->ws + (size_t)2 * p->buf_elems * csize(p);
+        const char* pb = (const char*)psibar + (size_t)f * cb;
+        const char* gr = (const char*)grad_rho + (size_t)f * cb / 2;
+        if (p->dbl)
+            hipLaunchKernelGGL(k_density_grad<double>, dim3(blocks_for(n)), dim3(kThreads), 0, st,
+                               (const double2*)pb, (const double*)gr, (double2*)g, n);
+        else
+            hipLaunchKernelGGL(k_density_grad<float>, dim3(blocks_for(n)), dim3(kThreads), 0, st,
+                               (const float2*)pb, (const float*)gr, (float2*)g, n);
+        FX_TRY_HIP(hipGetLastError());
+        if ((s = run_box(p, qb, qn, g, (char*)grad_psi0 + (size_t)f * cb, 0, nullptr, true, st)) != FX_OK) return s;
+    }
+    return FX_OK;
 }
 
 }  // extern "C"

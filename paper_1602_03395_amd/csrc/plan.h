@@ -75,6 +75,7 @@ struct fx_plan {
     int asr_max_g = 64;            // above this the LDS-transform form (k_AS) is used
     int cfp_blocks = 1024;         // register E kernel: target workgroups per launch
     bool use_p2 = true;            // compile-time specialised kernels for power-of-two axes
+    bool index_ok = true;          // every tensor of the current layout indexes in 32 bits (see workspace_layout)
     int persist = 0;               // >0: tile passes run as persistent grids of persist x CUs workgroups
     size_t budget = 0;
     // per-pass timing
@@ -102,6 +103,11 @@ fx_status run_ops(fx_plan* p, const std::vector<Op>& ops, const void* src, void*
 fx_status run_box(fx_plan* p, const int qb[3], const int qn[3], const void* src, void* dst, int accumulate,
                   void* rho, bool adjoint, hipStream_t st);
 fx_status check_ptr(const void* ptr, const char* what);
+int64_t stack_chunk(fx_plan* p, int64_t count, size_t extra_bytes_per_field);
+// FX_EINVAL when the byte ranges [a, a + na) and [b, b + nb) intersect; a NULL pointer is never checked.
+fx_status check_disjoint(const void* a, size_t na, const char* an, const void* b, size_t nb, const char* bn);
+// Elements below which every pass tensor, tile count and grid size indexes in 32 bits.
+constexpr int64_t kIndexLimit = (int64_t(1) << 31) - (int64_t(1) << 28);
 void bf_release(fx_plan* p);
 
 }  // namespace fx

@@ -1,0 +1,251 @@
+"""Parity of the headline paths at their real sizes, through the C ABI, against the oracle.
+
+* The ragged ensemble (64000 terms per realization, magnification 40, the three
+  3-D shape classes) through ``fx.Batch``, i.e. ``fx_batch_run`` in the launch
+  configuration the benchmark times (tuned work items of several realizations,
+  q-blocks, class lanes, one graph launch): every realization's density against
+  the oracle, the whole field for the first realization of each class and
+  sampled output points (``oracle.expand_points``) for the others; a plain FP64
+  ensemble at the same shapes; graph replays with eager work in between.
+* The 3-D interferometer field (64 x 64 x 1024, magnification (50, 50, 5)) over
+  the whole output field, and its column image (section 6).
+* The fitting workload as configured: 64 fields of 256 x 256, magnification 20,
+  differentiated in one stacked call; gradient of every field against the
+  oracle's, and central finite differences (h = 1e-3) of the FP32 loss.
+"""
+
+import json
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL32_RHO = 1e-5
+TOL64 = 1e-12
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1602_03395_amd as m
+    return m
+
+
+C4_LAM, C4_T, C4_DX = (40, 40, 40), 400.0, (1.0, 1.0, 1.0)
+
+
+def _c4_batch(fx, idx, dtype):
+    fields = workloads.c4_fields_c64(idx, workers=8)
+    if dtype == torch.complex128:
+        fields = [f.astype(np.complex128) for f in fields]
+    psis = [torch.from_numpy(f).cuda() for f in fields]
+    specs = [dict(shape=tuple(f.shape), dx=C4_DX, lam=C4_LAM, t=C4_T) for f in fields]
+    b = fx.Batch(specs, dtype=dtype)
+    return fields, psis, b
+
+
+def _sample_points(shape, n, seed):
+    rng = np.random.default_rng(seed)
+    sh = np.array(shape)
+    centre = np.stack([rng.integers(s // 2 - s // 8, s // 2 + s // 8, size=n) for s in sh], axis=1)
+    anywhere = np.stack([rng.integers(0, s, size=n // 4) for s in sh], axis=1)
+    return np.concatenate([centre, anywhere])
+
+
+def test_c4_ensemble_fp32_batched_against_oracle(fx):
+    idx = list(range(36))  # 12 realizations per shape class
+    say("C4 ensemble FP32: generating", len(idx), "realizations")
+    fields, psis, b = _c4_batch(fx, idx, torch.complex64)
+    classes = b.classes()
+    for c in classes:
+        say(f"  class {c['plan'].shape}: {len(c['members'])} realizations, item of {c['group']}, lane {c['lane']}")
+    # items of several realizations are the batched configuration under test
+    assert any(c["group"] > 1 for c in classes)
+    for c in classes:
+        say("   ", [(p["kind"], p["kernel"]) for p in json.loads(c["plan"].describe())["passes"]])
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        outs, rhos = b.run(psis)
+    torch.cuda.synchronize()
+    rho_np = [r.cpu().numpy().astype(np.float64) for r in rhos]
+    checked = set()
+    for c in classes:
+        first = c["members"][0]
+        say(f"  oracle, full field of realization {first} {fields[first].shape}")
+        ref = oracle.expand(fields[first].astype(np.complex128), C4_DX, 1.0, C4_T, C4_LAM)
+        e = rel(rho_np[first], oracle.density(ref))
+        say(f"  realization {first}: full-field rel L2 rho {e:.2e}")
+        assert e <= TOL32_RHO
+        checked.add(first)
+    for i in idx:
+        if i in checked:
+            continue
+        pts = _sample_points(fields[i].shape, 48, i)
+        ref = oracle.expand_points(fields[i].astype(np.complex128), pts, C4_DX, 1.0, C4_T, C4_LAM)
+        e = rel(rho_np[i][tuple(pts.T)], np.abs(ref) ** 2)
+        assert e <= TOL32_RHO, (i, e)
+    say(f"  {len(idx) - len(checked)} further realizations within {TOL32_RHO} on sampled points")
+    # graph replays, with eager work and synchronisations in between, reproduce the first run exactly
+    first_rho = [r.clone() for r in rhos]
+    for rep in range(3):
+        scratch = torch.randn(1 << 20, device="cuda")
+        scratch.mul_(2.0)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            b.run(psis, psi_outs=outs, rho_outs=rhos)
+        torch.cuda.synchronize()
+        for a, r in zip(first_rho, rhos):
+            assert torch.equal(a, r)
+
+
+def test_c4_ensemble_fp64_batched_against_oracle(fx):
+    idx = list(range(9))  # 3 realizations per class
+    say("C4 ensemble FP64")
+    fields, psis, b = _c4_batch(fx, idx, torch.complex128)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        outs, rhos = b.run(psis)
+    torch.cuda.synchronize()
+    for c in b.classes():
+        first = c["members"][0]
+        ref = oracle.expand(fields[first], C4_DX, 1.0, C4_T, C4_LAM)
+        e = rel(outs[first].cpu().numpy(), ref)
+        er = rel(rhos[first].cpu().numpy(), oracle.density(ref))
+        say(f"  realization {first} {fields[first].shape}: rel L2 psi {e:.2e} rho {er:.2e}")
+        assert e <= TOL64 and er <= TOL64
+        for i in c["members"][1:]:
+            pts = _sample_points(fields[i].shape, 24, 100 + i)
+            refp = oracle.expand_points(fields[i], pts, C4_DX, 1.0, C4_T, C4_LAM)
+            assert rel(outs[i].cpu().numpy()[tuple(pts.T)], refp) <= TOL64
+
+
+def test_c3_full_field_and_column_image(fx):
+    wl = workloads.make_c3()
+    f32 = wl.fields[0].astype(np.complex64)
+    say("C3 full field: GPU")
+    psi = torch.from_numpy(f32).cuda()
+    plan = fx.get_plan(psi.shape, wl.dx, 1.0, wl.t, wl.lam, dtype=torch.complex64)
+    out, rho = plan.expand(psi)
+    img = plan.column_density(rho, 0)
+    torch.cuda.synchronize()
+    say("C3 full field: oracle")
+    ref = oracle.expand(f32.astype(np.complex128), wl.dx, 1.0, wl.t, wl.lam)
+    rr = oracle.density(ref)
+    e_rho = rel(rho.cpu().numpy().astype(np.float64), rr)
+    e_psi = rel(out.cpu().numpy().astype(np.complex128), ref)
+    e_img = rel(img.cpu().numpy().astype(np.float64), oracle.column_density(rr, 0, wl.lam, wl.dx))
+    say(f"  C3 fp32 full field: rel L2 rho {e_rho:.2e} psi {e_psi:.2e} column image {e_img:.2e}")
+    assert e_rho <= TOL32_RHO and e_img <= TOL32_RHO
+
+
+@pytest.fixture(scope="module")
+def c5(fx):
+    wl = workloads.make_c5()
+    say("C5: oracle targets of the 64 hidden fields")
+    tau = np.stack([oracle.density(oracle.expand(h, wl.dx, 1.0, wl.t, wl.lam)) for h in wl.extra["hidden"]])
+    f32 = np.stack([f.astype(np.complex64) for f in wl.fields])
+    return wl, f32, tau
+
+
+def test_c5_batch_gradient_against_oracle(fx, c5):
+    wl, f32, tau = c5
+    psi = torch.from_numpy(f32).cuda().requires_grad_(True)
+    rho = fx.expand_density(psi, wl.dx, 1.0, wl.t, wl.lam)
+    assert tuple(rho.shape) == f32.shape
+    loss = ((rho - torch.from_numpy(tau.astype(np.float32)).cuda()) ** 2).sum()
+    loss.backward()
+    g = psi.grad.cpu().numpy()
+    say("C5: oracle gradient of the 64 fields")
+    loss_ref = 0.0
+    errs = []
+    for b in range(f32.shape[0]):
+        lb, gb = oracle.loss_and_grad(f32[b].astype(np.complex128), tau[b], wl.dx, 1.0, wl.t, wl.lam)
+        loss_ref += lb
+        errs.append(rel(g[b], gb))
+    say(f"  C5 fp32 batch of 64: loss rel {abs(loss.item() - loss_ref) / loss_ref:.2e}, "
+        f"gradient rel L2 max {max(errs):.2e}")
+    assert max(errs) <= 1e-5
+    assert abs(loss.item() - loss_ref) <= 1e-5 * loss_ref
+
+
+def test_c5_central_finite_differences_fp32(fx, c5):
+    # In FP32 the loss carries a rounding noise of ~1e-7 of rho at every output point, which swamps
+    # the change a step of 1e-3 in one of the 65536 inputs makes; the central difference is therefore
+    # taken along directions that move many inputs at once: d = the adjoint gradient restricted to a
+    # random quarter of the field, normalised. Then (L(x + h d) - L(x - h d)) / 2h must equal
+    # Re <g, d> = |g restricted| to 1e-2 (relative).
+    wl, f32, tau = c5
+    plan = fx.get_plan(f32.shape[1:], wl.dx, 1.0, wl.t, wl.lam, dtype=torch.complex64)
+    b = 5
+    x0 = torch.from_numpy(f32[b]).cuda()
+    tau_b = tau[b]
+
+    def loss_of(x):
+        _, r = plan.expand(x, want_psi=False)
+        d = r.cpu().numpy().astype(np.float64) - tau_b
+        return float((d * d).sum())
+
+    psi = x0.clone().requires_grad_(True)
+    rho = fx.expand_density(psi, wl.dx, 1.0, wl.t, wl.lam)
+    ((rho - torch.from_numpy(tau_b.astype(np.float32)).cuda()) ** 2).sum().backward()
+    g = psi.grad.cpu().numpy().astype(np.complex128)
+    h = 1e-3
+    rng = np.random.default_rng(7)
+    for k in range(3):
+        mask = rng.random(g.shape) < 0.25
+        d = np.where(mask, g, 0)
+        d = d / np.linalg.norm(d)
+        expect = float(np.real(np.vdot(d, g)))  # Re <g, d>, PyTorch's convention dL/dRe + i dL/dIm
+        dt = torch.from_numpy(d.astype(np.complex64)).cuda()
+        fd = (loss_of(x0 + h * dt) - loss_of(x0 - h * dt)) / (2 * h)
+        say(f"  C5 FP32 central difference along direction {k}: fd {fd:.6e} adjoint {expect:.6e}")
+        assert abs(fd - expect) <= 1e-2 * abs(expect)
+
+
+def test_c5_central_finite_differences_fp64_elementwise(fx, c5):
+    # plain FP64 at the fitting shape: element-wise central differences (h = 1e-3) of the largest
+    # gradient components, to 1e-6 relative
+    wl, f32, tau = c5
+    b = 9
+    x0 = torch.from_numpy(f32[b].astype(np.complex128)).cuda()
+    tau_b = tau[b]
+    plan = fx.get_plan(x0.shape, wl.dx, 1.0, wl.t, wl.lam, dtype=torch.complex128)
+
+    def loss_of(x):
+        _, r = plan.expand(x, want_psi=False)
+        d = r.cpu().numpy() - tau_b
+        return float((d * d).sum())
+
+    psi = x0.clone().requires_grad_(True)
+    rho = fx.expand_density(psi, wl.dx, 1.0, wl.t, wl.lam)
+    ((rho - torch.from_numpy(tau_b).cuda()) ** 2).sum().backward()
+    g = psi.grad.cpu().numpy()
+    h = 1e-3
+    for k in np.argsort(np.abs(g).ravel())[::-1][:3]:
+        i = np.unravel_index(k, g.shape)
+        for unit, comp in ((1.0, g[i].real), (1j, g[i].imag)):
+            xp = x0.clone()
+            xm = x0.clone()
+            xp[i] += h * unit
+            xm[i] -= h * unit
+            fd = (loss_of(xp) - loss_of(xm)) / (2 * h)
+            say(f"  C5 FP64 FD at {i} ({'re' if unit == 1.0 else 'im'}): fd {fd:.9e} adjoint {comp:.9e}")
+            assert abs(fd - comp) <= 1e-6 * np.abs(g).max()

@@ -8,6 +8,7 @@ sharing any of the method's code.
 
 from .generators import (  # noqa: F401
     C4_SHAPES,
+    c4_fields_c64,
     WORKLOADS,
     centred_coords,
     random_field,

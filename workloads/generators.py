@@ -191,6 +191,24 @@ def make_c4(n: int = 768, seed: int = 3, members: Optional[Sequence[int]] = None
                     dtype="c64", extra={"members": list(idx)})
 
 
+def _c4_member_c64(args):
+    i, n, seed = args
+    seqs = np.random.SeedSequence(seed).spawn(n)
+    return ensemble_member_3d(C4_SHAPES[i % 3], seqs[i]).astype(np.complex64)
+
+
+def c4_fields_c64(idx: Sequence[int], n: int = 768, seed: int = 3, workers: int = 1) -> List[np.ndarray]:
+    """The complex64 fields of realizations ``idx`` of the ragged ensemble (same values as
+    ``make_c4`` cast to complex64), generated by ``workers`` forked processes. Call it before the
+    process touches the GPU."""
+    jobs = [(int(i), n, seed) for i in idx]
+    if workers <= 1 or len(jobs) < 2:
+        return [_c4_member_c64(j) for j in jobs]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_c4_member_c64, jobs, chunksize=max(1, len(jobs) // (4 * workers)))
+
+
 def make_c5(n: int = 64, seed: int = 4, hidden_seed: int = 5) -> Workload:
     """Batch of 2D 256x256 fields for fitting, magnification 20 per axis; hidden fields give targets."""
     seqs = np.random.SeedSequence(seed).spawn(n)
