@@ -11,6 +11,11 @@
         kernel of known size read (and write) exactly its size; stored under <tag>
         (workload/dtype/schedule) and stamped with the hash of the kernel sources
 
+    python -m paper_1602_03395_amd.profiling traffic-kernels <fetch.csv> <write.csv> <copy_MiB> <out.json> <tag>
+                                                   <kernel=key> ...
+        the same per kernel name (runs whose passes interleave over several streams), stored
+        under the given keys
+
     python -m paper_1602_03395_amd.profiling passes <kernel_trace.csv> <calls>
         markdown table of the average kernel-trace duration of every pass of the schedule (key
         'kind#ordinal' as above; <calls> = expansion calls in the traced run)
@@ -47,6 +52,21 @@ def stats(path: str) -> str:
             short_name(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e6,
             float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
     return "\n".join(out)
+
+
+def copy_counter(path: str, counter: str):
+    """(kernel name, value) of the calibration copy: the largest single dispatch of a copy kernel
+    (other copies in the run, such as uploads of inputs, are smaller)."""
+    best = None
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name") != counter or "copy" not in r["Kernel_Name"].lower():
+            continue
+        v = float(r["Counter_Value"])
+        if best is None or v > best[1]:
+            best = (r["Kernel_Name"], v)
+    if best is None:
+        raise SystemExit("no copy kernel found in the counter file")
+    return best
 
 
 def counters(path: str, counter: str):
@@ -103,25 +123,26 @@ def _per_pass(rows, calls_per_run: int):
 
 
 def traffic(fetch_csv: str, write_csv: str, copy_mib: float, calls: int, out_json: str, tag: str):
-    f_avg, _ = counters(fetch_csv, "FETCH_SIZE")
-    w_avg, _ = counters(write_csv, "WRITE_SIZE")
     copy_kib = copy_mib * 1024.0
-    copies = [k for k in f_avg if "copy" in k.lower()]
-    if not copies:
-        raise SystemExit("no copy kernel found in the counter file")
-    ck = max(copies, key=lambda k: f_avg[k])
-    f_scale = copy_kib / f_avg[ck]
-    w_scale = copy_kib / w_avg[ck] if w_avg.get(ck) else 1.0
+    ck, cf = copy_counter(fetch_csv, "FETCH_SIZE")
+    _, cw = copy_counter(write_csv, "WRITE_SIZE")
+    f_scale = copy_kib / cf
+    w_scale = copy_kib / cw
     fp = _per_pass(_pass_dispatches(fetch_csv, "FETCH_SIZE"), calls)
     wp = _per_pass(_pass_dispatches(write_csv, "WRITE_SIZE"), calls)
     res = {"copy_kernel": short_name(ck), "copy_MiB": copy_mib,
-           "copy_fetch_KiB_counter": f_avg[ck], "copy_write_KiB_counter": w_avg.get(ck),
+           "copy_fetch_KiB_counter": cf, "copy_write_KiB_counter": cw,
            "fetch_scale": f_scale, "write_scale": w_scale, "passes": {}}
     for key, (fv, n) in fp.items():
         fb = fv * 1024.0 * f_scale
         wb = wp.get(key, (0.0, 0))[0] * 1024.0 * w_scale
         res["passes"][key] = {"dispatches": n, "fetch_bytes": fb, "write_bytes": wb,
                               "hbm_bytes_per_launch": fb + wb}
+    _store(out_json, tag, res)
+    return res
+
+
+def _store(out_json: str, tag: str, res: dict):
     doc = {}
     if os.path.exists(out_json):
         try:
@@ -132,6 +153,33 @@ def traffic(fetch_csv: str, write_csv: str, copy_mib: float, calls: int, out_jso
         doc = {"kernels_hash": kernels_hash(), "workloads": {}}
     doc.setdefault("workloads", {})[tag] = res
     json.dump(doc, open(out_json, "w"), indent=1)
+
+
+def traffic_kernels(fetch_csv: str, write_csv: str, copy_mib: float, out_json: str, tag: str, mapping):
+    """As ``traffic``, but per kernel name (for runs whose passes interleave, such as a batch whose
+    classes run on several streams): ``mapping`` is a list of 'short_name=key' (the key under which
+    the bench looks the kernel up, e.g. '64x64x512/EA#0'); bytes are averages per dispatch."""
+    f_avg, f_n = counters(fetch_csv, "FETCH_SIZE")
+    w_avg, _ = counters(write_csv, "WRITE_SIZE")
+    copy_kib = copy_mib * 1024.0
+    ck, cf = copy_counter(fetch_csv, "FETCH_SIZE")
+    _, cw = copy_counter(write_csv, "WRITE_SIZE")
+    f_scale = copy_kib / cf
+    w_scale = copy_kib / cw
+    res = {"copy_kernel": short_name(ck), "copy_MiB": copy_mib,
+           "copy_fetch_KiB_counter": cf, "copy_write_KiB_counter": cw,
+           "fetch_scale": f_scale, "write_scale": w_scale, "passes": {}}
+    by_short = {short_name(k): k for k in f_avg}
+    for item in mapping:
+        name, key = item.split("=", 1)
+        full = by_short.get(name)
+        if full is None:
+            raise SystemExit(f"kernel {name} not in the counter file")
+        fb = f_avg[full] * 1024.0 * f_scale
+        wb = w_avg.get(full, 0.0) * 1024.0 * w_scale
+        res["passes"][key] = {"kernel": name, "dispatches": f_n[full], "fetch_bytes": fb, "write_bytes": wb,
+                              "hbm_bytes_per_launch": fb + wb}
+    _store(out_json, tag, res)
     return res
 
 
@@ -163,5 +211,8 @@ if __name__ == "__main__":
     elif cmd == "traffic":
         print(json.dumps(traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), int(sys.argv[5]), sys.argv[6],
                                  sys.argv[7]), indent=1))
+    elif cmd == "traffic-kernels":
+        print(json.dumps(traffic_kernels(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5], sys.argv[6],
+                                         sys.argv[7:]), indent=1))
     else:
         raise SystemExit(__doc__)
