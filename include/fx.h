@@ -207,6 +207,28 @@ fx_status fx_expand_adjoint(fx_plan* plan, const void* grad_psi_out, void* grad_
 fx_status fx_density_adjoint(fx_plan* plan, const void* psibar, const void* grad_rho, void* grad_psi0,
                              void* stream);
 
+/* Bytes of the fixed scratch array fx_expand_noalloc works in, one per device. */
+#define FX_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc. Same result as fx_expand (same arguments, validation,
+ * overlap checks and outputs), but the intermediates live in a scratch array of
+ * FX_NOALLOC_SCRATCH_BYTES that is part of the library's device image (each device the library
+ * runs on holds its own copy until the process ends) instead of a workspace: the call performs
+ * no hipMalloc, hipFree or other allocation, and ignores any workspace set on the plan. The
+ * outermost magnification index is blocked as much as needed to fit the array; a problem whose
+ * intermediates exceed it even with blocks of one index returns FX_ENOMEM, with the size in
+ * fx_last_error(), before anything is launched. Per-pass timing is not recorded in this call.
+ * The first call on a device resolves the array's address there (a runtime symbol lookup, which
+ * may load the library's device code on that device): make one call, or any other call of the
+ * library, on each device before entering a region that must not allocate. All calls on one
+ * device share its array, so calls that overlap in time on one device (several streams or
+ * threads) race on it and give undefined results; sequential calls need no clearing between
+ * them. Errors: as fx_expand, plus FX_ENOMEM as above.
+ */
+fx_status fx_expand_noalloc(fx_plan* plan, const void* psi0, void* psi_out, void* rho_out, void* stream);
+
 /*
  * Stacks of fields (ensembles of realizations, section 1; batches of fields fitted to images):
  * `count` fields of the plan's shape stored back to back ([count][shape], C order), each

@@ -81,6 +81,7 @@ def _load():
         "fx_column_density": (ctypes.c_int, [vp, vp, ctypes.c_int, vp, vp]),
         "fx_expand_adjoint": (ctypes.c_int, [vp, vp, vp, vp]),
         "fx_density_adjoint": (ctypes.c_int, [vp, vp, vp, vp, vp]),
+        "fx_expand_noalloc": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "fx_expand_many": (ctypes.c_int, [vp, ctypes.c_int64, vp, vp, vp, vp]),
         "fx_density_adjoint_many": (ctypes.c_int, [vp, ctypes.c_int64, vp, vp, vp, vp]),
         "fx_expand_pair": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),

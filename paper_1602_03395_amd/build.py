@@ -17,7 +17,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfx.so")
-SOURCES = ["fx.cpp", "tables.cpp", "batch.cpp", "kernels.hip", "kernels_p2.hip", "kernels_ct.hip", "kernels_cfp.hip", "pair.hip", "farfield.hip", "brute.hip"]
+SOURCES = ["fx.cpp", "tables.cpp", "batch.cpp", "kernels.hip", "kernels_p2.hip", "kernels_ct.hip", "kernels_cfp.hip", "pair.hip", "farfield.hip", "brute.hip", "noalloc.hip"]
 
 
 def hipcc() -> str:

@@ -371,6 +371,11 @@ void to_prec(const std::vector<double>& src, std::vector<unsigned char>& dst, si
 }
 
 void workspace_layout(const fx_plan* p, int64_t slices, int64_t* nb_out, int64_t* buf_out, size_t* need_out) {
+    workspace_layout_for(p, slices, true, nb_out, buf_out, need_out);
+}
+
+void workspace_layout_for(const fx_plan* p, int64_t slices, bool with_adjoint, int64_t* nb_out, int64_t* buf_out,
+                          size_t* need_out) {
     const int k = p->nact;
     int qb[3] = {0, 0, 0}, qn[3];
     for (int i = 0; i < 3; ++i) qn[i] = p->ax[i].lam;
@@ -381,6 +386,7 @@ void workspace_layout(const fx_plan* p, int64_t slices, int64_t* nb_out, int64_t
         int qn2[3] = {qn[0], qn[1], qn[2]};
         if (k > 0 && p->schedule == FX_SCHED_PAPER) qn2[p->act[k - 1]] = (int)nbv;
         std::vector<Op> f = build_ops(p, qb, qn2, slices, false);
+        if (!with_adjoint) return max_intermediate(f);
         std::vector<Op> h = build_ops(p, qb, qn2, slices, true);
         return std::max(max_intermediate(f), max_intermediate(h));
     };

@@ -95,6 +95,9 @@ int64_t max_intermediate(const std::vector<Op>& ops);
 fx_status validate(const fx_problem* pr);
 // Outer block, ping-pong buffer elements and workspace bytes for `slices` leading slices.
 void workspace_layout(const fx_plan* p, int64_t slices, int64_t* nb, int64_t* buf, size_t* need);
+// The same for the forward schedule alone (with_adjoint = false) or both schedules (true).
+void workspace_layout_for(const fx_plan* p, int64_t slices, bool with_adjoint, int64_t* nb, int64_t* buf,
+                          size_t* need);
 fx_status plan_setup_workspace(fx_plan* p, int64_t slices);
 fx_status ensure_workspace(fx_plan* p);
 // slot0: first timing slot of the list (0 forward, FX_ADJOINT_SLOT0 adjoint)
