@@ -86,6 +86,21 @@ def kernels_hash() -> str:
     return kh()
 
 
+def load_traffic_entry(tag: str, kernel_key: str):
+    """The committed counter summary of one pass (dict), or None when it was taken on other kernel
+    sources or another workload."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernels_hash") != kernels_hash():
+        return None
+    return d.get("workloads", {}).get(tag, {}).get("passes", {}).get(kernel_key)
+
+
 def load_traffic(tag: str, kernel_key: str):
     """HBM bytes per launch of one pass from the committed counter summary, or None when it
     was taken on other kernel sources or another workload."""
@@ -260,7 +275,17 @@ def bench_c4(args, fields):
                              "frac": dom["gbs"] / PEAK_HBM_GBS})
         # measured HBM bytes per launch of that kernel (copy-calibrated FETCH_SIZE + WRITE_SIZE), while
         # the committed counters match the kernel sources
-        roofline["traffic"] = load_traffic(f"c4_ragged_ensemble/c64/{args.schedule}", f'{dom["class"]}/{dom["key"]}')
+        ent = load_traffic_entry(f"c4_ragged_ensemble/c64/{args.schedule}", f'{dom["class"]}/{dom["key"]}')
+        if ent:
+            alg = roofline["algorithmic_bytes_per_launch"]
+            if ent.get("group") == dom["group"] and ent.get("q_block") == dom["q_block"]:
+                roofline["traffic"] = ent["hbm_bytes_per_launch"]
+            elif ent.get("traffic_over_algorithmic"):
+                # the tuner chose another item shape than the profiled run: the counters' ratio of
+                # measured to algorithmic bytes, applied to this launch's algorithmic bytes
+                roofline["traffic"] = ent["traffic_over_algorithmic"] * alg
+                roofline["traffic_note"] = (f'scaled from the profiled launch (items of {ent.get("group")} '
+                                            f'realizations, q-block {ent.get("q_block")})')
         result["passes"] = rows
     result["roofline"] = roofline
     del b, psis, outs, rhos
