@@ -53,11 +53,13 @@ struct Tune {
     bool allow_split = true;
     bool use_cfp = true;
     int use_eas = 1;
+    bool use_eaw = true;
     int64_t group = 0;  // realizations per item (0: the largest that fits the workspace budget)
     int64_t qblock = 0; // outermost magnification indices per q-block (0: as the budget allows)
     bool operator==(const Tune& o) const {
         return ts_target == o.ts_target && persist == o.persist && allow_split == o.allow_split &&
-               use_cfp == o.use_cfp && use_eas == o.use_eas && group == o.group && qblock == o.qblock;
+               use_cfp == o.use_cfp && use_eas == o.use_eas && use_eaw == o.use_eaw && group == o.group &&
+               qblock == o.qblock;
     }
 };
 
@@ -84,11 +86,12 @@ void load_tune_cache() {
     while (f >> kind >> key) {
         if (kind == "class") {
             Tune t;
-            int split = 1, cfp = 1;
+            int split = 1, cfp = 1, eaw = 1;
             long long g = 0, qb = 0;
-            if (!(f >> t.ts_target >> t.persist >> split >> cfp >> t.use_eas >> g >> qb)) break;
+            if (!(f >> t.ts_target >> t.persist >> split >> cfp >> t.use_eas >> eaw >> g >> qb)) break;
             t.allow_split = split != 0;
             t.use_cfp = cfp != 0;
+            t.use_eaw = eaw != 0;
             t.group = g;
             t.qblock = qb;
             g_tune[key] = t;
@@ -109,7 +112,7 @@ void save_tune_cache() {
     for (const auto& kv : g_tune)
         f << "class " << kv.first << " " << kv.second.ts_target << " " << kv.second.persist << " "
           << (kv.second.allow_split ? 1 : 0) << " " << (kv.second.use_cfp ? 1 : 0) << " " << kv.second.use_eas << " "
-          << kv.second.group << " " << kv.second.qblock << "\n";
+          << (kv.second.use_eaw ? 1 : 0) << " " << kv.second.group << " " << kv.second.qblock << "\n";
     for (const auto& kv : g_conc) f << "batch " << kv.first << " " << kv.second << "\n";
 }
 
@@ -162,6 +165,7 @@ void apply_tune(fx_plan* p, const Tune& t, int64_t G) {
     p->allow_split = t.allow_split;
     p->use_cfp = t.use_cfp;
     p->use_eas = t.use_eas;
+    p->use_eaw = t.use_eaw;
     p->nb_fixed = t.qblock;
     plan_setup_workspace(p, G);
 }
@@ -371,6 +375,7 @@ Tune tune_class(fx_batch* b, fx_batch::Class& c, hipStream_t st) {
     }
     for (int sweep = 0; sweep < 2; ++sweep) {
         for (bool v : {true, false}) { Tune t = best; t.use_cfp = v; consider(t); }
+        for (bool v : {true, false}) { Tune t = best; t.use_eaw = v; consider(t); }
         for (int v : {0, 1, 2}) { Tune t = best; t.use_eas = v; consider(t); }
         for (bool v : {true, false}) { Tune t = best; t.allow_split = v; consider(t); }
         for (int v : {0, 4}) { Tune t = best; t.persist = v; consider(t); }

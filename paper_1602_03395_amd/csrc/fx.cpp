@@ -161,12 +161,15 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
         g.qn = qn[ax];
         const bool reg_eh = kind == Kind::EH && p->use_cfp && p->ax[ax].HT != nullptr && qn[ax] <= 64 &&
                             ehr_applicable(p->ax[ax].M, p->ax[ax].g);
-        g.eas = kind == Kind::EA && p->use_cfp && p->ax[ax].HTx != nullptr &&
+        g.eaw = kind == Kind::EA && p->use_cfp && p->use_eaw && p->ax[ax].HTx != nullptr &&
+                eaw_applicable(p->dbl, p->ax[ax].M, p->ax[ax].g, qn[ax]);
+        g.eas = !g.eaw && kind == Kind::EA && p->use_cfp && p->ax[ax].HTx != nullptr &&
                 (p->use_eas == 2 || (p->use_eas == 1 && p->ax[ax].P >= 8 && p->ax[ax].g <= 16)) &&
                 eas_applicable(p->dbl, p->ax[ax].M, p->ax[ax].g, qn[ax]);
-        const bool reg = !g.eas && (use_cfp(p, kind, p->ax[ax]) || reg_eh);
+        const bool reg = !g.eas && !g.eaw && (use_cfp(p, kind, p->ax[ax]) || reg_eh);
         g.eh2 = kind == Kind::EH && !reg_eh && p->use_eh2 && eh2_applicable(p->ax[ax].M, p->ax[ax].P);
-        g.TS = g.eas ? eas_tile_lines(p->ax[ax].g)
+        g.TS = g.eaw ? eaw_tile_lines()
+               : g.eas ? eas_tile_lines(p->ax[ax].g)
                      : reg_eh ? ehr_tile_lines(p->ax[ax].g)
                               : reg ? cfp_tile_lines(p->ax[ax].g) : choose_ts(p, kind, p->ax[ax].M, g.A, g.S);
         auto set_tiles = [&]() {
@@ -696,6 +699,7 @@ fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_pla
     if (const char* e = std::getenv("FX_AA")) p->use_aa = (e[0] == '1') ? 2 : 0;
     if (const char* e = std::getenv("FX_EAS")) p->use_eas = (e[0] == '1') ? 2 : 1;
     if (std::getenv("FX_NO_EAS")) p->use_eas = 0;
+    if (std::getenv("FX_NO_EAW")) p->use_eaw = false;
     if (std::getenv("FX_NO_EH2")) p->use_eh2 = false;
     if (const char* e = std::getenv("FX_ASR_MAXG")) p->asr_max_g = std::max(1, std::atoi(e));
     p->cfp_blocks = 2 * num_cus();
@@ -993,6 +997,7 @@ const char* kernel_of(const fx_plan* p, const Op& o) {
         case Kind::AAH: return "k_AAHR";
         default: break;
     }
+    if (o.kind == Kind::EA && g.eaw) return "k_EAW";
     if (o.kind == Kind::EA && g.eas) return "k_EAS";
     if (g.qc > 0 && o.kind == Kind::EH) return "k_EHR";
     if (o.kind == Kind::EH && g.eh2) return "k_EH2";
@@ -1044,10 +1049,10 @@ fx_status fx_plan_describe(const fx_plan* p, char* buf, size_t len) {
                       "\"A\":%lld,\"S\":%lld,\"TS\":%d,\"reg\":%d",
                       i ? "," : "", names[(int)o.kind], o.axis - (3 - p->ndim), a.M, a.P, a.lam, o.g.qn,
                       (long long)o.g.Qin, (long long)o.g.A, (long long)o.g.S, o.g.TS,
-                      (o.g.qc > 0 || o.g.reg_a || o.g.eas) ? 1 : 0);
+                      (o.g.qc > 0 || o.g.reg_a || o.g.eas || o.g.eaw) ? 1 : 0);
         s += tmp;
         s += std::string(",\"kernel\":\"") + kernel_of(p, o) + "\"";
-        if (o.g.eas) s += ",\"eas\":1";
+        if (o.g.eas || o.g.eaw) s += ",\"eas\":1";
         if (o.g.eh2) s += ",\"eh2\":1";
         if (o.kind == Kind::AA || o.kind == Kind::AAH) {
             const AxisDev& b = p->ax[o.axis2];

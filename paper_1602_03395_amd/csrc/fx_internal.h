@@ -65,6 +65,7 @@ struct PassGeom {
     int qc = 0;        // > 0: register E kernel, magnification indices per workgroup
     bool reg_a = false;  // A pass: register structured accumulate
     bool eas = false;    // EA pass: waves share the terms of 64 / g lines, structured accumulate
+    bool eaw = false;    // EA pass (g = 8): one wave per tile of 8 lines, every term, structured accumulate
     bool eh2 = false;    // EH pass: compile-time power-of-two kernel, one output line per workgroup
 };
 
@@ -158,6 +159,12 @@ hipError_t launch_pass_aa(bool dbl, const void* in, void* out, const AxisDev& au
 bool eas_applicable(bool dbl, int M, int g, int qn);
 int eas_tile_lines(int g);
 hipError_t launch_pass_eas(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
+                           void* rho, hipStream_t st);
+// EA in register form with the structured accumulate for g = 8 and P in {2, 3, 4, 6, 8}: one wave
+// per tile of 8 lines running every term, the partial sums over q mod 8 in registers.
+bool eaw_applicable(bool dbl, int M, int g, int qn);
+int eaw_tile_lines();
+hipError_t launch_pass_eaw(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
                            void* rho, hipStream_t st);
 // Adjoint of E in register form (power-of-two P <= g <= 64, P <= 16): 64 / g lines per workgroup.
 bool ehr_applicable(int M, int g);

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <mutex>
 #include <set>
 
@@ -1911,6 +1912,223 @@ hipError_t launch_asr_T(const void* in, void* out, const AxisDev& ax, const Pass
     }
 }
 
+// EA with the structured accumulate for g = 8, one wavefront per tile of 8 lines (P = M / 8 in
+// {2, 3, 4, 6, 8}). Each wave works alone on its tile and runs every term of the pass: lane
+// (l, n2) keeps its P inputs x[8 i + n2] in registers, forms E_q for each term q as the register E
+// kernel does and, as lane u = n2 < P holding E_q[u], adds Tf_q[n0] E_q[u] into the partial sum
+// H[j], j = (q - qb) mod 8, of its output group n0 (r(n0) = u). The terms run j by j (q = qb + j,
+// qb + j + 8, ...), so the running sum is one register and each finished H[j] goes to its slot of
+// the lane's register array once per j. After the last term the lane applies the 8-point inverse
+// transform of the structured accumulate (presf):
+//   out[n0 + P c] = exp(2 pi i qb c / 8) sum_j exp(2 pi i j c / 8) H[j],   c < 8,
+// and writes its 8 outputs. The sum over the 8 lanes of a line and the P-point inverse are, for a
+// power-of-two P, the butterfly reduce-scatter and the cross-lane inverse of the register E kernel;
+// for P = 3 and 6 every lane applies the P-point inverse to its own HT-weighted values, pads them
+// to 8 and the lanes' results are added by the select form of the reduce-scatter (lane n2 ends
+// with value bitrev3(n2)). There is no workgroup barrier after the table rows of the pass (TA, HT,
+// Tf) are staged in LDS, once per workgroup of a persistent grid.
+constexpr int kEwWaves = 8;
+constexpr size_t kEwStageBytes = 32768;  // HT rows of the pass staged when they fit
+
+template <typename T, int P, bool HST>
+__global__ __launch_bounds__(kEwWaves * kWave) void k_EAW(const C<T>* __restrict__ in, C<T>* __restrict__ out,
+                                                         AxisDev ax, PassGeom g, int accumulate,
+                                                         T* __restrict__ rho, const C<T>* __restrict__ TA,
+                                                         const C<T>* __restrict__ HT) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int G = 8;
+    constexpr int M = G * P;
+    constexpr bool P2 = kPow2<P>;
+    constexpr int LP = (P >= 8) ? 3 : (P >= 4) ? 2 : (P >= 2) ? 1 : 0;
+    const int qn = g.qn;
+    C<T>* TAs = (C<T>*)smem;         // [q - qb][i] = TA_q[8 i]
+    C<T>* Tfs = TAs + qn * P;        // [q - qb][n0] = Tf_q[n0]
+    C<T>* Hst = Tfs + qn * P;        // [q - qb][r][n2] (HST)
+    const int tid = (int)threadIdx.x;
+    const int w = tid / kWave;
+    const int lane = tid % kWave;
+    const int l = lane / G;
+    const int n2 = lane % G;
+    const C<T>* Tf = (const C<T>*)ax.Tf;
+    for (int e = tid; e < qn * P; e += kEwWaves * kWave) {
+        const int qq = e / P, i = e % P;
+        TAs[e] = TA[(int64_t)(g.qb + qq) * M + G * i];
+        Tfs[e] = Tf[(int64_t)(g.qb + qq) * M + i];
+    }
+    if constexpr (HST) {
+        const C<T>* hsrc = HT + (int64_t)g.qb * M;
+        for (int e = tid; e < qn * M; e += kEwWaves * kWave) Hst[e] = hsrc[e];
+    }
+    __syncthreads();
+    // lane constants: the cross-lane inverse (power-of-two P), the lane's output group, the
+    // exp(2 pi i qb c / 8) of the final transform
+    const bool odd_flip = P2 && (n2 & 1);
+    C<T> wst[LP > 0 ? LP : 1];
+    C<T> fin = mk<T>(1, 0);
+    if constexpr (P2) fin = lane_twiddles_x<T, LP>(wst, n2, (const C<T>*)ax.tw, M);
+    // the value u of E_q the lane holds: n2 mod P after the cross-lane inverse (power-of-two P);
+    // after the padded reduce-scatter (P = 3, 6), bitrev3(n2), valid below P
+    const int br = ((n2 & 1) << 2) | (n2 & 2) | ((n2 >> 2) & 1);
+    const int u = P2 ? n2 % P : (br < P ? br : 0);
+    const bool holds = P2 ? n2 < P : br < P;
+    const int n0u = (int)((u * ax.lg_inv) % P);
+    const C<T>* tw = (const C<T>*)ax.tw;  // exp(-2 pi i k / M); k = P m gives exp(-2 pi i m / 8)
+    const int qbr = g.qb % G;
+    C<T> ctw[G];
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+        const C<T> t = tw[((qbr * c) % G) * P];
+        ctw[c] = mk<T>(t.x, -t.y);
+    }
+    // tiles: each wave is a worker; the waves of a workgroup take consecutive tiles and every XCD
+    // (workgroup id mod 8) a contiguous range, so neighbouring strided tiles share one L2
+    const int64_t ntl = g.Qin * g.ntiles;  // < 2^31 (host check)
+    const int64_t units = (ntl + kEwWaves - 1) / kEwWaves;
+    const int64_t U8 = (units + 7) / 8;
+    for (int64_t bid = blockIdx.x; bid < 8 * U8; bid += gridDim.x) {
+        const int64_t unit = (bid & 7) * U8 + (bid >> 3);
+        const int64_t tile = unit * kEwWaves + w;
+        if (unit >= units || tile >= ntl) continue;  // uniform over the wave
+        const int64_t qi = (int64_t)((unsigned)tile / (unsigned)g.ntiles);
+        const int64_t tt = tile - qi * g.ntiles;
+        const Tile tl = decode_tile(g, tt);
+        const bool live = l < tl.nl;
+        C<T> x[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const int n = G * i + n2;
+            const int64_t off = (g.S == 1) ? ((qi * g.A + tl.a0 + l) * M + n)
+                                           : (((qi * g.A + tl.a0) * M + n) * g.S + tl.s0 + l);
+            x[i] = live ? in[off] : mk<T>(0, 0);
+        }
+        if (odd_flip) {
+#pragma unroll
+            for (int i = 1; i < P; i += 2) x[i] = mk<T>(-x[i].x, -x[i].y);
+        }
+        C<T> hj[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) hj[j] = mk<T>(0, 0);
+        // FP32: the chains of slots j and j + 1 run together, two terms (q, q + 1) per iteration, so
+        // their sequences of cross-lane steps are independent and interleave; FP64 keeps one term
+        // per iteration, as two would not fit the registers of four waves per SIMD
+        constexpr bool PAIR = sizeof(T) == 4;
+        constexpr int JS = PAIR ? 2 : 1;
+#pragma unroll 1
+        for (int j = 0; j < G; j += JS) {
+            C<T> acca = mk<T>(0, 0), accb = mk<T>(0, 0);
+            for (int qq = j; qq < qn; qq += G) {
+                const bool two = PAIR && qq + 1 < qn;
+                const int qb2 = two ? qq + 1 : qq;
+                C<T> va[P], vb[P];
+                const C<T>* ta = TAs + qq * P;
+                const C<T>* tb2 = TAs + qb2 * P;
+                const C<T>* ha = (HST ? Hst + qq * M : HT + (int64_t)(g.qb + qq) * M) + n2;
+                const C<T>* hb = (HST ? Hst + qb2 * M : HT + (int64_t)(g.qb + qb2) * M) + n2;
+#pragma unroll
+                for (int i = 0; i < P; ++i) va[i] = cmul<T>(x[i], ta[i]);
+                RegDFT<T, P, false>::run(va);
+#pragma unroll
+                for (int r = 0; r < P; ++r) va[r] = cmul<T>(va[r], ha[r * G]);
+                if constexpr (PAIR) {
+#pragma unroll
+                    for (int i = 0; i < P; ++i) vb[i] = cmul<T>(x[i], tb2[i]);
+                    RegDFT<T, P, false>::run(vb);
+#pragma unroll
+                    for (int r = 0; r < P; ++r) vb[r] = cmul<T>(vb[r], hb[r * G]);
+                }
+                C<T> sa, sb = mk<T>(0, 0);
+                if constexpr (P2) {
+                    reduce_scatter_x<T, P>(va, n2, 3);
+                    sa = va[0];
+#pragma unroll
+                    for (int s = LP; s < 3; ++s) sa = cadd<T>(sa, shfl_xor_c<T>(sa, 1 << s));
+                    sa = lane_idft_x<T, LP>(sa, wst, fin);  // lane n2 now holds E_q[n2 mod P]
+                    if constexpr (PAIR) {
+                        reduce_scatter_x<T, P>(vb, n2, 3);
+                        sb = vb[0];
+#pragma unroll
+                        for (int s = LP; s < 3; ++s) sb = cadd<T>(sb, shfl_xor_c<T>(sb, 1 << s));
+                        sb = lane_idft_x<T, LP>(sb, wst, fin);
+                    }
+                } else {
+                    // the P values padded to 8 and summed over the 8 lanes by the select form of the
+                    // reduce-scatter: lane n2 ends with the sum of value bitrev3(n2)
+                    RegDFT<T, P, true>::run(va);
+                    C<T> wa[G];
+#pragma unroll
+                    for (int k = 0; k < G; ++k) wa[k] = k < P ? va[k] : mk<T>(0, 0);
+                    reduce_step<T, G, 0>(wa, n2, 3);
+                    sa = wa[0];
+                    if constexpr (PAIR) {
+                        RegDFT<T, P, true>::run(vb);
+                        C<T> wb[G];
+#pragma unroll
+                        for (int k = 0; k < G; ++k) wb[k] = k < P ? vb[k] : mk<T>(0, 0);
+                        reduce_step<T, G, 0>(wb, n2, 3);
+                        sb = wb[0];
+                    }
+                }
+                acca = cfma<T>(acca, Tfs[qq * P + n0u], sa);
+                if (two) accb = cfma<T>(accb, Tfs[qb2 * P + n0u], sb);
+            }
+#pragma unroll
+            for (int jj = 0; jj < G; jj += JS)
+                if (jj == j) {
+                    hj[jj] = acca;
+                    if constexpr (PAIR) hj[jj + 1] = accb;
+                }
+        }
+        // the 8-point inverse over j of the output group (l, n0u); lanes n2 >= P hold copies
+        RegDFT<T, G, true>::run(hj);
+        if (live && holds) {
+#pragma unroll
+            for (int c = 0; c < G; ++c) {
+                C<T> v = cmul<T>(hj[c], ctw[c]);
+                const int nb = n0u + P * c;
+                const int64_t off = (g.S == 1) ? ((qi * g.A + tl.a0 + l) * M + nb)
+                                               : (((qi * g.A + tl.a0) * M + nb) * g.S + tl.s0 + l);
+                if (accumulate) v = cadd<T>(v, out[off]);
+                out[off] = v;
+                if (rho) rho[off] = v.x * v.x + v.y * v.y;
+            }
+        }
+    }
+}
+
+template <typename T, int P>
+hipError_t launch_eaw(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
+                      hipStream_t st) {
+    const size_t stage = (size_t)g.qn * ax.M * sizeof(C<T>);
+    const bool hst = stage <= kEwStageBytes;
+    // P = 3, 6: the padded reduce-scatter unless FX_EAW_TRANSPOSE=1 selects the LDS transpose
+    const size_t lds = ((size_t)2 * g.qn * P + (hst ? (size_t)g.qn * ax.M : 0)) * sizeof(C<T>);
+    const int64_t units = (g.Qin * g.ntiles + kEwWaves - 1) / kEwWaves;
+    int64_t blocks = (units + 7) / 8 * 8;
+    const int64_t cap = (int64_t)(2 * cu_count() + 7) / 8 * 8;  // persistent: the staged rows are reused
+    if (blocks > cap) blocks = cap;
+    if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = (g.max_blocks + 7) / 8 * 8;
+    auto k = hst ? k_EAW<T, P, true> : k_EAW<T, P, false>;
+    hipError_t e = prep_lds((const void*)k, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kEwWaves * kWave), lds, st,
+                       (const C<T>*)in, (C<T>*)out, ax, g, accumulate, (T*)rho, (const C<T>*)ax.TA,
+                       (const C<T>*)ax.HTx);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_eaw_T(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
+                        hipStream_t st) {
+    switch (ax.P) {
+        case 2: return launch_eaw<T, 2>(in, out, ax, g, accumulate, rho, st);
+        case 3: return launch_eaw<T, 3>(in, out, ax, g, accumulate, rho, st);
+        case 4: return launch_eaw<T, 4>(in, out, ax, g, accumulate, rho, st);
+        case 6: return launch_eaw<T, 6>(in, out, ax, g, accumulate, rho, st);
+        case 8: return launch_eaw<T, 8>(in, out, ax, g, accumulate, rho, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
 
 // g <= 8: one thread per group (k_ASR); g = 16, 32, 64: K = g / 8 lanes per group (k_ASK).
@@ -2022,6 +2240,24 @@ hipError_t launch_pass_eas(bool dbl, const void* in, void* out, const AxisDev& a
     if (g.Qin * g.ntiles >= (int64_t(1) << 31)) return hipErrorInvalidValue;
     return dbl ? launch_eas_T<double>(in, out, ax, g, accumulate, rho, st)
                : launch_eas_T<float>(in, out, ax, g, accumulate, rho, st);
+}
+
+bool eaw_applicable(bool dbl, int M, int g, int qn) {
+    if (g != 8 || M % 8 != 0 || qn < 1) return false;
+    const int P = M / 8;
+    if (!(P == 2 || P == 3 || P == 4 || P == 6 || P == 8)) return false;
+    const size_t cs = dbl ? 16 : 8;
+    return (size_t)2 * qn * P * cs <= (size_t)lds_limit_bytes();
+}
+
+int eaw_tile_lines() { return 8; }
+
+hipError_t launch_pass_eaw(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
+                           void* rho, hipStream_t st) {
+    if (!eaw_applicable(dbl, ax.M, ax.g, g.qn) || !ax.HTx || g.TS != eaw_tile_lines()) return hipErrorInvalidValue;
+    if (g.Qin * g.ntiles >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    return dbl ? launch_eaw_T<double>(in, out, ax, g, accumulate, rho, st)
+               : launch_eaw_T<float>(in, out, ax, g, accumulate, rho, st);
 }
 
 bool ehr_applicable(int M, int g) {

@@ -72,6 +72,8 @@ struct fx_plan {
                                    // are dominated by the per-wave overheads; its table-row traffic
                                    // per line grows as g^2 / 64 times the line's output), 2 wherever
                                    // it applies (FX_EAS=1)
+    bool use_eaw = true;           // EA for g = 8 through the one-wave-per-tile structured kernel
+                                   // (FX_NO_EAW disables)
     int asr_max_g = 64;            // above this the LDS-transform form (k_AS) is used
     int cfp_blocks = 1024;         // register E kernel: target workgroups per launch
     bool use_p2 = true;            // compile-time specialised kernels for power-of-two axes

@@ -167,6 +167,7 @@ def test_adjoint_matches_oracle(fx, shape, lam, schedule):
 def test_structured_ea_matches_oracle(fx, shape, lam, dtype, monkeypatch):
     import json
     monkeypatch.setenv("FX_EAS", "1")  # wherever it applies (by default only for P >= 8)
+    monkeypatch.setenv("FX_NO_EAW", "1")  # g = 8 would otherwise take the one-wave-per-tile kernel
     say("structured EA", shape, lam, dtype)
     dx = tuple(0.9 for _ in shape)
     psi_np = workloads.random_field(shape, 81)
