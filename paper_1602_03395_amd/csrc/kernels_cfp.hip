@@ -608,6 +608,24 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
                 }
             } else {
                 RegDFT<T, P, true>::run(v);
+                if constexpr (!kPow2<P> && P < 8) {
+                    if (lgG == 3) {
+                        // g = 8: the values padded to 8 and summed by the select form of the
+                        // reduce-scatter; lane n2 ends with value bitrev3(n2) and writes it
+                        C<T> w8[8];
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) w8[k] = k < P ? v[k] : mk<T>(0, 0);
+                        reduce_step<T, 8, 0>(w8, n2, 3);
+                        const int uu = ((n2 & 1) << 2) | (n2 & 2) | ((n2 >> 2) & 1);
+                        if (live && uu < P) {
+                            const int64_t qo = qi * g.qn + (q - g.qb);
+                            const int64_t off = (g.S == 1) ? ((qo * g.A + tl.a0 + l) * P + uu)
+                                                           : (((qo * g.A + tl.a0) * P + uu) * g.S + tl.s0 + l);
+                            out[off] = w8[0];
+                        }
+                        continue;
+                    }
+                }
                 if constexpr (!kPow2<P>) {
                     // all-reduce; lane n2 writes the values u = n2 mod G
                     reduce_all<T, P>(v, lgG);
