@@ -205,8 +205,13 @@ def _calibration_copy(mib, dev):
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
+    # two strided gathers of the same source (rows of 512 bytes, the first 256 / 64 bytes of each): they
+    # check the copy's scale factors on partial-line reads like those of the strided line passes
+    rows = src.view(-1, 128)
+    half = rows[:, :64].contiguous()
+    eighth = rows[:, :16].contiguous()
     torch.cuda.synchronize()
-    del src, dst
+    del src, dst, half, eighth
 
 
 def bench_c4(args, fields):
@@ -407,17 +412,22 @@ def main():
         wl = workloads.make_c4(members=[args.member])
     else:
         wl = workloads.make_workload(args.config)
-    if args.config == "c5":
-        wl.fields = wl.fields[:1]
     dtype_name = args.dtype or wl.dtype
     dtype = torch.complex64 if dtype_name == "c64" else torch.complex128
-    field = wl.fields[0].astype(np.complex64 if dtype_name == "c64" else np.complex128)
+    npdt = np.complex64 if dtype_name == "c64" else np.complex128
+    field = wl.fields[0].astype(npdt)
     dx, lam, t = wl.dx, wl.lam, wl.t
+    # the fitting workload is a stack of fields expanded (and differentiated) in one call
+    stacked = args.config == "c5"
+    if stacked and args.variant not in ("free", "grad"):
+        print(json.dumps({"error": "the stacked fitting workload runs the free or grad variant only"}), flush=True)
+        sys.exit(2)
 
     dev = torch.device("cuda:0")
     if args.calibrate_copy_mb > 0:
         _calibration_copy(args.calibrate_copy_mb, dev)
     psi = torch.from_numpy(field).to(dev)
+    stack = torch.from_numpy(np.stack([f.astype(npdt) for f in wl.fields])).to(dev) if stacked else None
     spectrum = None
     if args.variant == "spectrum":
         # per-axis Bogoliubov-like spectrum omega = sqrt(eps (eps + 2 mu)), eps = k^2 / 2m
@@ -443,6 +453,21 @@ def main():
     elif args.variant == "brute_force":
         def step():
             return plan.brute_force(psi)
+    elif stacked:
+        # the whole stack per step: its expansion, and with the grad variant the gradient of the
+        # fitting loss L = sum (rho - tau)^2 of every field (tau: fixed synthetic images, here the
+        # densities of the hidden fields on the input lattice; the timing does not depend on them)
+        sout = torch.empty_like(stack)
+        srho = torch.empty(stack.shape, dtype=rho.dtype, device=dev)
+        tau = torch.from_numpy(np.stack([np.abs(h) ** 2 for h in wl.extra["hidden"]])).to(dev, rho.dtype)
+        sgrad_rho = torch.empty_like(srho)
+        sgrad = torch.empty_like(stack)
+
+        def step():
+            plan.expand_many(stack, psi_out=sout, rho_out=srho)
+            if args.variant == "grad":
+                torch.sub(srho, tau, out=sgrad_rho).mul_(2.0)
+                plan.density_adjoint_many(sout, sgrad_rho, grad_in=sgrad)
     elif args.variant == "grad":
         # one forward + backward of the fitting loss L = sum (rho - tau)^2 (tau: a fixed synthetic image)
         tau = torch.full(psi.shape, 1e-6, dtype=rho.dtype, device=dev)
@@ -489,8 +514,10 @@ def main():
         passes = plan.pass_times()
         plan.set_timing(False)
 
+    if stacked:
+        desc = json.loads(plan.describe())  # the pass layout of the stacked call (fields as slices)
     ms_per_step = gpu_ms / args.steps
-    npts = int(np.prod(psi.shape))
+    npts = int(np.prod(psi.shape)) * (int(stack.shape[0]) if stacked else 1)
     value = npts / (ms_per_step * 1e-3)
     terms = plan.num_terms()
 
@@ -554,7 +581,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if dtype == torch.complex64 else "f64",
         "data": "synthetic",
-        "config": {"workload": wl.name, "shape": list(psi.shape), "lam": list(lam), "dx": list(dx), "t": t,
+        "config": {"workload": wl.name, "shape": list(psi.shape), "fields": int(stack.shape[0]) if stacked else 1,
+                   "lam": list(lam), "dx": list(dx), "t": t,
                    "terms": terms, "schedule": args.schedule, "variant": args.variant,
                    "precision": "c64_phase64" if dtype == torch.complex64 else "c128",
                    "outer_block": desc["outer_block"]},
@@ -567,7 +595,9 @@ def main():
     if not args.no_cpu_baseline and args.variant == "free":
         ref, ref_rho, cb = cpu_baseline(wl, field, lam, dx, t)
         result["cpu_baseline"] = cb
-        got = rho.cpu().numpy().astype(np.float64)
+        got = (srho[0] if stacked else rho).cpu().numpy().astype(np.float64)
+        if stacked:
+            out = sout[0]
         result["rel_l2_rho_vs_oracle"] = float(np.linalg.norm(got - ref_rho) / np.linalg.norm(ref_rho))
         result["rel_l2_psi_vs_oracle"] = float(np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref))
     else:

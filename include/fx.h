@@ -56,7 +56,9 @@ typedef enum fx_status {
     FX_EINVAL = -1,        /* invalid argument (shape, lambda, dx, t, pointers, ...) */
     FX_ENOMEM = -2,        /* device or host allocation failed, or workspace too small */
     FX_EDEVICE = -3,       /* a HIP runtime call or kernel launch failed */
-    FX_EUNSUPPORTED = -4   /* valid problem outside what this library supports (e.g. too long an axis) */
+    FX_EUNSUPPORTED = -4,  /* valid problem outside what this library supports (e.g. too long an axis) */
+    FX_STATUS_RANGE_ = 0x7fffffff  /* not a status: makes every 32-bit value a valid fx_status, so that
+                                      fx_status_string may be handed any int */
 } fx_status;
 
 typedef enum fx_precision {

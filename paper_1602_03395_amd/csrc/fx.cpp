@@ -1082,6 +1082,7 @@ const char* fx_status_string(fx_status s) {
         case FX_ENOMEM: return "FX_ENOMEM: out of memory or workspace too small";
         case FX_EDEVICE: return "FX_EDEVICE: HIP runtime or kernel error";
         case FX_EUNSUPPORTED: return "FX_EUNSUPPORTED: outside what this library supports";
+        default: break;
     }
     return "unknown fx_status";
 }

@@ -155,6 +155,34 @@ def _store(out_json: str, tag: str, res: dict):
     json.dump(doc, open(out_json, "w"), indent=1)
 
 
+def strided_calibration(fetch_csv: str, write_csv: str, copy_mib: float, f_scale: float, w_scale: float):
+    """Check of the copy factors on partial-line reads: the benchmark's calibration follows the plain
+    copy with two strided gathers of the same source, viewed as rows of 512 bytes, keeping the first
+    256 bytes of every row, then the first 64 (the first two copy dispatches that are not runtime
+    blits, in dispatch order). Returns raw and scaled counters against the bytes each gather moves."""
+    def gathers(path, counter):
+        rows = []
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"]
+            if r.get("Counter_Name") != counter or "copy" not in name.lower() or "rocclr" in name.lower():
+                continue
+            rows.append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+        rows.sort()
+        return [v for _, v in rows[:2]]
+
+    fg, wg = gathers(fetch_csv, "FETCH_SIZE"), gathers(write_csv, "WRITE_SIZE")
+    out = []
+    for i, (frac, run) in enumerate(((0.5, 256), (0.125, 64))):
+        if i >= len(fg) or i >= len(wg):
+            break
+        kib = copy_mib * 1024.0 * frac
+        out.append({"run_bytes": run, "row_bytes": 512, "moved_KiB_each_way": kib,
+                    "fetch_KiB_counter": fg[i], "write_KiB_counter": wg[i],
+                    "fetch_scaled_over_moved": fg[i] * f_scale / kib,
+                    "write_scaled_over_moved": wg[i] * w_scale / kib})
+    return out
+
+
 def traffic_kernels(fetch_csv: str, write_csv: str, copy_mib: float, out_json: str, tag: str, mapping):
     """As ``traffic``, but per kernel name (for runs whose passes interleave, such as a batch whose
     classes run on several streams): ``mapping`` is a list of 'short_name=key' (the key under which
@@ -168,7 +196,8 @@ def traffic_kernels(fetch_csv: str, write_csv: str, copy_mib: float, out_json: s
     w_scale = copy_kib / cw
     res = {"copy_kernel": short_name(ck), "copy_MiB": copy_mib,
            "copy_fetch_KiB_counter": cf, "copy_write_KiB_counter": cw,
-           "fetch_scale": f_scale, "write_scale": w_scale, "passes": {}}
+           "fetch_scale": f_scale, "write_scale": w_scale,
+           "strided_check": strided_calibration(fetch_csv, write_csv, copy_mib, f_scale, w_scale), "passes": {}}
     by_short = {short_name(k): k for k in f_avg}
     for item in mapping:
         name, key = item.split("=", 1)
@@ -177,7 +206,8 @@ def traffic_kernels(fetch_csv: str, write_csv: str, copy_mib: float, out_json: s
             raise SystemExit(f"kernel {name} not in the counter file")
         fb = f_avg[full] * 1024.0 * f_scale
         wb = w_avg.get(full, 0.0) * 1024.0 * w_scale
-        res["passes"][key] = {"kernel": name, "dispatches": f_n[full], "fetch_bytes": fb, "write_bytes": wb,
+        res["passes"][key] = {"kernel": name, "dispatches": f_n[full], "fetch_KiB_counter": f_avg[full],
+                              "write_KiB_counter": w_avg.get(full, 0.0), "fetch_bytes": fb, "write_bytes": wb,
                               "hbm_bytes_per_launch": fb + wb}
     _store(out_json, tag, res)
     return res
