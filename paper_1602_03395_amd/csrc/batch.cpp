@@ -20,15 +20,17 @@
 // run. Inside a class the transform passes run as persistent grids where the
 // tuner finds that faster.
 //
-// Autotuning (per class, at batch creation, coordinate descent from the
-// defaults): the realizations per item G and the q-block, the transform family
-// (register-resident lane transforms or LDS Stockham radix-8/4/2 stages), the
-// fused or split structured accumulate, the LDS tile size and persistent grids;
-// each candidate runs one full item eagerly, timed with HIP events, and the
-// choice with the best time per realization is kept. Then the lane concurrency
-// (all classes in parallel, or one after the other) is timed on one item of
-// every class. Results are cached per process and, with FX_AUTOTUNE_CACHE=<file>,
-// on disk.
+// Autotuning (per class, at batch creation): first the item shape, over the
+// frontier of realizations per item G against the q-block that the workspace
+// budget allows; then coordinate descent from the best shape over the transform
+// family (register-resident lane transforms or LDS Stockham radix-8/4/2 stages),
+// the fused (one wave per tile, or eight waves sharing the terms) or split
+// structured accumulate, the LDS tile size and persistent grids. Each candidate
+// runs one full item eagerly three times, timed with HIP events, and the best of
+// the last two runs per realization counts. Then the lane concurrency (all
+// classes in parallel, or one after the other) is decided on whole runs of the
+// batch, alternating between the two forms. Results are cached per process and,
+// with FX_AUTOTUNE_CACHE=<file>, on disk.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -306,14 +308,15 @@ double time_item(fx_batch* b, fx_batch::Class& c, const Tune& t, hipStream_t st)
     Timer tm;
     double best = -1.0;
     if (tm.ok) {
-        for (int rep = 0; rep < 2; ++rep) {
+        for (int rep = 0; rep < 3; ++rep) {
             (void)hipEventRecord(tm.e0, st);
             fx_status s = run_group(b, c, 0, (size_t)G, in.data(), nullptr, nullptr, st);
             (void)hipEventRecord(tm.e1, st);
             if (s != FX_OK || hipEventSynchronize(tm.e1) != hipSuccess) { best = -1.0; break; }
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, tm.e0, tm.e1);
-            if (rep == 1) best = ms / (double)G;  // the first repetition sets LDS attributes, warms caches
+            // the first repetition sets LDS attributes and warms caches; the best of the others counts
+            if (rep >= 1 && (best < 0 || ms / (double)G < best)) best = ms / (double)G;
         }
     }
     (void)hipGetLastError();
@@ -392,31 +395,31 @@ Tune tune_class(fx_batch* b, fx_batch::Class& c, hipStream_t st) {
     return best;
 }
 
-// ms of one item of every class, one after the other (lanes = 1) or forked over the lanes.
-double time_round(fx_batch* b, int lanes, hipStream_t st) {
-    std::vector<const void*> in(b->n, nullptr);
+// ms of one whole run of the batch (every item of every class, each class's staging tensor as the
+// input of all its realizations, no outputs) with the given lane count; -1 on failure.
+double time_full(fx_batch* b, int lanes, hipStream_t st) {
     Timer tm;
-    double best = -1.0;
-    if (tm.ok) {
-        for (int rep = 0; rep < 2; ++rep) {
-            (void)hipEventRecord(tm.e0, st);
-            fx_status s = lanes > 1 ? fork_lanes(b, lanes, st) : FX_OK;
-            for (auto& c : b->classes) {
-                if (s != FX_OK) break;
-                for (size_t i = 0; i < in.size(); ++i) in[i] = c.stage;
-                s = run_group(b, c, 0, (size_t)c.group, in.data(), nullptr, nullptr,
-                              lanes > 1 ? b->lanes[c.lane % lanes] : st);
-            }
-            if (lanes > 1) (void)join_lanes(b, lanes, st);
-            (void)hipEventRecord(tm.e1, st);
-            if (s != FX_OK || hipEventSynchronize(tm.e1) != hipSuccess) { best = -1.0; break; }
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, tm.e0, tm.e1);
-            if (rep == 1) best = ms;
-        }
+    if (!tm.ok) return -1.0;
+    const int saved = b->concurrency;
+    b->concurrency = lanes;
+    double ms_out = -1.0;
+    (void)hipEventRecord(tm.e0, st);
+    fx_status s = lanes > 1 ? fork_lanes(b, lanes, st) : FX_OK;
+    for (auto& c : b->classes) {
+        if (s != FX_OK) break;
+        std::vector<const void*> in(b->n, c.stage);
+        s = run_class(b, c, in.data(), nullptr, nullptr, lanes > 1 ? b->lanes[c.lane % lanes] : st);
     }
+    if (lanes > 1) (void)join_lanes(b, lanes, st);
+    (void)hipEventRecord(tm.e1, st);
+    if (s == FX_OK && hipEventSynchronize(tm.e1) == hipSuccess) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, tm.e0, tm.e1);
+        ms_out = ms;
+    }
+    b->concurrency = saved;
     (void)hipGetLastError();
-    return best;
+    return ms_out;
 }
 
 // Every output range (psi_out[i], rho_out[i]) must be disjoint from every other output range and
@@ -572,8 +575,14 @@ fx_status fx_batch_create(const fx_problem* probs, int32_t n, fx_batch** out) {
         if (it != g_conc.end()) {
             b->concurrency = std::min(it->second, ncls);
         } else if (tune) {
-            const double t1 = time_round(b, 1, st);
-            const double tn = time_round(b, ncls, st);
+            // whole runs, alternating between the two forms, best of two each after one warm-up
+            double t1 = -1.0, tn = -1.0;
+            for (int rep = 0; rep < 3; ++rep) {
+                const double a = time_full(b, 1, st), c = time_full(b, ncls, st);
+                if (rep == 0) continue;
+                if (a >= 0 && (t1 < 0 || a < t1)) t1 = a;
+                if (c >= 0 && (tn < 0 || c < tn)) tn = c;
+            }
             b->concurrency = (tn >= 0 && (t1 < 0 || tn < t1)) ? ncls : 1;
             g_conc[bkey] = b->concurrency;
             dirty = true;

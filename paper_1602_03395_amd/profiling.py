@@ -183,10 +183,18 @@ def strided_calibration(fetch_csv: str, write_csv: str, copy_mib: float, f_scale
     return out
 
 
-def traffic_kernels(fetch_csv: str, write_csv: str, copy_mib: float, out_json: str, tag: str, mapping):
+def traffic_kernels(fetch_csv: str, write_csv: str, copy_mib: float, out_json: str, tag: str, mapping,
+                    bench_json: str = None):
     """As ``traffic``, but per kernel name (for runs whose passes interleave, such as a batch whose
     classes run on several streams): ``mapping`` is a list of 'short_name=key' (the key under which
-    the bench looks the kernel up, e.g. '64x64x512/EA#0'); bytes are averages per dispatch."""
+    the bench looks the kernel up, e.g. '64x64x512/EA#0'); bytes are averages per dispatch. With
+    ``bench_json`` (the benchmark line of the same launch configuration) every entry also records
+    the item shape of its launches and the ratio of measured to algorithmic bytes."""
+    rows = {}
+    if bench_json:
+        line = [ln for ln in open(bench_json).read().splitlines() if ln.strip().startswith("{")][-1]
+        for r in json.loads(line).get("passes", []):
+            rows[f'{r["class"]}/{r["key"]}'] = r
     f_avg, f_n = counters(fetch_csv, "FETCH_SIZE")
     w_avg, _ = counters(write_csv, "WRITE_SIZE")
     copy_kib = copy_mib * 1024.0
@@ -206,9 +214,15 @@ def traffic_kernels(fetch_csv: str, write_csv: str, copy_mib: float, out_json: s
             raise SystemExit(f"kernel {name} not in the counter file")
         fb = f_avg[full] * 1024.0 * f_scale
         wb = w_avg.get(full, 0.0) * 1024.0 * w_scale
-        res["passes"][key] = {"kernel": name, "dispatches": f_n[full], "fetch_KiB_counter": f_avg[full],
-                              "write_KiB_counter": w_avg.get(full, 0.0), "fetch_bytes": fb, "write_bytes": wb,
-                              "hbm_bytes_per_launch": fb + wb}
+        ent = {"kernel": name, "dispatches": f_n[full], "fetch_KiB_counter": f_avg[full],
+               "write_KiB_counter": w_avg.get(full, 0.0), "fetch_bytes": fb, "write_bytes": wb,
+               "hbm_bytes_per_launch": fb + wb}
+        r = rows.get(key)
+        if r:
+            alg = r["bytes"] / r["launches"]
+            ent.update({"group": r["group"], "q_block": r["q_block"], "algorithmic_bytes_per_launch": alg,
+                        "traffic_over_algorithmic": (fb + wb) / alg})
+        res["passes"][key] = ent
     _store(out_json, tag, res)
     return res
 
@@ -242,7 +256,11 @@ if __name__ == "__main__":
         print(json.dumps(traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), int(sys.argv[5]), sys.argv[6],
                                  sys.argv[7]), indent=1))
     elif cmd == "traffic-kernels":
+        rest = sys.argv[7:]
+        bench = None
+        if rest and rest[0].startswith("--bench="):
+            bench, rest = rest[0].split("=", 1)[1], rest[1:]
         print(json.dumps(traffic_kernels(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5], sys.argv[6],
-                                         sys.argv[7:]), indent=1))
+                                         rest, bench), indent=1))
     else:
         raise SystemExit(__doc__)
