@@ -163,12 +163,15 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
                             ehr_applicable(p->ax[ax].M, p->ax[ax].g);
         g.eaw = kind == Kind::EA && p->use_cfp && p->use_eaw && p->ax[ax].HTx != nullptr &&
                 eaw_applicable(p->dbl, p->ax[ax].M, p->ax[ax].g, qn[ax]);
+        g.erw = kind == Kind::E && p->use_cfp && p->use_erw > 0 && p->ax[ax].HT != nullptr && g.S == 1 &&
+                erw_applicable(p->dbl, p->ax[ax].M, p->ax[ax].g) && (p->ax[ax].P >= 32 || p->use_erw == 2);
         g.eas = !g.eaw && kind == Kind::EA && p->use_cfp && p->ax[ax].HTx != nullptr &&
                 (p->use_eas == 2 || (p->use_eas == 1 && p->ax[ax].P >= 8 && p->ax[ax].g <= 16)) &&
                 eas_applicable(p->dbl, p->ax[ax].M, p->ax[ax].g, qn[ax]);
-        const bool reg = !g.eas && !g.eaw && (use_cfp(p, kind, p->ax[ax]) || reg_eh);
+        const bool reg = !g.eas && !g.eaw && (g.erw || use_cfp(p, kind, p->ax[ax]) || reg_eh);
         g.eh2 = kind == Kind::EH && !reg_eh && p->use_eh2 && eh2_applicable(p->ax[ax].M, p->ax[ax].P);
-        g.TS = g.eaw ? eaw_tile_lines()
+        g.TS = g.erw ? erw_tile_lines(p->ax[ax].P)
+               : g.eaw ? eaw_tile_lines()
                : g.eas ? eas_tile_lines(p->ax[ax].g)
                      : reg_eh ? ehr_tile_lines(p->ax[ax].g)
                               : reg ? cfp_tile_lines(p->ax[ax].g) : choose_ts(p, kind, p->ax[ax].M, g.A, g.S);
@@ -196,6 +199,8 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
             const int64_t base = g.Qin * g.ntiles;
             const int64_t want = std::max<int64_t>(1, (int64_t)p->cfp_blocks);
             g.qc = (int)std::max<int64_t>(1, std::min<int64_t>(g.qn, (base * g.qn + want - 1) / want));
+            if (g.erw)
+                while (g.qc > 1 && (int64_t)erw_lds_bytes(p->dbl, p->ax[ax].P, g.qc) > lds_limit_bytes()) --g.qc;
         }
         return g;
     };
@@ -624,7 +629,7 @@ fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_pla
         ad.fm = make_radix_plan(ad.M);
         ad.fp = make_radix_plan(ad.P);
         ad.fg = make_radix_plan(ad.g);
-        ap.want_ht = cfp_applicable(Kind::E, p->dbl, (int)ap.M, ad.g) &&
+        ap.want_ht = (cfp_applicable(Kind::E, p->dbl, (int)ap.M, ad.g) || erw_applicable(p->dbl, (int)ap.M, ad.g)) &&
                      ap.lam * ap.M * (int64_t)ad.g <= (int64_t(1) << 26);
         tabs[pa] = build_axis_tables(ap);
         p->par[pa].phase = nullptr;  // the caller's table is not kept
@@ -700,6 +705,7 @@ fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_pla
     if (const char* e = std::getenv("FX_EAS")) p->use_eas = (e[0] == '1') ? 2 : 1;
     if (std::getenv("FX_NO_EAS")) p->use_eas = 0;
     if (std::getenv("FX_NO_EAW")) p->use_eaw = false;
+    if (const char* e = std::getenv("FX_ERW")) p->use_erw = std::atoi(e);
     if (std::getenv("FX_NO_EH2")) p->use_eh2 = false;
     if (const char* e = std::getenv("FX_ASR_MAXG")) p->asr_max_g = std::max(1, std::atoi(e));
     p->cfp_blocks = 2 * num_cus();
@@ -997,6 +1003,7 @@ const char* kernel_of(const fx_plan* p, const Op& o) {
         case Kind::AAH: return "k_AAHR";
         default: break;
     }
+    if (o.kind == Kind::E && g.erw) return "k_ERW";
     if (o.kind == Kind::EA && g.eaw) return "k_EAW";
     if (o.kind == Kind::EA && g.eas) return "k_EAS";
     if (g.qc > 0 && o.kind == Kind::EH) return "k_EHR";

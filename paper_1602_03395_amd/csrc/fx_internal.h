@@ -66,6 +66,7 @@ struct PassGeom {
     bool reg_a = false;  // A pass: register structured accumulate
     bool eas = false;    // EA pass: waves share the terms of 64 / g lines, structured accumulate
     bool eaw = false;    // EA pass (g = 8): one wave per tile of 8 lines, every term, structured accumulate
+    bool erw = false;    // E pass (g = 8, P = 16..64, contiguous lines): register form, a line per 8 P / V lanes
     bool eh2 = false;    // EH pass: compile-time power-of-two kernel, one output line per workgroup
 };
 
@@ -160,6 +161,12 @@ bool eas_applicable(bool dbl, int M, int g, int qn);
 int eas_tile_lines(int g);
 hipError_t launch_pass_eas(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
                            void* rho, hipStream_t st);
+// Register E with 8 P / V lanes per line (g = 8, P = 16, 32, 48, 64, contiguous lines; kernels_cfp.hip).
+bool erw_applicable(bool dbl, int M, int g);
+int erw_tile_lines(int P);
+size_t erw_lds_bytes(bool dbl, int P, int qc);
+hipError_t launch_pass_erw(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, hipStream_t st);
+
 // EA in register form with the structured accumulate for g = 8 and P in {2, 3, 4, 6, 8}: one wave
 // per tile of 8 lines running every term, the partial sums over q mod 8 in registers.
 bool eaw_applicable(bool dbl, int M, int g, int qn);

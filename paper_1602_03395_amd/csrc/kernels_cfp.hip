@@ -24,6 +24,7 @@ namespace fx {
 namespace {
 
 constexpr int kWave = 64;
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 
 // cos(2 pi e / 32) for e = 0..8; the other 32nd roots follow by symmetry
 constexpr double kQ32[9] = {1.0,
@@ -666,6 +667,207 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
     }
 }
 
+// Register E for longer pruned lengths (g = 8; P = 16, 32, 64 and 48: axes of 128 to 512 points),
+// contiguous lines. With V = 8 values per lane (V = 6 for P = 48) and NL = P / V, a line takes
+// L = 8 NL lanes; lane lam = lo + NL n2 (lo < NL, n2 < 8) keeps the V inputs x[8 n1 + n2] with
+// n1 = NL i + lo (i < V) in registers for every term. With k = k1 + V k2 (k1 < V, k2 < NL) the
+// P-point transform of the n2 subsequence splits as
+//   V[n2][k1 + V k2] = sum_lo w_NL^(lo k2) w_P^(lo k1) sum_i w_V^(i k1) y[8 (NL i + lo) + n2],
+// a V-point transform in the lane, a twiddle, and an NL-point transform across the lo lanes
+// (decimation in frequency: natural input, lane lo ends with k2 = bitrev(lo)). The table multiply
+// and the sum over n2 follow, and the inverse P-point transform splits the same way with
+// u = u1 + NL u2:
+//   E[u1 + NL u2] = sum_k1 w_V^(-k1 u2) w_P^(-k1 u1) sum_k2 w_NL^(-k2 u1) W[k1 + V k2].
+// V = 8: the sum over n2 is a reduce-scatter over the n2 lane bits (lane (lo, n2) keeps
+// k1 = bitrev3(n2)), and both inverse stages run across lanes on bit-reversed input (each lane
+// forms own + c partner with one scale at the end, as in lane_idft_x), so lane lam ends with
+// E[lam] and the writes of a line are contiguous. V = 6: one reduce-scatter step leaves each lane
+// three values of k1, the other two n2 bits are summed in full, the inverse over k2 runs across
+// lanes for the three values, and each lane n2 < 6 forms its output u2 = n2 as a 6-term sum over
+// its own values and its partner's. The odd n2 lanes take their input times (-1)^i, which moves
+// their k1 by V / 2, so the first reduce step needs no selects; the table rows are staged in LDS in
+// the order each lane consumes them (row of lane lam: its V values, padded by one).
+template <int P> constexpr int erw_values() { return (P % 3 == 0) ? 6 : 8; }
+
+template <typename T, int P>
+__global__ __launch_bounds__(kThreads) void k_ERW(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
+                                                  PassGeom g, const C<T>* __restrict__ TA, const C<T>* __restrict__ HT) {
+    constexpr int G = 8;
+    constexpr int V = erw_values<P>();
+    constexpr int NL = P / V;
+    constexpr int LNL = ilog2c(NL);
+    constexpr int L = NL * G;          // lanes per line
+    constexpr int TL = kThreads / L;   // lines per tile
+    constexpr int HR = V + 1;          // LDS row of one lane's table values
+    constexpr int HV = V / 2;
+    static_assert(NL >= 2 && (NL & (NL - 1)) == 0 && L <= kWave, "P = 16, 32, 48 or 64");
+    extern __shared__ __align__(16) unsigned char smem[];
+    C<T>* TAs = (C<T>*)smem;         // [q - qlo][n1]: TA_q[8 n1] of the workgroup's terms
+    C<T>* Hs = TAs + g.qc * P;       // [q - q0][lam][HR]: table values of kErStage terms
+    const int M = ax.M;
+    const int lam = (int)threadIdx.x & (L - 1);
+    const int l = (int)threadIdx.x / L;
+    const int lo = lam & (NL - 1);
+    const int n2 = lam >> LNL;
+    const int b0 = n2 & 1;
+    const C<T>* tw = (const C<T>*)ax.tw;  // exp(-2 pi i k / M); w_P^a = tw[8 a mod M]
+    C<T> t1[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) t1[j] = tw[(lo * ((j + HV * b0) % V) * G) % M];
+    // decimation-in-frequency stages across lo (top bit first): lower lane a + b, upper (a - b) w
+    T dsg[LNL];
+    C<T> dmul[LNL];
+#pragma unroll
+    for (int s = 0; s < LNL; ++s) {
+        const bool up = (lo >> s) & 1;
+        dsg[s] = up ? (T)-1 : (T)1;
+        dmul[s] = up ? tw[(lo & ((1 << s) - 1)) * (M >> (s + 1))] : mk<T>(1, 0);
+    }
+    C<T> w1[LNL];
+    const C<T> fin1 = lane_twiddles_x<T, LNL, true>(w1, lo, tw, M);
+    // after the inverse over k2: undo its scale and apply w_P^(-k1 u1) (u1 = lo)
+    constexpr int NM = (V == 8) ? 1 : HV;
+    C<T> m2[NM];
+    C<T> w3[3], fin3 = mk<T>(1, 0);
+    C<T> cown[HV], cpar[HV];  // V = 6: w_6^(-k1 n2) for the lane's own k1 and its partner's
+    if constexpr (V == 8) {
+        fin3 = lane_twiddles_x<T, 3, true>(w3, n2, tw, M);
+        const int k1 = ((n2 & 1) << 2) | (n2 & 2) | ((n2 >> 2) & 1);
+        const C<T> e = tw[(k1 * lo * G) % M];
+        m2[0] = cmul<T>(fin1, mk<T>(e.x, -e.y));
+    } else {
+#pragma unroll
+        for (int j = 0; j < HV; ++j) {
+            const C<T> e = tw[((HV * b0 + j) * lo * G) % M];
+            m2[j] = cmul<T>(fin1, mk<T>(e.x, -e.y));
+            const C<T> co = tw[(((HV * b0 + j) * n2) % 6) * (M / 6)];
+            const C<T> cp = tw[(((HV * (1 - b0) + j) * n2) % 6) * (M / 6)];
+            cown[j] = mk<T>(co.x, -co.y);
+            cpar[j] = mk<T>(cp.x, -cp.y);
+        }
+    }
+    const int qc = g.qc;
+    const int nqc = (g.qn + qc - 1) / qc;
+    // XCD-aware order as in k_ER: the nqc workgroups of a tile run on one XCD
+    const int64_t ntl = g.Qin * g.ntiles;
+    const int64_t T8 = (ntl + 7) / 8;
+    const int64_t total = T8 * 8 * nqc;
+    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
+        const unsigned rr = (unsigned)bid >> 3;
+        const int ci = (int)(rr % (unsigned)nqc);
+        const int64_t tile = ((int64_t)bid & 7) * T8 + (int64_t)(rr / (unsigned)nqc);
+        if (tile >= ntl) continue;  // uniform over the workgroup
+        const int64_t qi = (int64_t)((unsigned)tile / (unsigned)g.ntiles);
+        const int64_t a0 = (tile - qi * g.ntiles) * TL;
+        const bool live = a0 + l < g.A;
+        const int qlo = g.qb + ci * qc;
+        const int qhi = min(qlo + qc, g.qb + g.qn);
+        const int ti = (int)threadIdx.x;
+        const int nta = (qhi - qlo) * P;
+        for (int e = ti; e < nta; e += kThreads) TAs[e] = TA[(int64_t)(qlo + e / P) * M + (e % P) * G];
+        C<T> x[V];
+        {
+            const C<T>* src = in + (qi * g.A + a0 + (live ? l : 0)) * M + G * lo + n2;
+#pragma unroll
+            for (int i = 0; i < V; ++i) x[i] = live ? src[i * G * NL] : mk<T>(0, 0);
+        }
+        if (b0) {
+#pragma unroll
+            for (int i = 1; i < V; i += 2) x[i] = mk<T>(-x[i].x, -x[i].y);
+        }
+        for (int q = qlo; q < qhi; ++q) {
+            const int ql = (q - qlo) % kErStage;
+            if (ql == 0) {
+                // the next round of table rows, rearranged for the lanes: HT[q][r][n2] with
+                // r = k1 + V k2 goes to lane bitrev(k2) + NL n2, slot k1 + V/2 (mod V) for odd n2
+                __syncthreads();
+                const int cnt = min(kErStage, qhi - q) * M;
+                const C<T>* src = HT + (int64_t)q * M;
+                for (int e = ti; e < cnt; e += kThreads) {
+                    const int qq = e / M, rem = e - qq * M;
+                    const int r = rem >> 3, m2i = rem & 7;
+                    const int kk2 = r / V, kk1 = r - kk2 * V;
+                    int br = 0;
+#pragma unroll
+                    for (int b = 0; b < LNL; ++b) br |= ((kk2 >> b) & 1) << (LNL - 1 - b);
+                    Hs[(qq * L + br + NL * m2i) * HR + (kk1 + HV * (m2i & 1)) % V] = src[e];
+                }
+                __syncthreads();
+            }
+            const C<T>* ta = TAs + (q - qlo) * P + lo;
+            C<T> v[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) v[i] = cmul<T>(x[i], ta[i * NL]);
+            RegDFT<T, V, false>::run(v);
+#pragma unroll
+            for (int j = 0; j < V; ++j) v[j] = cmul<T>(v[j], t1[j]);
+#pragma unroll
+            for (int s = LNL - 1; s >= 0; --s) {
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    const C<T> pj = shfl_xor_c<T>(v[j], 1 << s);
+                    v[j] = cmul<T>(mk<T>(pj.x + dsg[s] * v[j].x, pj.y + dsg[s] * v[j].y), dmul[s]);
+                }
+            }
+            const C<T>* h = Hs + (ql * L + lam) * HR;
+#pragma unroll
+            for (int j = 0; j < V; ++j) v[j] = cmul<T>(v[j], h[j]);
+            // sum over n2: both lanes of the first pair keep slots 0 .. V/2 - 1
+#pragma unroll
+            for (int j = 0; j < HV; ++j) v[j] = cadd<T>(v[j], shfl_xor_c<T>(v[j + HV], NL));
+            C<T> a;
+            if constexpr (V == 8) {
+                {
+                    const bool hi = (n2 >> 1) & 1;
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const C<T> keep = hi ? v[j + 2] : v[j];
+                        const C<T> send = hi ? v[j] : v[j + 2];
+                        v[j] = cadd<T>(keep, shfl_xor_c<T>(send, 2 * NL));
+                    }
+                }
+                {
+                    const bool hi = (n2 >> 2) & 1;
+                    const C<T> keep = hi ? v[1] : v[0];
+                    const C<T> send = hi ? v[0] : v[1];
+                    a = cadd<T>(keep, shfl_xor_c<T>(send, 4 * NL));
+                }
+                // inverse: over k2 (lo lanes), twiddle, over k1 (n2 lanes)
+#pragma unroll
+                for (int s = 0; s < LNL; ++s) a = cfma<T>(a, w1[s], shfl_xor_c<T>(a, 1 << s));
+                a = cmul<T>(a, m2[0]);
+#pragma unroll
+                for (int s = 0; s < 3; ++s) a = cfma<T>(a, w3[s], shfl_xor_c<T>(a, NL << s));
+                a = cmul<T>(a, fin3);
+            } else {
+                // the other two n2 bits summed in full: the lane holds k1 = V/2 b0 + j, j < V/2
+#pragma unroll
+                for (int s = 1; s < 3; ++s) {
+#pragma unroll
+                    for (int j = 0; j < HV; ++j) v[j] = cadd<T>(v[j], shfl_xor_c<T>(v[j], NL << s));
+                }
+#pragma unroll
+                for (int j = 0; j < HV; ++j) {
+#pragma unroll
+                    for (int s = 0; s < LNL; ++s) v[j] = cfma<T>(v[j], w1[s], shfl_xor_c<T>(v[j], 1 << s));
+                    v[j] = cmul<T>(v[j], m2[j]);
+                }
+                a = mk<T>(0, 0);
+#pragma unroll
+                for (int j = 0; j < HV; ++j) {
+                    a = cfma<T>(a, cown[j], v[j]);
+                    a = cfma<T>(a, cpar[j], shfl_xor_c<T>(v[j], NL));
+                }
+            }
+            if (live && (V == 8 || n2 < V)) {
+                const int64_t qo = qi * g.qn + (q - g.qb);
+                out[(qo * g.A + a0 + l) * P + lo + NL * n2] = a;
+            }
+        }
+        __syncthreads();  // the next tile overwrites the buffers the q loop reads
+    }
+}
+
 // EA in register form: the E values of every q are combined at once into the lane's M / G = P
 // outputs nbar = n2 + G k (the accumulate of (FFpsi) along this axis):
 //   out[nbar] = sum_q Tf_q[nbar] E_q[r(nbar)],  r(nbar) = (nbar lg) mod P.
@@ -1147,7 +1349,6 @@ __global__ __launch_bounds__(kThreads) void k_AA(const C<T>* __restrict__ in, C<
 // j_v the same way. Workgroups take the groups in XCD-contiguous ranges: the groups of one output line
 // (all n0_v of an n0_u) write the same cache lines.
 constexpr int aar_threads(int G, int R) { return (G * G / R > kThreads) ? G * G / R : kThreads; }
-constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 
 template <typename T, int G, int R>
 __global__ __launch_bounds__(2 * kThreads) void k_AAR(const C<T>* __restrict__ in, C<T>* __restrict__ out,
@@ -2378,6 +2579,53 @@ hipError_t launch_pass_aa(bool dbl, const void* in, void* out, const AxisDev& au
         hipLaunchKernelGGL(k_AA<float>, dim3(blocks), dim3(kThreads), lds, st, (const float2*)in, (float2*)out, au, av,
                            g, accumulate, (float*)rho);
     return hipGetLastError();
+}
+
+bool erw_applicable(bool dbl, int M, int g) {
+    (void)dbl;
+    if (g != 8 || M % 8 != 0) return false;
+    const int P = M / 8;
+    return P == 16 || P == 32 || P == 48 || P == 64;
+}
+
+// lanes per line of k_ERW: 8 P / V
+static int erw_lanes(int P) { return (P % 3 == 0) ? 8 * (P / 6) : P; }
+
+int erw_tile_lines(int P) { return kThreads / std::max(1, erw_lanes(P)); }
+
+size_t erw_lds_bytes(bool dbl, int P, int qc) {
+    const int V = (P % 3 == 0) ? 6 : 8;
+    return ((size_t)qc * P + (size_t)kErStage * erw_lanes(P) * (V + 1)) * (dbl ? 16 : 8);
+}
+
+template <typename T, int P>
+hipError_t launch_erw(const void* in, void* out, const AxisDev& ax, const PassGeom& g, hipStream_t st) {
+    const size_t lds = erw_lds_bytes(sizeof(T) == 8, P, g.qc);
+    auto k = k_ERW<T, P>;
+    hipError_t e = prep_lds((const void*)k, lds);
+    if (e != hipSuccess) return e;
+    const int nqc = (g.qn + g.qc - 1) / g.qc;
+    int64_t blocks = ((g.Qin * g.ntiles + 7) / 8) * 8 * nqc;
+    if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = (g.max_blocks + 7) / 8 * 8;
+    if (blocks > (1 << 22)) blocks = 1 << 22;
+    hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), lds, st, (const C<T>*)in,
+                       (C<T>*)out, ax, g, (const C<T>*)ax.TA, (const C<T>*)ax.HT);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass_erw(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, hipStream_t st) {
+    if (!erw_applicable(dbl, ax.M, ax.g) || !ax.HT || !ax.tw || g.S != 1 || g.TS != erw_tile_lines(ax.P) || g.qc < 1)
+        return hipErrorInvalidValue;
+    if ((int64_t)erw_lds_bytes(dbl, ax.P, g.qc) > lds_limit_bytes()) return hipErrorInvalidValue;
+    if (((g.Qin * g.ntiles + 7) / 8) * 8 * ((g.qn + g.qc - 1) / g.qc) >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    if ((g.Qin * g.A + 1) * (int64_t)ax.M >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    switch (ax.P) {
+        case 16: return dbl ? launch_erw<double, 16>(in, out, ax, g, st) : launch_erw<float, 16>(in, out, ax, g, st);
+        case 32: return dbl ? launch_erw<double, 32>(in, out, ax, g, st) : launch_erw<float, 32>(in, out, ax, g, st);
+        case 48: return dbl ? launch_erw<double, 48>(in, out, ax, g, st) : launch_erw<float, 48>(in, out, ax, g, st);
+        case 64: return dbl ? launch_erw<double, 64>(in, out, ax, g, st) : launch_erw<float, 64>(in, out, ax, g, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 bool cfp_applicable(Kind kind, bool dbl, int M, int g) {

@@ -73,6 +73,7 @@ struct fx_plan {
                                    // per line grows as g^2 / 64 times the line's output), 2 wherever
                                    // it applies (FX_EAS=1)
     bool use_eaw = true;           // EA for g = 8 through the one-wave-per-tile structured kernel
+    int use_erw = 1;               // E with P lanes per line (g = 8): 0 never, 1 for P >= 32, 2 also P = 16
                                    // (FX_NO_EAW disables)
     int asr_max_g = 64;            // above this the LDS-transform form (k_AS) is used
     int cfp_blocks = 1024;         // register E kernel: target workgroups per launch
