@@ -480,6 +480,28 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
     // lane's input is modulated by (-1)^n1 (applied once per tile below), which exchanges the
     // halves of its spectrum.
     const bool odd_flip = LANEINV && (n2 & 1) && lgG >= 1;
+    // P = 6 with g = 8: the odd lane's input times (-1)^i moves its spectrum by 3, and it reads its
+    // table row rotated by 3 to match (see the sum over the lanes below)
+    const bool six = (P == 6) && lgG == 3;
+    const bool flip6 = six && (n2 & 1);
+    int hrot[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) hrot[r] = flip6 ? (r + 3) % P : r;
+    // the inverse 6-point transform of the summed values, output u = n2 (n2 < 6): with W[3 b0 + j] in the
+    // lane and W[3 (1 - b0) + j] in its partner, E[u] = sum_j exp(2 pi i j u / 6) (W[j] + (-1)^u W[j + 3])
+    T s_own = 1, s_par = 1;
+    C<T> c6[2];
+    if constexpr (P == 6) {
+        const T sg = (n2 & 1) ? (T)-1 : (T)1;  // (-1)^u, u = n2
+        s_own = (n2 & 1) ? sg : (T)1;
+        s_par = (n2 & 1) ? (T)1 : sg;
+        const C<T>* twp = (const C<T>*)ax.tw;
+#pragma unroll
+        for (int j = 1; j < 3; ++j) {
+            const C<T> c = twp[((j * n2) % 6) * (M / 6)];
+            c6[j - 1] = mk<T>(c.x, -c.y);
+        }
+    }
     C<T> wst[LP > 0 ? LP : 1];
     const C<T> fin = lane_twiddles_x<T, LP>(wst, n2, (const C<T>*)ax.tw, M);
     for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
@@ -535,7 +557,7 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
 #pragma unroll
             for (int i = 0; i < P; ++i) x[i] = live ? B[l * ldb + (i << lgG) + n2] : mk<T>(0, 0);
         }
-        if (odd_flip) {
+        if (odd_flip || flip6) {
 #pragma unroll
             for (int i = 1; i < P; i += 2) x[i] = mk<T>(-x[i].x, -x[i].y);
         }
@@ -594,7 +616,34 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
             for (int i = 0; i < P; ++i) v[i] = cmul<T>(x[i], ta[i]);
             RegDFT<T, P, false>::run(v);
 #pragma unroll
-            for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r]);
+            for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[hrot[r]]);
+            if constexpr (P == 6) {
+                if (six) {
+                    // sum over the 8 lanes: one select-free step (values 0..2 kept), the other two
+                    // lane bits in full; lane n2 < 6 then forms E[n2] from its and its partner's values
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) v[j] = cadd<T>(v[j], shfl_xor_c<T>(v[j + 3], 1));
+#pragma unroll
+                    for (int s2 = 1; s2 < 3; ++s2) {
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) v[j] = cadd<T>(v[j], shfl_xor_c<T>(v[j], 1 << s2));
+                    }
+                    C<T> aj[3];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const C<T> pj = shfl_xor_c<T>(v[j], 1);
+                        aj[j] = mk<T>(s_own * v[j].x + s_par * pj.x, s_own * v[j].y + s_par * pj.y);
+                    }
+                    const C<T> e = cfma<T>(cfma<T>(aj[0], c6[0], aj[1]), c6[1], aj[2]);
+                    if (live && n2 < P) {
+                        const int64_t qo = qi * g.qn + (q - g.qb);
+                        const int64_t off = (g.S == 1) ? ((qo * g.A + tl.a0 + l) * P + n2)
+                                                       : (((qo * g.A + tl.a0) * P + n2) * g.S + tl.s0 + l);
+                        out[off] = e;
+                    }
+                    continue;
+                }
+            }
             if constexpr (LANEINV) {
                 // sum over the lanes first, then one inverse transform across the P lanes
                 reduce_scatter_full<T, P>(v, n2);
@@ -611,7 +660,7 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
                 RegDFT<T, P, true>::run(v);
                 if constexpr (!kPow2<P> && P < 8) {
                     if (lgG == 3) {
-                        // g = 8: the values padded to 8 and summed by the select form of the
+                        // g = 8 (P = 3): the values padded to 8 and summed by the select form of the
                         // reduce-scatter; lane n2 ends with value bitrev3(n2) and writes it
                         C<T> w8[8];
 #pragma unroll
@@ -2175,23 +2224,53 @@ __global__ __launch_bounds__(kEwWaves * kWave) void k_EAW(const C<T>* __restrict
         Tfs[e] = Tf[(int64_t)(g.qb + qq) * M + i];
     }
     if constexpr (HST) {
+        // P = 6: the odd lanes' rows rotated by 3 (see below)
         const C<T>* hsrc = HT + (int64_t)g.qb * M;
-        for (int e = tid; e < qn * M; e += kEwWaves * kWave) Hst[e] = hsrc[e];
+        for (int e = tid; e < qn * M; e += kEwWaves * kWave) {
+            int src = e;
+            if constexpr (P == 6) {
+                const int qq = e / M, rem = e - qq * M, r = rem / G, m2 = rem - r * G;
+                src = qq * M + ((r + 3 * (m2 & 1)) % 6) * G + m2;
+            }
+            Hst[e] = hsrc[src];
+        }
     }
     __syncthreads();
     // lane constants: the cross-lane inverse (power-of-two P), the lane's output group, the
     // exp(2 pi i qb c / 8) of the final transform
-    const bool odd_flip = P2 && (n2 & 1);
+    // P = 6: the odd lane's input times (-1)^i moves its spectrum by 3, and it reads its table row
+    // rotated by 3 to match, so both lanes of the first reduce step keep values 0..2
+    constexpr bool SIX = (P == 6);
+    const bool odd_flip = (P2 || SIX) && (n2 & 1);
     C<T> wst[LP > 0 ? LP : 1];
     C<T> fin = mk<T>(1, 0);
     if constexpr (P2) fin = lane_twiddles_x<T, LP>(wst, n2, (const C<T>*)ax.tw, M);
     // the value u of E_q the lane holds: n2 mod P after the cross-lane inverse (power-of-two P);
-    // after the padded reduce-scatter (P = 3, 6), bitrev3(n2), valid below P
+    // n2 for P = 6 (valid below 6); after the padded reduce-scatter (P = 3), bitrev3(n2), valid below P
     const int br = ((n2 & 1) << 2) | (n2 & 2) | ((n2 >> 2) & 1);
-    const int u = P2 ? n2 % P : (br < P ? br : 0);
-    const bool holds = P2 ? n2 < P : br < P;
+    const int u = P2 ? n2 % P : SIX ? (n2 < P ? n2 : 0) : (br < P ? br : 0);
+    const bool holds = P2 ? n2 < P : SIX ? n2 < P : br < P;
     const int n0u = (int)((u * ax.lg_inv) % P);
     const C<T>* tw = (const C<T>*)ax.tw;  // exp(-2 pi i k / M); k = P m gives exp(-2 pi i m / 8)
+    // table row offsets of the lane (P = 6 without staged rows: the odd lanes' rows rotated by 3)
+    int hoff[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) hoff[r] = ((SIX && !HST) ? (r + 3 * (n2 & 1)) % 6 : r) * G;
+    // P = 6: with the summed values W[3 b0 + j] in the lane and W[3 (1 - b0) + j] in its partner,
+    // E[u] = sum_j exp(2 pi i j u / 6) (W[j] + (-1)^u W[j + 3]); the lane's factors: s_own on its own
+    // value, s_par on its partner's, c_j = exp(2 pi i j u / 6) = conj(tw[8 j u mod M]) for j = 1, 2
+    T s_own = 1, s_par = 1;
+    C<T> c6[2];
+    if constexpr (SIX) {
+        const T sg = (u & 1) ? (T)-1 : (T)1;
+        s_own = (n2 & 1) ? sg : (T)1;
+        s_par = (n2 & 1) ? (T)1 : sg;
+#pragma unroll
+        for (int j = 1; j < 3; ++j) {
+            const C<T> c = tw[((j * u) % 6) * (M / 6)];
+            c6[j - 1] = mk<T>(c.x, -c.y);
+        }
+    }
     const int qbr = g.qb % G;
     C<T> ctw[G];
 #pragma unroll
@@ -2247,16 +2326,44 @@ __global__ __launch_bounds__(kEwWaves * kWave) void k_EAW(const C<T>* __restrict
                 for (int i = 0; i < P; ++i) va[i] = cmul<T>(x[i], ta[i]);
                 RegDFT<T, P, false>::run(va);
 #pragma unroll
-                for (int r = 0; r < P; ++r) va[r] = cmul<T>(va[r], ha[r * G]);
+                for (int r = 0; r < P; ++r) va[r] = cmul<T>(va[r], ha[hoff[r]]);
                 if constexpr (PAIR) {
 #pragma unroll
                     for (int i = 0; i < P; ++i) vb[i] = cmul<T>(x[i], tb2[i]);
                     RegDFT<T, P, false>::run(vb);
 #pragma unroll
-                    for (int r = 0; r < P; ++r) vb[r] = cmul<T>(vb[r], hb[r * G]);
+                    for (int r = 0; r < P; ++r) vb[r] = cmul<T>(vb[r], hb[hoff[r]]);
                 }
                 C<T> sa, sb = mk<T>(0, 0);
-                if constexpr (P2) {
+                if constexpr (SIX) {
+                    // sum over the 8 lanes: one select-free step (values 0..2 kept), then the other
+                    // two lane bits in full; then the 6-term inverse of the lane's output u
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        va[j] = cadd<T>(va[j], shfl_xor_c<T>(va[j + 3], 1));
+                        if constexpr (PAIR) vb[j] = cadd<T>(vb[j], shfl_xor_c<T>(vb[j + 3], 1));
+                    }
+#pragma unroll
+                    for (int s2 = 1; s2 < 3; ++s2) {
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) {
+                            va[j] = cadd<T>(va[j], shfl_xor_c<T>(va[j], 1 << s2));
+                            if constexpr (PAIR) vb[j] = cadd<T>(vb[j], shfl_xor_c<T>(vb[j], 1 << s2));
+                        }
+                    }
+                    C<T> aa[3], ab[3];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const C<T> pa = shfl_xor_c<T>(va[j], 1);
+                        aa[j] = mk<T>(s_own * va[j].x + s_par * pa.x, s_own * va[j].y + s_par * pa.y);
+                        if constexpr (PAIR) {
+                            const C<T> pb = shfl_xor_c<T>(vb[j], 1);
+                            ab[j] = mk<T>(s_own * vb[j].x + s_par * pb.x, s_own * vb[j].y + s_par * pb.y);
+                        }
+                    }
+                    sa = cfma<T>(cfma<T>(aa[0], c6[0], aa[1]), c6[1], aa[2]);
+                    if constexpr (PAIR) sb = cfma<T>(cfma<T>(ab[0], c6[0], ab[1]), c6[1], ab[2]);
+                } else if constexpr (P2) {
                     reduce_scatter_x<T, P>(va, n2, 3);
                     sa = va[0];
 #pragma unroll
@@ -2319,7 +2426,7 @@ hipError_t launch_eaw(const void* in, void* out, const AxisDev& ax, const PassGe
                       hipStream_t st) {
     const size_t stage = (size_t)g.qn * ax.M * sizeof(C<T>);
     const bool hst = stage <= kEwStageBytes;
-    // P = 3, 6: the padded reduce-scatter unless FX_EAW_TRANSPOSE=1 selects the LDS transpose
+    // the pass's table rows staged in LDS once per workgroup when they fit kEwStageBytes
     const size_t lds = ((size_t)2 * g.qn * P + (hst ? (size_t)g.qn * ax.M : 0)) * sizeof(C<T>);
     const int64_t units = (g.Qin * g.ntiles + kEwWaves - 1) / kEwWaves;
     int64_t blocks = (units + 7) / 8 * 8;

@@ -81,3 +81,28 @@ def test_eaw_blocked_and_partial_term_ranges(fx, dtype, tol, monkeypatch):
     torch.cuda.synchronize()
     ref = oracle.expand(f.astype(np.complex128), dx, 1.0, t, lam)
     assert rel(acc.cpu().numpy().astype(np.complex128), ref) <= (tol if dtype == torch.complex128 else 1e-5)
+
+
+E6_CASES = [
+    # E along a 48-point axis with g = 8 (P = 6) in the register kernel k_ER: contiguous and strided lines
+    ((5, 48), (3, 40), (1.0, 0.9), 20.0),
+    ((3, 48, 4), (2, 40, 3), (1.0, 1.0, 0.7), 15.0),
+    ((2, 7, 48), (3, 2, 8), (0.8, 1.0, 1.1), 6.0),
+]
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)])
+@pytest.mark.parametrize("case", range(len(E6_CASES)))
+def test_register_e_six_matches_oracle(fx, case, dtype, tol):
+    shape, lam, dx, t = E6_CASES[case]
+    npdt = np.complex128 if dtype == torch.complex128 else np.complex64
+    f = workloads.random_field(shape, 950 + case).astype(npdt)
+    plan = fx.Plan(shape, dx, 1.0, t, lam, dtype=dtype)
+    passes = json.loads(plan.describe())["passes"]
+    assert any(p["kind"] == "E" and p["kernel"] == "k_ER" and p["P"] == 6 for p in passes), passes
+    out, rho = plan.expand(torch.from_numpy(f).cuda())
+    torch.cuda.synchronize()
+    ref = oracle.expand(f.astype(np.complex128), dx, 1.0, t, lam)
+    assert rel(rho.cpu().numpy().astype(np.float64), oracle.density(ref)) <= tol
+    if dtype == torch.complex128:
+        assert rel(out.cpu().numpy(), ref) <= tol
