@@ -165,12 +165,23 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
                 eaw_applicable(p->dbl, p->ax[ax].M, p->ax[ax].g, qn[ax]);
         g.erw = kind == Kind::E && p->use_cfp && p->use_erw > 0 && p->ax[ax].HT != nullptr && g.S == 1 &&
                 erw_applicable(p->dbl, p->ax[ax].M, p->ax[ax].g) && (p->ax[ax].P >= 32 || p->use_erw == 2);
-        g.eas = !g.eaw && kind == Kind::EA && p->use_cfp && p->ax[ax].HTx != nullptr &&
+        g.erg = !g.erw && (kind == Kind::E || kind == Kind::EA) && p->use_cfp && p->use_erw > 0 &&
+                p->ax[ax].HT != nullptr && erg_applicable(p->dbl, p->ax[ax].M, p->ax[ax].g) &&
+                (p->ax[ax].P >= 32 || p->use_erw == 2);
+        if (g.erg) {
+            // the term staging of the fused form must fit the LDS (every term's TA and Tf values)
+            const int qc_max = kind == Kind::EA ? qn[ax] : 1;
+            if ((int64_t)erg_lds_bytes(p->dbl, kind, p->ax[ax].M, p->ax[ax].g, qc_max, qn[ax], g.S != 1) >
+                lds_limit_bytes())
+                g.erg = false;
+        }
+        g.eas = !g.eaw && !g.erg && kind == Kind::EA && p->use_cfp && p->ax[ax].HTx != nullptr &&
                 (p->use_eas == 2 || (p->use_eas == 1 && p->ax[ax].P >= 8 && p->ax[ax].g <= 16)) &&
                 eas_applicable(p->dbl, p->ax[ax].M, p->ax[ax].g, qn[ax]);
-        const bool reg = !g.eas && !g.eaw && (g.erw || use_cfp(p, kind, p->ax[ax]) || reg_eh);
+        const bool reg = !g.eas && !g.eaw && (g.erw || g.erg || use_cfp(p, kind, p->ax[ax]) || reg_eh);
         g.eh2 = kind == Kind::EH && !reg_eh && p->use_eh2 && eh2_applicable(p->ax[ax].M, p->ax[ax].P);
         g.TS = g.erw ? erw_tile_lines(p->ax[ax].P)
+               : g.erg ? erg_tile_lines(p->ax[ax].M, p->ax[ax].g)
                : g.eaw ? eaw_tile_lines()
                : g.eas ? eas_tile_lines(p->ax[ax].g)
                      : reg_eh ? ehr_tile_lines(p->ax[ax].g)
@@ -201,6 +212,10 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
             g.qc = (int)std::max<int64_t>(1, std::min<int64_t>(g.qn, (base * g.qn + want - 1) / want));
             if (g.erw)
                 while (g.qc > 1 && (int64_t)erw_lds_bytes(p->dbl, p->ax[ax].P, g.qc) > lds_limit_bytes()) --g.qc;
+            if (g.erg)
+                while (g.qc > 1 && (int64_t)erg_lds_bytes(p->dbl, kind, p->ax[ax].M, p->ax[ax].g, g.qc, g.qn, g.S != 1) >
+                                       lds_limit_bytes())
+                    --g.qc;
         }
         return g;
     };
@@ -629,7 +644,8 @@ fx_status create_plan(const fx_problem* prob, const double* const* phase, fx_pla
         ad.fm = make_radix_plan(ad.M);
         ad.fp = make_radix_plan(ad.P);
         ad.fg = make_radix_plan(ad.g);
-        ap.want_ht = (cfp_applicable(Kind::E, p->dbl, (int)ap.M, ad.g) || erw_applicable(p->dbl, (int)ap.M, ad.g)) &&
+        ap.want_ht = (cfp_applicable(Kind::E, p->dbl, (int)ap.M, ad.g) || erw_applicable(p->dbl, (int)ap.M, ad.g) ||
+                      erg_applicable(p->dbl, (int)ap.M, ad.g)) &&
                      ap.lam * ap.M * (int64_t)ad.g <= (int64_t(1) << 26);
         tabs[pa] = build_axis_tables(ap);
         p->par[pa].phase = nullptr;  // the caller's table is not kept
@@ -1004,6 +1020,7 @@ const char* kernel_of(const fx_plan* p, const Op& o) {
         default: break;
     }
     if (o.kind == Kind::E && g.erw) return "k_ERW";
+    if ((o.kind == Kind::E || o.kind == Kind::EA) && g.erg) return "k_ERG";
     if (o.kind == Kind::EA && g.eaw) return "k_EAW";
     if (o.kind == Kind::EA && g.eas) return "k_EAS";
     if (g.qc > 0 && o.kind == Kind::EH) return "k_EHR";
@@ -1059,7 +1076,7 @@ fx_status fx_plan_describe(const fx_plan* p, char* buf, size_t len) {
                       (o.g.qc > 0 || o.g.reg_a || o.g.eas || o.g.eaw) ? 1 : 0);
         s += tmp;
         s += std::string(",\"kernel\":\"") + kernel_of(p, o) + "\"";
-        if (o.g.eas || o.g.eaw) s += ",\"eas\":1";
+        if (o.g.eas || o.g.eaw || (o.g.erg && o.kind == Kind::EA)) s += ",\"eas\":1";
         if (o.g.eh2) s += ",\"eh2\":1";
         if (o.kind == Kind::AA || o.kind == Kind::AAH) {
             const AxisDev& b = p->ax[o.axis2];

@@ -917,6 +917,249 @@ __global__ __launch_bounds__(kThreads) void k_ERW(const C<T>* __restrict__ in, C
     }
 }
 
+// The same lane layout for g = 2, 4, 8 (G lanes of n2) and P = 16, 32, 64 with V = 8 values per
+// lane, for E and for EA, contiguous or strided lines (strided tiles go through LDS). A line takes
+// L = G NL lanes (NL = P / 8). After the table multiply the sum over the G lanes of n2 is a
+// reduce-scatter that leaves VG = 8 / G values per lane, k1 = VG bitrev(n2) + t (t < VG), and the
+// inverse splits once more: with k1 = t + VG j and u2 = u2a + G u2b,
+//   sum_k1 w_8^(-k1 u2) Z[k1] = sum_t w_VG^(-t u2b) w_8^(-t u2a) sum_j w_G^(-j u2a) Z[t + VG j],
+// the sum over j across the n2 lanes (bit-reversed input, lane n2 ends with u2a = n2), a twiddle,
+// and a VG-point transform in the lane, so lane lam holds E[lam + L u2b] for u2b < VG. The EA form
+// adds Tf_q[n0] E_q[u] into the residue (q - qb) mod g of the output group n0 of each held u (the
+// term loop unrolled by g, so every residue is a fixed register) and ends each tile with the
+// g-point inverse over the residues (the structured accumulate).
+template <typename T, int P, int LG, bool EAF>
+__global__ __launch_bounds__(kThreads) void k_ERG(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
+                                                  PassGeom g, int accumulate, T* __restrict__ rho,
+                                                  const C<T>* __restrict__ TA, const C<T>* __restrict__ HT) {
+    constexpr int G = 1 << LG;
+    constexpr int V = 8;
+    constexpr int NL = P / V;
+    constexpr int LNL = ilog2c(NL);
+    constexpr int L = NL * G;          // lanes per line
+    constexpr int TL = kThreads / L;   // lines per tile
+    constexpr int HR = V + 1;
+    constexpr int VG = V >> LG;        // values per lane after the sum over n2
+    constexpr int M = G * P;
+    static_assert(NL >= 2 && (NL & (NL - 1)) == 0 && L <= kWave && LG >= 1 && LG <= 3, "P = 16, 32, 64; g = 2, 4, 8");
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int qcap = EAF ? g.qn : g.qc;
+    C<T>* TAs = (C<T>*)smem;                    // [q - qlo][n1] = TA_q[g n1]
+    C<T>* Tfs = TAs + qcap * P;                 // EA: [q - qb][n0] = Tf_q[n0]
+    C<T>* Hs = Tfs + (EAF ? g.qn * P : 0);      // [q - q0][lam][HR]: table values of kErStage terms
+    C<T>* B = Hs + kErStage * L * HR;           // strided tile: TL rows of M + kTilePad
+    const int ldb = M + kTilePad;
+    const int lam = (int)threadIdx.x & (L - 1);
+    const int l = (int)threadIdx.x / L;
+    const int lo = lam & (NL - 1);
+    const int n2 = lam >> LNL;
+    const int f = (n2 & 1) ? 4 : 0;
+    const int ti = (int)threadIdx.x;
+    const C<T>* tw = (const C<T>*)ax.tw;  // exp(-2 pi i k / M); w_P^a = tw[G a mod M]
+    C<T> t1[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) t1[j] = tw[(lo * (j ^ f) * G) % M];
+    T dsg[LNL];
+    C<T> dmul[LNL];
+#pragma unroll
+    for (int s = 0; s < LNL; ++s) {
+        const bool up = (lo >> s) & 1;
+        dsg[s] = up ? (T)-1 : (T)1;
+        dmul[s] = up ? tw[(lo & ((1 << s) - 1)) * (M >> (s + 1))] : mk<T>(1, 0);
+    }
+    C<T> w1[LNL], w3[LG];
+    const C<T> fin1 = lane_twiddles_x<T, LNL, true>(w1, lo, tw, M);
+    const C<T> fin3 = lane_twiddles_x<T, LG, true>(w3, n2, tw, M);
+    int brn = 0;  // bitrev of n2 over LG bits
+#pragma unroll
+    for (int b = 0; b < LG; ++b) brn |= ((n2 >> b) & 1) << (LG - 1 - b);
+    C<T> m2[VG], m3[VG];
+#pragma unroll
+    for (int t = 0; t < VG; ++t) {
+        const int k1 = VG * brn + t;
+        const C<T> e = tw[(k1 * lo * G) % M];
+        m2[t] = cmul<T>(fin1, mk<T>(e.x, -e.y));           // undo step 1's scale, w_P^(-k1 u1)
+        const C<T> e3 = tw[((t * n2) % V) * (M / V)];
+        m3[t] = cmul<T>(fin3, mk<T>(e3.x, -e3.y));         // undo step 3's scale, w_8^(-t u2a)
+    }
+    // EA: output group of every held value u = lam + L u2b, and exp(2 pi i qb c / g)
+    int n0u[EAF ? VG : 1];
+    C<T> ctw[EAF ? G : 1];
+    if constexpr (EAF) {
+#pragma unroll
+        for (int t = 0; t < VG; ++t) n0u[t] = (int)(((lam + L * t) * ax.lg_inv) % P);
+        const int qbr = g.qb % G;
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+            const C<T> e = tw[((qbr * c) % G) * P];
+            ctw[c] = mk<T>(e.x, -e.y);
+        }
+        // the pass's premultiply and twiddle values, once per workgroup
+        const C<T>* Tf = (const C<T>*)ax.Tf;
+        for (int e = ti; e < g.qn * P; e += kThreads) {
+            const int qq = e / P, i = e - qq * P;
+            TAs[e] = TA[(int64_t)(g.qb + qq) * M + G * i];
+            Tfs[e] = Tf[(int64_t)(g.qb + qq) * M + i];
+        }
+    }
+    const int qc = EAF ? g.qn : g.qc;
+    const int nqc = (g.qn + qc - 1) / qc;
+    const int64_t ntl = g.Qin * g.ntiles;
+    const int64_t T8 = (ntl + 7) / 8;
+    const int64_t total = T8 * 8 * nqc;
+    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
+        // every id and index here is below 2^31 (checked on the host): 32-bit division
+        const unsigned rr = (unsigned)bid >> 3;
+        const int ci = (int)(rr % (unsigned)nqc);
+        const int64_t tile = ((int64_t)bid & 7) * T8 + (int64_t)(rr / (unsigned)nqc);
+        if (tile >= ntl) continue;  // uniform over the workgroup
+        const int64_t qi = (int64_t)((unsigned)tile / (unsigned)g.ntiles);
+        const Tile tl = decode_tile(g, tile - qi * g.ntiles);
+        const bool live = l < tl.nl;
+        const int qlo = g.qb + ci * qc;
+        const int qhi = min(qlo + qc, g.qb + g.qn);
+        if constexpr (!EAF) {
+            const int nta = (qhi - qlo) * P;
+            for (int e = ti; e < nta; e += kThreads) TAs[e] = TA[(int64_t)(qlo + e / P) * M + (e % P) * G];
+        }
+        C<T> x[V];
+        if (g.S == 1) {
+            const C<T>* src = in + (qi * g.A + tl.a0 + (live ? l : 0)) * M + G * lo + n2;
+#pragma unroll
+            for (int i = 0; i < V; ++i) x[i] = live ? src[i * L] : mk<T>(0, 0);
+        } else {
+            const FDiv fdM = tile_div(g, tl, M);
+            load_tile<T, V, (sizeof(T) == 4 ? V : 1)>(in, B, g, tl, qi, M, fdM, ldb);
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < V; ++i) x[i] = live ? B[l * ldb + G * (NL * i + lo) + n2] : mk<T>(0, 0);
+        }
+        if (f) {
+#pragma unroll
+            for (int i = 1; i < V; i += 2) x[i] = mk<T>(-x[i].x, -x[i].y);
+        }
+        // E_q of the tile's lines for term q (q - qlo < the staged round): a[u2b] = E_q[lam + L u2b]
+        auto term = [&](int q, C<T>* a) {
+            const int ql = (q - qlo) % kErStage;
+            const C<T>* ta = TAs + (q - qlo) * P + lo;
+            C<T> v[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) v[i] = cmul<T>(x[i], ta[i * NL]);
+            RegDFT<T, V, false>::run(v);
+#pragma unroll
+            for (int j = 0; j < V; ++j) v[j] = cmul<T>(v[j], t1[j]);
+#pragma unroll
+            for (int s = LNL - 1; s >= 0; --s) {
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    const C<T> pj = shfl_xor_c<T>(v[j], 1 << s);
+                    v[j] = cmul<T>(mk<T>(pj.x + dsg[s] * v[j].x, pj.y + dsg[s] * v[j].y), dmul[s]);
+                }
+            }
+            const C<T>* h = Hs + (ql * L + lam) * HR;
+#pragma unroll
+            for (int j = 0; j < V; ++j) v[j] = cmul<T>(v[j], h[j]);
+            // sum over n2: the first step select-free (odd lanes hold k1 ^ 4), then the select form
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = cadd<T>(v[j], shfl_xor_c<T>(v[j + 4], NL));
+#pragma unroll
+            for (int s = 1; s < LG; ++s) {
+                const int half = 4 >> s;
+                const bool hi = (n2 >> s) & 1;
+#pragma unroll
+                for (int j = 0; j < half; ++j) {
+                    const C<T> keep = hi ? v[j + half] : v[j];
+                    const C<T> send = hi ? v[j] : v[j + half];
+                    v[j] = cadd<T>(keep, shfl_xor_c<T>(send, NL << s));
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < VG; ++t) {
+                C<T> b = v[t];
+#pragma unroll
+                for (int s = 0; s < LNL; ++s) b = cfma<T>(b, w1[s], shfl_xor_c<T>(b, 1 << s));
+                b = cmul<T>(b, m2[t]);
+#pragma unroll
+                for (int s = 0; s < LG; ++s) b = cfma<T>(b, w3[s], shfl_xor_c<T>(b, NL << s));
+                a[t] = cmul<T>(b, m3[t]);
+            }
+            RegDFT<T, VG, true>::run(a);
+        };
+        // the table rows of the terms [q, q + kErStage), rearranged for the lanes: HT[q][r][n2] with
+        // r = k1 + 8 k2 goes to lane bitrev(k2) + NL n2, slot k1 ^ 4 (n2 odd)
+        auto stage_rows = [&](int q) {
+            __syncthreads();
+            const int cnt = min(kErStage, qhi - q) * M;
+            const C<T>* src = HT + (int64_t)q * M;
+            for (int e = ti; e < cnt; e += kThreads) {
+                const int qq = e / M, rem = e - qq * M;
+                const int r = rem >> LG, m2i = rem & (G - 1);
+                const int kk2 = r >> 3, kk1 = r & 7;
+                int br = 0;
+#pragma unroll
+                for (int b = 0; b < LNL; ++b) br |= ((kk2 >> b) & 1) << (LNL - 1 - b);
+                Hs[(qq * L + br + NL * m2i) * HR + (kk1 ^ ((m2i & 1) << 2))] = src[e];
+            }
+            __syncthreads();
+        };
+        if constexpr (!EAF) {
+            for (int q = qlo; q < qhi; ++q) {
+                if ((q - qlo) % kErStage == 0) stage_rows(q);
+                C<T> a[VG];
+                term(q, a);
+                if (live) {
+                    const int64_t qo = qi * g.qn + (q - g.qb);
+#pragma unroll
+                    for (int t = 0; t < VG; ++t) {
+                        const int u = lam + L * t;
+                        const int64_t off = (g.S == 1) ? ((qo * g.A + tl.a0 + l) * P + u)
+                                                       : (((qo * g.A + tl.a0) * P + u) * g.S + tl.s0 + l);
+                        out[off] = a[t];
+                    }
+                }
+            }
+        } else {
+            // term loop unrolled by g: residue jj of every output group is a fixed register
+            C<T> H[VG][G];
+#pragma unroll
+            for (int t = 0; t < VG; ++t)
+#pragma unroll
+                for (int c = 0; c < G; ++c) H[t][c] = mk<T>(0, 0);
+            for (int q0 = qlo; q0 < qhi; q0 += G) {
+#pragma unroll
+                for (int jj = 0; jj < G; ++jj) {
+                    const int q = q0 + jj;
+                    if (q < qhi) {  // uniform
+                        if ((q - qlo) % kErStage == 0) stage_rows(q);
+                        C<T> a[VG];
+                        term(q, a);
+#pragma unroll
+                        for (int t = 0; t < VG; ++t) H[t][jj] = cfma<T>(H[t][jj], Tfs[(q - g.qb) * P + n0u[t]], a[t]);
+                    }
+                }
+            }
+            // the g-point inverse over the residues of each output group: outputs n0 + P c
+#pragma unroll
+            for (int t = 0; t < VG; ++t) {
+                RegDFT<T, G, true>::run(H[t]);
+                if (live) {
+#pragma unroll
+                    for (int c = 0; c < G; ++c) {
+                        C<T> v = cmul<T>(H[t][c], ctw[c]);
+                        const int nb = n0u[t] + P * c;
+                        const int64_t off = (g.S == 1) ? ((qi * g.A + tl.a0 + l) * M + nb)
+                                                       : (((qi * g.A + tl.a0) * M + nb) * g.S + tl.s0 + l);
+                        if (accumulate) v = cadd<T>(v, out[off]);
+                        out[off] = v;
+                        if (rho) rho[off] = v.x * v.x + v.y * v.y;
+                    }
+                }
+            }
+        }
+        __syncthreads();  // the next tile overwrites the buffers the term loop reads
+    }
+}
+
 // EA in register form: the E values of every q are combined at once into the lane's M / G = P
 // outputs nbar = n2 + G k (the accumulate of (FFpsi) along this axis):
 //   out[nbar] = sum_q Tf_q[nbar] E_q[r(nbar)],  r(nbar) = (nbar lg) mod P.
@@ -2686,6 +2929,70 @@ hipError_t launch_pass_aa(bool dbl, const void* in, void* out, const AxisDev& au
         hipLaunchKernelGGL(k_AA<float>, dim3(blocks), dim3(kThreads), lds, st, (const float2*)in, (float2*)out, au, av,
                            g, accumulate, (float*)rho);
     return hipGetLastError();
+}
+
+bool erg_applicable(bool dbl, int M, int g) {
+    (void)dbl;
+    if (!(g == 2 || g == 4 || g == 8) || M % g != 0) return false;
+    const int P = M / g;
+    return P == 16 || P == 32 || P == 64;
+}
+
+int erg_tile_lines(int M, int g) { return kThreads / std::max(1, g * (M / g) / 8); }
+
+size_t erg_lds_bytes(bool dbl, Kind kind, int M, int g, int qc, int qn, bool strided) {
+    const int P = M / g, L = g * P / 8, TL = kThreads / L;
+    const size_t tab = (kind == Kind::EA) ? (size_t)2 * qn * P : (size_t)qc * P;
+    return (tab + (size_t)kErStage * L * 9 + (strided ? (size_t)TL * (M + kTilePad) : 0)) * (dbl ? 16 : 8);
+}
+
+template <typename T, int P, int LG, bool EAF>
+hipError_t launch_erg(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
+                      hipStream_t st) {
+    const size_t lds = erg_lds_bytes(sizeof(T) == 8, EAF ? Kind::EA : Kind::E, ax.M, ax.g, g.qc, g.qn, g.S != 1);
+    auto k = k_ERG<T, P, LG, EAF>;
+    hipError_t e = prep_lds((const void*)k, lds);
+    if (e != hipSuccess) return e;
+    const int nqc = EAF ? 1 : (g.qn + g.qc - 1) / g.qc;
+    int64_t blocks = ((g.Qin * g.ntiles + 7) / 8) * 8 * nqc;
+    if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = (g.max_blocks + 7) / 8 * 8;
+    if (blocks > (1 << 22)) blocks = 1 << 22;
+    hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), lds, st, (const C<T>*)in,
+                       (C<T>*)out, ax, g, accumulate, (T*)rho, (const C<T>*)ax.TA, (const C<T>*)ax.HT);
+    return hipGetLastError();
+}
+
+template <typename T, bool EAF>
+hipError_t launch_erg_T(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, void* rho,
+                        hipStream_t st) {
+    const int key = ax.g * 100 + ax.P;
+    switch (key) {
+        case 216: return launch_erg<T, 16, 1, EAF>(in, out, ax, g, accumulate, rho, st);
+        case 232: return launch_erg<T, 32, 1, EAF>(in, out, ax, g, accumulate, rho, st);
+        case 264: return launch_erg<T, 64, 1, EAF>(in, out, ax, g, accumulate, rho, st);
+        case 416: return launch_erg<T, 16, 2, EAF>(in, out, ax, g, accumulate, rho, st);
+        case 432: return launch_erg<T, 32, 2, EAF>(in, out, ax, g, accumulate, rho, st);
+        case 464: return launch_erg<T, 64, 2, EAF>(in, out, ax, g, accumulate, rho, st);
+        case 816: return launch_erg<T, 16, 3, EAF>(in, out, ax, g, accumulate, rho, st);
+        case 832: return launch_erg<T, 32, 3, EAF>(in, out, ax, g, accumulate, rho, st);
+        case 864: return launch_erg<T, 64, 3, EAF>(in, out, ax, g, accumulate, rho, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pass_erg(Kind kind, bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g,
+                           int accumulate, void* rho, hipStream_t st) {
+    if ((kind != Kind::E && kind != Kind::EA) || !erg_applicable(dbl, ax.M, ax.g) || !ax.HT || !ax.tw || !ax.Tf ||
+        g.TS != erg_tile_lines(ax.M, ax.g) || g.qc < 1)
+        return hipErrorInvalidValue;
+    if ((int64_t)erg_lds_bytes(dbl, kind, ax.M, ax.g, g.qc, g.qn, g.S != 1) > lds_limit_bytes()) return hipErrorInvalidValue;
+    const int nqc = kind == Kind::EA ? 1 : (g.qn + g.qc - 1) / g.qc;
+    if (((g.Qin * g.ntiles + 7) / 8) * 8 * nqc >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    if (kind == Kind::EA)
+        return dbl ? launch_erg_T<double, true>(in, out, ax, g, accumulate, rho, st)
+                   : launch_erg_T<float, true>(in, out, ax, g, accumulate, rho, st);
+    return dbl ? launch_erg_T<double, false>(in, out, ax, g, accumulate, rho, st)
+               : launch_erg_T<float, false>(in, out, ax, g, accumulate, rho, st);
 }
 
 bool erw_applicable(bool dbl, int M, int g) {
