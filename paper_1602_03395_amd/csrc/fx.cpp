@@ -165,21 +165,22 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
                 eaw_applicable(p->dbl, p->ax[ax].M, p->ax[ax].g, qn[ax]);
         g.erw = kind == Kind::E && p->use_cfp && p->use_erw > 0 && p->ax[ax].HT != nullptr && g.S == 1 &&
                 erw_applicable(p->dbl, p->ax[ax].M, p->ax[ax].g) && (p->ax[ax].P >= 32 || p->use_erw == 2);
-        g.erg = !g.erw && (kind == Kind::E || kind == Kind::EA) && p->use_cfp && p->use_erw > 0 &&
-                p->ax[ax].HT != nullptr && erg_applicable(p->dbl, p->ax[ax].M, p->ax[ax].g) &&
+        g.erg = !g.erw && (kind == Kind::E || kind == Kind::EA || kind == Kind::EH) && p->use_cfp &&
+                p->use_erw > 0 && p->ax[ax].HT != nullptr && erg_applicable(p->dbl, p->ax[ax].M, p->ax[ax].g) &&
                 (p->ax[ax].P >= 32 || p->use_erw == 2);
         if (g.erg) {
-            // the term staging of the fused form must fit the LDS (every term's TA and Tf values)
-            const int qc_max = kind == Kind::EA ? qn[ax] : 1;
-            if ((int64_t)erg_lds_bytes(p->dbl, kind, p->ax[ax].M, p->ax[ax].g, qc_max, qn[ax], g.S != 1) >
-                lds_limit_bytes())
-                g.erg = false;
+            // the term staging must fit the LDS (EA: every term's TA and Tf values; EH: every term's TA)
+            const int64_t need = kind == Kind::EH
+                                     ? (int64_t)ehg_lds_bytes(p->dbl, p->ax[ax].M, p->ax[ax].g, qn[ax], g.S != 1)
+                                     : (int64_t)erg_lds_bytes(p->dbl, kind, p->ax[ax].M, p->ax[ax].g,
+                                                              kind == Kind::EA ? qn[ax] : 1, qn[ax], g.S != 1);
+            if (need > lds_limit_bytes()) g.erg = false;
         }
         g.eas = !g.eaw && !g.erg && kind == Kind::EA && p->use_cfp && p->ax[ax].HTx != nullptr &&
                 (p->use_eas == 2 || (p->use_eas == 1 && p->ax[ax].P >= 8 && p->ax[ax].g <= 16)) &&
                 eas_applicable(p->dbl, p->ax[ax].M, p->ax[ax].g, qn[ax]);
         const bool reg = !g.eas && !g.eaw && (g.erw || g.erg || use_cfp(p, kind, p->ax[ax]) || reg_eh);
-        g.eh2 = kind == Kind::EH && !reg_eh && p->use_eh2 && eh2_applicable(p->ax[ax].M, p->ax[ax].P);
+        g.eh2 = kind == Kind::EH && !reg_eh && !g.erg && p->use_eh2 && eh2_applicable(p->ax[ax].M, p->ax[ax].P);
         g.TS = g.erw ? erw_tile_lines(p->ax[ax].P)
                : g.erg ? erg_tile_lines(p->ax[ax].M, p->ax[ax].g)
                : g.eaw ? eaw_tile_lines()
@@ -203,8 +204,8 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
         g.reg_a = (kind == Kind::A || kind == Kind::AH) && p->use_asr && asr_applicable(p->ax[ax].g, p->asr_max_g);
         if (reg && kind == Kind::EA) {
             g.qc = g.qn;  // the fused pass sums every magnification index inside the workgroup
-        } else if (reg_eh) {
-            g.qc = g.qn;  // the waves of a workgroup share the terms and add through LDS
+        } else if (reg_eh || (g.erg && kind == Kind::EH)) {
+            g.qc = g.qn;  // every term of an output line inside one workgroup
         } else if (reg) {
             // magnification indices per workgroup: as many as keep >= cfp_blocks workgroups
             const int64_t base = g.Qin * g.ntiles;
@@ -273,7 +274,11 @@ std::vector<Op> build_ops(const fx_plan* p, const int qb[3], const int qn[3], in
         // also split where EH has its compile-time power-of-two kernel (the fused generic pass
         // runs one transform chain per term and workgroup)
         const bool eh2 = p->use_eh2 && eh2_applicable(p->ax[ax].M, p->ax[ax].P);
-        if (reg_adjoint(ax) || eh2 || split(Kind::EAH, ax)) { do_AH(ax); do_EH(ax); return; }
+        // the register adjoint E in the lanes-per-line layout, where the intermediate of the split
+        // (every term's pruned lines) stays well inside 32-bit indexing
+        const bool ehg = geom(Kind::EH, ax, slices / std::max(1, qn[ax])).erg &&
+                         vol() / p->ax[ax].M * p->ax[ax].P * qn[ax] < kIndexLimit / 4;
+        if (reg_adjoint(ax) || eh2 || ehg || split(Kind::EAH, ax)) { do_AH(ax); do_EH(ax); return; }
         emit(Kind::EAH, ax, geom(Kind::EAH, ax, slices), vol());
     };
     const int k = p->nact;
@@ -1021,6 +1026,7 @@ const char* kernel_of(const fx_plan* p, const Op& o) {
     }
     if (o.kind == Kind::E && g.erw) return "k_ERW";
     if ((o.kind == Kind::E || o.kind == Kind::EA) && g.erg) return "k_ERG";
+    if (o.kind == Kind::EH && g.erg) return "k_EHG";
     if (o.kind == Kind::EA && g.eaw) return "k_EAW";
     if (o.kind == Kind::EA && g.eas) return "k_EAS";
     if (g.qc > 0 && o.kind == Kind::EH) return "k_EHR";

@@ -67,7 +67,7 @@ struct PassGeom {
     bool eas = false;    // EA pass: waves share the terms of 64 / g lines, structured accumulate
     bool eaw = false;    // EA pass (g = 8): one wave per tile of 8 lines, every term, structured accumulate
     bool erw = false;    // E pass (g = 8, P = 16..64, contiguous lines): register form, a line per 8 P / V lanes
-    bool erg = false;    // E or EA pass (g = 2, 4, 8; P = 16..64): register form, a line per g P / 8 lanes
+    bool erg = false;    // E, EA or EH pass (g = 2, 4, 8; P = 16..64): register form, a line per g P / 8 lanes
     bool eh2 = false;    // EH pass: compile-time power-of-two kernel, one output line per workgroup
 };
 
@@ -168,6 +168,10 @@ int erg_tile_lines(int M, int g);
 size_t erg_lds_bytes(bool dbl, Kind kind, int M, int g, int qc, int qn, bool strided);
 hipError_t launch_pass_erg(Kind kind, bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g,
                            int accumulate, void* rho, hipStream_t st);
+// Its adjoint (EH) in the same lane layout.
+size_t ehg_lds_bytes(bool dbl, int M, int g, int qn, bool strided);
+hipError_t launch_pass_ehg(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
+                           hipStream_t st);
 
 // Register E with 8 P / V lanes per line (g = 8, P = 16, 32, 48, 64, contiguous lines; kernels_cfp.hip).
 bool erw_applicable(bool dbl, int M, int g);

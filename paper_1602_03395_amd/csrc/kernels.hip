@@ -740,6 +740,7 @@ hipError_t launch_pass(Kind kind, bool dbl, const void* in, void* out, const Axi
     if (((g.Qin * g.ntiles + 7) / 8) * 8 * g.qn >= (int64_t(1) << 31)) return hipErrorInvalidValue;
     if (kind == Kind::E && g.erw) return launch_pass_erw(dbl, in, out, ax, g, st);
     if ((kind == Kind::E || kind == Kind::EA) && g.erg) return launch_pass_erg(kind, dbl, in, out, ax, g, accumulate, rho, st);
+    if (kind == Kind::EH && g.erg) return launch_pass_ehg(dbl, in, out, ax, g, accumulate, st);
     if (kind == Kind::EA && g.eaw) return launch_pass_eaw(dbl, in, out, ax, g, accumulate, rho, st);
     if (kind == Kind::EA && g.eas) return launch_pass_eas(dbl, in, out, ax, g, accumulate, rho, st);
     if (g.qc > 0 && kind == Kind::EH) return launch_pass_ehr(dbl, in, out, ax, g, accumulate, st);

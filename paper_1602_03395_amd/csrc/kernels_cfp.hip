@@ -1160,6 +1160,197 @@ __global__ __launch_bounds__(kThreads) void k_ERG(const C<T>* __restrict__ in, C
     }
 }
 
+// Adjoint of E in the layout of k_ERG (g = 2, 4, 8; P = 16, 32, 64): the output line x (M points)
+// collects, over the terms q of the pass, conj(TA_q) * IDFT_P(conj(HT_q[n2]) * DFT_P(y_q)) with both
+// transforms unnormalised (the adjoint of E_q = IDFT_P(sum_n2 HT_q[n2] DFT_P(TA_q x_n2))). Lane lam =
+// lo + NL n2 reads y_q[lam + L u2b] (u2b < VG) and runs the transpose of the forward pipeline: a
+// VG-point forward transform in the lane, the twiddle w_8^(t n2), a g-point forward transform
+// across the n2 lanes and the twiddle w_P^(lo k1), an NL-point forward transform across the lo
+// lanes (both decimation in frequency: natural input, bit-reversed output), which leaves
+// DFT_P(y)[k1 + 8 k2] with k1 = VG bitrev(n2) + t and k2 = bitrev(lo), the layout after the
+// forward reduce-scatter; then the transpose of that reduce-scatter (an all-gather over the n2
+// lanes, the odd lanes ending with their slots in k1 ^ 4 order), the table multiply, the inverse
+// NL-point transform across the lo lanes (bit-reversed input), the twiddle w_P^(-lo k1) and an
+// 8-point inverse transform in the lane, times conj(TA_q), summed over the terms in registers. The
+// odd lanes' (-1)^i (from their k1 ^ 4 slots) is applied once per tile, when the line is written.
+template <typename T, int P, int LG>
+__global__ __launch_bounds__(kThreads) void k_EHG(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
+                                                  PassGeom g, int accumulate, const C<T>* __restrict__ TA,
+                                                  const C<T>* __restrict__ HT) {
+    constexpr int G = 1 << LG;
+    constexpr int V = 8;
+    constexpr int NL = P / V;
+    constexpr int LNL = ilog2c(NL);
+    constexpr int L = NL * G;
+    constexpr int TL = kThreads / L;
+    constexpr int HR = V + 1;
+    constexpr int VG = V >> LG;
+    constexpr int M = G * P;
+    static_assert(NL >= 2 && (NL & (NL - 1)) == 0 && L <= kWave && LG >= 1 && LG <= 3, "P = 16, 32, 64; g = 2, 4, 8");
+    extern __shared__ __align__(16) unsigned char smem[];
+    C<T>* TAs = (C<T>*)smem;                  // [q - qb][n1] = TA_q[g n1]
+    C<T>* Hs = TAs + g.qn * P;                // [q - q0][lam][HR]
+    C<T>* Ys = Hs + kErStage * L * HR;        // strided input: [q - q0][line][P]
+    const int lam = (int)threadIdx.x & (L - 1);
+    const int l = (int)threadIdx.x / L;
+    const int lo = lam & (NL - 1);
+    const int n2 = lam >> LNL;
+    const int f = (n2 & 1) ? 4 : 0;
+    const int ti = (int)threadIdx.x;
+    const C<T>* tw = (const C<T>*)ax.tw;
+    int brn = 0;
+#pragma unroll
+    for (int b = 0; b < LG; ++b) brn |= ((n2 >> b) & 1) << (LG - 1 - b);
+    // forward part: w_8^(t n2) after the lane transform, w_P^(lo k1) between the two lane transforms
+    C<T> b8[VG], dlo[VG];
+#pragma unroll
+    for (int t = 0; t < VG; ++t) {
+        b8[t] = tw[((t * n2) % V) * (M / V)];
+        dlo[t] = tw[(lo * (VG * brn + t) * G) % M];
+    }
+    // decimation-in-frequency stages across n2 (masks NL << s) and across lo (masks 1 << s)
+    T sgn2[LG], sgn1[LNL];
+    C<T> mul2[LG], mul1[LNL];
+#pragma unroll
+    for (int s = 0; s < LG; ++s) {
+        const bool up = (n2 >> s) & 1;
+        sgn2[s] = up ? (T)-1 : (T)1;
+        mul2[s] = up ? tw[(n2 & ((1 << s) - 1)) * (M >> (s + 1))] : mk<T>(1, 0);
+    }
+#pragma unroll
+    for (int s = 0; s < LNL; ++s) {
+        const bool up = (lo >> s) & 1;
+        sgn1[s] = up ? (T)-1 : (T)1;
+        mul1[s] = up ? tw[(lo & ((1 << s) - 1)) * (M >> (s + 1))] : mk<T>(1, 0);
+    }
+    // inverse part: across lo on bit-reversed input, then w_P^(-lo k1) (k1 = j ^ f in slot j) with
+    // the scale of the lane butterflies
+    C<T> w1[LNL];
+    const C<T> fin1 = lane_twiddles_x<T, LNL, true>(w1, lo, tw, M);
+    C<T> it1[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        const C<T> e = tw[(lo * (j ^ f) * G) % M];
+        it1[j] = cmul<T>(fin1, mk<T>(e.x, -e.y));
+    }
+    for (int e = ti; e < g.qn * P; e += kThreads) {
+        const int qq = e / P, i = e - qq * P;
+        TAs[e] = TA[(int64_t)(g.qb + qq) * M + G * i];
+    }
+    const int64_t ntl = g.Qin * g.ntiles;  // output lines' tiles, < 2^31 (host check)
+    const int64_t T8 = (ntl + 7) / 8;
+    for (int64_t bid = blockIdx.x; bid < 8 * T8; bid += gridDim.x) {
+        const int64_t tile = (bid & 7) * T8 + (bid >> 3);
+        if (tile >= ntl) continue;  // uniform over the workgroup
+        const int64_t qo = (int64_t)((unsigned)tile / (unsigned)g.ntiles);
+        const Tile tl = decode_tile(g, tile - qo * g.ntiles);
+        const bool live = l < tl.nl;
+        C<T> acc[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc[i] = mk<T>(0, 0);
+        for (int qq = 0; qq < g.qn; ++qq) {
+            const int ql = qq % kErStage;
+            if (ql == 0) {
+                // the next round: table rows in lane order (as k_ERG) and, for strided lines, the
+                // inputs of the round's terms with the lines fastest (coalesced)
+                __syncthreads();
+                const int nq = min(kErStage, g.qn - qq);
+                const C<T>* src = HT + (int64_t)(g.qb + qq) * M;
+                for (int e = ti; e < nq * M; e += kThreads) {
+                    const int q4 = e / M, rem = e - q4 * M;
+                    const int r = rem >> LG, m2i = rem & (G - 1);
+                    const int kk2 = r >> 3, kk1 = r & 7;
+                    int br = 0;
+#pragma unroll
+                    for (int b = 0; b < LNL; ++b) br |= ((kk2 >> b) & 1) << (LNL - 1 - b);
+                    Hs[(q4 * L + br + NL * m2i) * HR + (kk1 ^ ((m2i & 1) << 2))] = src[e];
+                }
+                if (g.S != 1) {
+                    const int per = tl.nl * P;
+                    for (int e = ti; e < nq * per; e += kThreads) {
+                        const int q4 = e / per, rem = e - q4 * per;
+                        const int u = rem / tl.nl, ll = rem - u * tl.nl;
+                        const int64_t si = qo * g.qn + qq + q4;
+                        Ys[(q4 * TL + ll) * P + u] = in[((si * g.A + tl.a0) * P + u) * g.S + tl.s0 + ll];
+                    }
+                }
+                __syncthreads();
+            }
+            C<T> v[V];
+            // y_q[lam + L u2b]
+            if (g.S == 1) {
+                const int64_t si = qo * g.qn + qq;
+                const C<T>* src = in + (si * g.A + tl.a0 + (live ? l : 0)) * P + lam;
+#pragma unroll
+                for (int t = 0; t < VG; ++t) v[t] = live ? src[L * t] : mk<T>(0, 0);
+            } else {
+#pragma unroll
+                for (int t = 0; t < VG; ++t) v[t] = live ? Ys[(ql * TL + l) * P + lam + L * t] : mk<T>(0, 0);
+            }
+            RegDFT<T, VG, false>::run(v);
+#pragma unroll
+            for (int t = 0; t < VG; ++t) v[t] = cmul<T>(v[t], b8[t]);
+#pragma unroll
+            for (int s = LG - 1; s >= 0; --s) {
+#pragma unroll
+                for (int t = 0; t < VG; ++t) {
+                    const C<T> pj = shfl_xor_c<T>(v[t], NL << s);
+                    v[t] = cmul<T>(mk<T>(pj.x + sgn2[s] * v[t].x, pj.y + sgn2[s] * v[t].y), mul2[s]);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < VG; ++t) v[t] = cmul<T>(v[t], dlo[t]);
+#pragma unroll
+            for (int s = LNL - 1; s >= 0; --s) {
+#pragma unroll
+                for (int t = 0; t < VG; ++t) {
+                    const C<T> pj = shfl_xor_c<T>(v[t], 1 << s);
+                    v[t] = cmul<T>(mk<T>(pj.x + sgn1[s] * v[t].x, pj.y + sgn1[s] * v[t].y), mul1[s]);
+                }
+            }
+            // the transpose of the reduce-scatter: all-gather over the n2 lanes
+#pragma unroll
+            for (int s = LG - 1; s >= 1; --s) {
+                const int half = 4 >> s;
+                const bool hi = (n2 >> s) & 1;
+#pragma unroll
+                for (int j = 0; j < half; ++j) {
+                    const C<T> pj = shfl_xor_c<T>(v[j], NL << s);
+                    v[j + half] = hi ? v[j] : pj;
+                    v[j] = hi ? pj : v[j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j + 4] = shfl_xor_c<T>(v[j], NL);
+            const C<T>* h = Hs + (ql * L + lam) * HR;
+#pragma unroll
+            for (int j = 0; j < V; ++j) v[j] = cmulc<T>(v[j], h[j]);
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+#pragma unroll
+                for (int s = 0; s < LNL; ++s) v[j] = cfma<T>(v[j], w1[s], shfl_xor_c<T>(v[j], 1 << s));
+                v[j] = cmul<T>(v[j], it1[j]);
+            }
+            RegDFT<T, V, true>::run(v);
+            const C<T>* ta = TAs + qq * P + lo;
+#pragma unroll
+            for (int i = 0; i < V; ++i) acc[i] = cfmac<T>(acc[i], v[i], ta[i * NL]);
+        }
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                C<T> v = (f && (i & 1)) ? mk<T>(-acc[i].x, -acc[i].y) : acc[i];
+                const int n = G * (NL * i + lo) + n2;
+                const int64_t off = (g.S == 1) ? ((qo * g.A + tl.a0 + l) * M + n)
+                                               : (((qo * g.A + tl.a0) * M + n) * g.S + tl.s0 + l);
+                if (accumulate) v = cadd<T>(v, out[off]);
+                out[off] = v;
+            }
+        }
+        __syncthreads();  // the next tile overwrites the staged rounds
+    }
+}
+
 // EA in register form: the E values of every q are combined at once into the lane's M / G = P
 // outputs nbar = n2 + G k (the accumulate of (FFpsi) along this axis):
 //   out[nbar] = sum_q Tf_q[nbar] E_q[r(nbar)],  r(nbar) = (nbar lg) mod P.
@@ -2439,7 +2630,7 @@ hipError_t launch_asr_T(const void* in, void* out, const AxisDev& ax, const Pass
 // with value bitrev3(n2)). There is no workgroup barrier after the table rows of the pass (TA, HT,
 // Tf) are staged in LDS, once per workgroup of a persistent grid.
 constexpr int kEwWaves = 8;
-constexpr size_t kEwStageBytes = 32768;  // HT rows of the pass staged when they fit
+constexpr size_t kEwStageBytes = 65536;  // HT rows of the pass staged when they fit
 
 template <typename T, int P, bool HST>
 __global__ __launch_bounds__(kEwWaves * kWave) void k_EAW(const C<T>* __restrict__ in, C<T>* __restrict__ out,
@@ -2993,6 +3184,49 @@ hipError_t launch_pass_erg(Kind kind, bool dbl, const void* in, void* out, const
                    : launch_erg_T<float, true>(in, out, ax, g, accumulate, rho, st);
     return dbl ? launch_erg_T<double, false>(in, out, ax, g, accumulate, rho, st)
                : launch_erg_T<float, false>(in, out, ax, g, accumulate, rho, st);
+}
+
+size_t ehg_lds_bytes(bool dbl, int M, int g, int qn, bool strided) {
+    const int P = M / g, L = g * P / 8, TL = kThreads / L;
+    return ((size_t)qn * P + (size_t)kErStage * L * 9 + (strided ? (size_t)kErStage * TL * P : 0)) * (dbl ? 16 : 8);
+}
+
+template <typename T, int P, int LG>
+hipError_t launch_ehg(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, hipStream_t st) {
+    const size_t lds = ehg_lds_bytes(sizeof(T) == 8, ax.M, ax.g, g.qn, g.S != 1);
+    auto k = k_EHG<T, P, LG>;
+    hipError_t e = prep_lds((const void*)k, lds);
+    if (e != hipSuccess) return e;
+    int64_t blocks = ((g.Qin * g.ntiles + 7) / 8) * 8;
+    if (g.max_blocks > 0 && blocks > g.max_blocks) blocks = (g.max_blocks + 7) / 8 * 8;
+    if (blocks > (1 << 22)) blocks = 1 << 22;
+    hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), lds, st, (const C<T>*)in,
+                       (C<T>*)out, ax, g, accumulate, (const C<T>*)ax.TA, (const C<T>*)ax.HT);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ehg_T(const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate, hipStream_t st) {
+    switch (ax.g * 100 + ax.P) {
+        case 216: return launch_ehg<T, 16, 1>(in, out, ax, g, accumulate, st);
+        case 232: return launch_ehg<T, 32, 1>(in, out, ax, g, accumulate, st);
+        case 264: return launch_ehg<T, 64, 1>(in, out, ax, g, accumulate, st);
+        case 416: return launch_ehg<T, 16, 2>(in, out, ax, g, accumulate, st);
+        case 432: return launch_ehg<T, 32, 2>(in, out, ax, g, accumulate, st);
+        case 464: return launch_ehg<T, 64, 2>(in, out, ax, g, accumulate, st);
+        case 816: return launch_ehg<T, 16, 3>(in, out, ax, g, accumulate, st);
+        case 832: return launch_ehg<T, 32, 3>(in, out, ax, g, accumulate, st);
+        case 864: return launch_ehg<T, 64, 3>(in, out, ax, g, accumulate, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pass_ehg(bool dbl, const void* in, void* out, const AxisDev& ax, const PassGeom& g, int accumulate,
+                           hipStream_t st) {
+    if (!erg_applicable(dbl, ax.M, ax.g) || !ax.HT || !ax.tw || g.TS != erg_tile_lines(ax.M, ax.g)) return hipErrorInvalidValue;
+    if ((int64_t)ehg_lds_bytes(dbl, ax.M, ax.g, g.qn, g.S != 1) > lds_limit_bytes()) return hipErrorInvalidValue;
+    if (((g.Qin * g.ntiles + 7) / 8) * 8 >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    return dbl ? launch_ehg_T<double>(in, out, ax, g, accumulate, st) : launch_ehg_T<float>(in, out, ax, g, accumulate, st);
 }
 
 bool erw_applicable(bool dbl, int M, int g) {

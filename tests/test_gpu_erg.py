@@ -85,3 +85,47 @@ def test_erg_partial_term_ranges(fx, case, dtype, tol, monkeypatch):
     torch.cuda.synchronize()
     ref = oracle.expand(f.astype(np.complex128), dx, 1.0, t, lam)
     assert rel(acc.cpu().numpy().astype(np.complex128), ref) <= tol
+
+
+ADJ_CASES = [
+    # shape, lam, dx, t (the adjoint schedule runs EH through k_EHG on the listed axes)
+    ((64,), (50,), (1.0,), 40.0),                   # g = 2, P = 32, contiguous
+    ((256,), (20,), (0.9,), 30.0),                  # g = 4, P = 64
+    ((64, 12), (50, 3), (1.0, 0.9), 30.0),          # strided (g = 2)
+    ((6, 256), (3, 20), (1.1, 1.0), 50.0),          # contiguous, after another axis
+    ((256, 64), (20, 50), (1.0, 1.0), 25.0),        # both axes (g = 4 strided, g = 2 contiguous)
+    ((128, 10), (24, 5), (0.9, 1.0), 15.0),         # g = 8, P = 16, strided
+]
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)])
+@pytest.mark.parametrize("case", range(len(ADJ_CASES)))
+def test_ehg_adjoint_matches_oracle(fx, case, dtype, tol, monkeypatch):
+    shape, lam, dx, t = ADJ_CASES[case]
+    monkeypatch.setenv("FX_ERW", "2")
+    plan = fx.Plan(shape, dx, 1.0, t, lam, dtype=dtype)
+    adj = json.loads(plan.describe())["adjoint_passes"]
+    assert any(p["kind"] == "EH" and p["kernel"] == "k_EHG" for p in adj), adj
+    npdt = np.complex128 if dtype == torch.complex128 else np.complex64
+    y = workloads.random_field(shape, 1500 + case).astype(npdt)
+    g = plan.expand_adjoint(torch.from_numpy(y).cuda())
+    torch.cuda.synchronize()
+    ref = oracle.expand_adjoint(y.astype(np.complex128), dx, 1.0, t, lam)
+    assert rel(g.cpu().numpy().astype(np.complex128), ref) <= tol
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)])
+def test_ehg_adjoint_blocked(fx, dtype, tol, monkeypatch):
+    # a tiny workspace splits the outer magnification index into blocks: the adjoint E pass then
+    # starts at a term index qb > 0 and accumulates into its output
+    monkeypatch.setenv("FX_WORKSPACE_MB", "1")
+    shape, lam, dx, t = (256, 256), (20, 20), (1.0, 1.0), 23.0
+    plan = fx.Plan(shape, dx, 1.0, t, lam, dtype=dtype)
+    d = json.loads(plan.describe())
+    assert d["outer_block"] < 20 and any(p["kernel"] == "k_EHG" for p in d["adjoint_passes"]), d
+    npdt = np.complex128 if dtype == torch.complex128 else np.complex64
+    y = workloads.random_field(shape, 1999).astype(npdt)
+    g = plan.expand_adjoint(torch.from_numpy(y).cuda())
+    torch.cuda.synchronize()
+    ref = oracle.expand_adjoint(y.astype(np.complex128), dx, 1.0, t, lam)
+    assert rel(g.cpu().numpy().astype(np.complex128), ref) <= tol
