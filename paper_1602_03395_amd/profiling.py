@@ -90,9 +90,21 @@ def kernels_hash() -> str:
     return h.hexdigest()[:16]
 
 
-# pass kernels: k_E, k_E2 (power-of-two), k_Ect (3*2^k), k_ER (register form), k_EA*, k_A,
-# k_AS / k_ASR / k_ASK (structured accumulates), k_AA (fused two-axis accumulate), adjoints
-PASS_KIND = re.compile(r"\bk_(EAH|EA|EH|AH|AAH|AA|E|A)(?:2|ct|S|R|SR|SK)?<")
+# pass kernels: k_E, k_E2 (power-of-two), k_Ect (3*2^k), k_ER / k_ERW / k_ERG (register forms), k_EA*,
+# k_EAW, k_A, k_AS / k_ASR / k_ASK (structured accumulates), k_AA (fused two-axis accumulate), adjoints
+# (k_EH*, k_EHG, k_AH*)
+PASS_KIND = re.compile(r"\bk_(EAH|EA|EH|AH|AAH|AA|E|A)(?:2|ct|S|R|SR|SK|RW|RG|W|G)?<")
+
+
+def pass_kind(name: str):
+    """Kind of the pass a kernel name runs (E, EA, A, AA, EH, AH, ...), or None. k_ERG serves E and
+    EA; its last template argument tells them apart."""
+    m = PASS_KIND.search(name)
+    if not m:
+        return None
+    if "k_ERG<" in name and re.search(r"k_ERG<[^>]*,\s*true\s*>", name):
+        return "EA"
+    return m.group(1)
 
 
 def _pass_dispatches(path: str, counter: str):
@@ -101,9 +113,9 @@ def _pass_dispatches(path: str, counter: str):
     for r in csv.DictReader(open(path)):
         if r.get("Counter_Name") != counter:
             continue
-        m = PASS_KIND.search(r["Kernel_Name"])
-        if m:
-            out.append((int(r["Dispatch_Id"]), m.group(1), float(r["Counter_Value"])))
+        kind = pass_kind(r["Kernel_Name"])
+        if kind:
+            out.append((int(r["Dispatch_Id"]), kind, float(r["Counter_Value"])))
     out.sort()
     return out
 
@@ -230,7 +242,7 @@ def traffic_kernels(fetch_csv: str, write_csv: str, copy_mib: float, out_json: s
 def passes(trace_csv: str, calls: int) -> str:
     rows = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"])
                   for r in csv.DictReader(open(trace_csv)))
-    seq = [(m.group(1), (e - b) / 1e3) for b, e, n in rows for m in [PASS_KIND.search(n)] if m]
+    seq = [(k, (e - b) / 1e3) for b, e, n in rows for k in [pass_kind(n)] if k]
     per = max(1, len(seq) // max(1, calls))
     kinds = [k for k, _ in seq[:per]]
     acc = collections.OrderedDict()
