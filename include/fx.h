@@ -352,6 +352,15 @@ fx_status fx_batch_class(fx_batch* batch, int32_t i, fx_plan** plan, int32_t* me
 fx_status fx_batch_class_members(const fx_batch* batch, int32_t i, int32_t* members, int32_t max);
 
 /*
+ * Overrides the number of lane streams the classes of a batch run on (profiling: lanes = 1 runs
+ * every class on the caller's stream, one kernel at a time, so that per-pass timing measures each
+ * kernel alone on the device; 0 restores the tuned value). Values above the number of classes are
+ * clamped. Drops the captured graph (the next fx_batch_run captures again). Errors: FX_EINVAL
+ * (NULL batch, negative lanes).
+ */
+fx_status fx_batch_set_lanes(fx_batch* batch, int32_t lanes);
+
+/*
  * Per-pass timing (profiling aid). With enable != 0 every pass launch of this
  * plan is bracketed by two HIP events recorded on the stream the pass is
  * launched on. fx_plan_pass_times waits for the recorded events and returns,

@@ -95,6 +95,7 @@ def _load():
         "fx_batch_class": (ctypes.c_int, [vp, ctypes.c_int32, P(vp), P(ctypes.c_int32), P(ctypes.c_int64),
                                           P(ctypes.c_int32)]),
         "fx_batch_class_members": (ctypes.c_int, [vp, ctypes.c_int32, P(ctypes.c_int32), ctypes.c_int32]),
+        "fx_batch_set_lanes": (ctypes.c_int, [vp, ctypes.c_int32]),
         "fx_plan_describe": (ctypes.c_int, [vp, ctypes.c_char_p, ctypes.c_size_t]),
         "fx_plan_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
         "fx_plan_pass_times": (ctypes.c_int, [vp, P(ctypes.c_int32), P(ctypes.c_int64), P(ctypes.c_double),

@@ -398,6 +398,11 @@ class Batch:
             out.append({"plan": plan, "members": members, "group": int(grp.value), "lane": int(lane.value)})
         return out
 
+    def set_lanes(self, lanes: int):
+        """Lane streams the classes run on (1: one kernel at a time on the caller's stream, for
+        per-pass timing of each kernel alone; 0: the tuned value), see ``fx_batch_set_lanes``."""
+        L.check(L.lib.fx_batch_set_lanes(self._h, int(lanes)), "fx_batch_set_lanes")
+
     def run(self, psis, psi_outs=None, rho_outs=None, want_psi=True, want_rho=True):
         n = len(self.shapes)
         if len(psis) != n:

@@ -29,8 +29,10 @@
 // runs one full item eagerly three times, timed with HIP events, and the best of
 // the last two runs per realization counts. Then the lane concurrency (all
 // classes in parallel, or one after the other) is decided on whole runs of the
-// batch, alternating between the two forms. Results are cached per process and,
-// with FX_AUTOTUNE_CACHE=<file>, on disk.
+// batch, alternating between the two forms; before that, whether the largest class
+// runs as two replicas (two plans and workspaces, half of its items each, on two
+// lanes, so that two of its items run at once) is decided the same way. Results are
+// cached per process and, with FX_AUTOTUNE_CACHE=<file>, on disk.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -68,6 +70,7 @@ struct Tune {
 std::mutex g_tune_mu;
 std::map<std::string, Tune> g_tune;
 std::map<std::string, int> g_conc;
+std::map<std::string, int> g_repl;  // replicas of the largest class per batch key
 bool g_tune_loaded = false;
 
 std::string class_key(const fx_problem& p, size_t members) {
@@ -98,9 +101,10 @@ void load_tune_cache() {
             t.qblock = qb;
             g_tune[key] = t;
         } else if (kind == "batch") {
-            int c = 1;
-            if (!(f >> c)) break;
+            int c = 1, r = 1;
+            if (!(f >> c >> r)) break;
             g_conc[key] = c;
+            g_repl[key] = r;
         } else {
             break;
         }
@@ -115,7 +119,10 @@ void save_tune_cache() {
         f << "class " << kv.first << " " << kv.second.ts_target << " " << kv.second.persist << " "
           << (kv.second.allow_split ? 1 : 0) << " " << (kv.second.use_cfp ? 1 : 0) << " " << kv.second.use_eas << " "
           << (kv.second.use_eaw ? 1 : 0) << " " << kv.second.group << " " << kv.second.qblock << "\n";
-    for (const auto& kv : g_conc) f << "batch " << kv.first << " " << kv.second << "\n";
+    for (const auto& kv : g_conc) {
+        auto r = g_repl.find(kv.first);
+        f << "batch " << kv.first << " " << kv.second << " " << (r != g_repl.end() ? r->second : 1) << "\n";
+    }
 }
 
 bool same_problem(const fx_problem& a, const fx_problem& b) {
@@ -146,6 +153,7 @@ struct fx_batch {
     bool dbl = false;
     std::vector<Class> classes;  // in issue order (largest cost first)
     int concurrency = 1;         // lanes in use (1: every class on the caller's stream)
+    int tuned_concurrency = 1;   // the value batch creation chose
     std::vector<hipStream_t> lanes;
     hipEvent_t fork = nullptr;
     std::vector<hipEvent_t> joins;
@@ -422,6 +430,75 @@ double time_full(fx_batch* b, int lanes, hipStream_t st) {
     return ms_out;
 }
 
+// Adds a lane stream (and its join event) for one more class.
+fx_status add_lane(fx_batch* b) {
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        set_error("creating a batch lane failed");
+        return FX_EDEVICE;
+    }
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        set_error("creating a batch lane failed");
+        return FX_EDEVICE;
+    }
+    b->lanes.push_back(s);
+    b->joins.push_back(e);
+    return FX_OK;
+}
+
+// Splits class k into two replicas: the second half of its members (a whole number of items) goes to
+// a copy of the class with a plan and workspace of its own, issued right after it on a lane of its
+// own, so that two items of the class run at once. Returns FX_EUNSUPPORTED when the class has fewer
+// than two items.
+fx_status split_class(fx_batch* b, size_t k, hipStream_t st) {
+    fx_batch::Class& c = b->classes[k];
+    const size_t G = (size_t)c.group;
+    const size_t items = (c.members.size() + G - 1) / G;
+    if (items < 2) return FX_EUNSUPPORTED;
+    fx_batch::Class r;
+    fx_status s = fx_plan_create(&c.plan->prob_in, &r.plan);
+    if (s != FX_OK) return s;
+    r.plan->prob_in = c.plan->prob_in;
+    r.tune = c.tune;
+    r.group = c.group;
+    r.cost = c.cost;
+    const size_t keep = ((items + 1) / 2) * G;
+    r.members.assign(c.members.begin() + keep, c.members.end());
+    apply_tune(r.plan, r.tune, r.group);
+    if ((s = ensure_workspace(r.plan)) == FX_OK) s = ensure_stage(b, r, r.group);
+    if (s == FX_OK) s = add_lane(b);
+    if (s != FX_OK) {
+        fx_plan_destroy(r.plan);
+        if (r.stage) (void)hipFree(r.stage);
+        return s;
+    }
+    b->classes[k].members.resize(keep);
+    b->classes.insert(b->classes.begin() + (k + 1), r);
+    for (size_t i = 0; i < b->classes.size(); ++i) b->classes[i].lane = (int)i;
+    // one eager item before any capture (the replica's workspace is new)
+    fx_batch::Class& rr = b->classes[k + 1];
+    std::vector<const void*> in(b->n, rr.stage);
+    return run_group(b, rr, 0, std::min(G, rr.members.size()), in.data(), nullptr, nullptr, st);
+}
+
+// Undoes split_class: the replica's members go back to the class, its plan, staging and lane are freed.
+void merge_class(fx_batch* b, size_t k) {
+    fx_batch::Class& r = b->classes[k + 1];
+    b->classes[k].members.insert(b->classes[k].members.end(), r.members.begin(), r.members.end());
+    fx_plan_destroy(r.plan);
+    if (r.stage) (void)hipFree(r.stage);
+    b->classes.erase(b->classes.begin() + (k + 1));
+    if (!b->lanes.empty()) {
+        (void)hipStreamDestroy(b->lanes.back());
+        (void)hipEventDestroy(b->joins.back());
+        b->lanes.pop_back();
+        b->joins.pop_back();
+    }
+    for (size_t i = 0; i < b->classes.size(); ++i) b->classes[i].lane = (int)i;
+}
+
 // Every output range (psi_out[i], rho_out[i]) must be disjoint from every other output range and
 // from every input; inputs may be shared between realizations. Sort-and-sweep over the ranges.
 fx_status check_batch_disjoint(const fx_batch* b, const void* const* psi0, void* const* psi_out,
@@ -568,29 +645,64 @@ fx_status fx_batch_create(const fx_problem* probs, int32_t n, fx_batch** out) {
         }
         if (s != FX_OK) return fail(s);
     }
+    // replicas of the largest class: two items of it at once, on two lanes, when whole runs say so
+    {
+        auto it = g_repl.find(bkey);
+        int repl = 1;
+        if (it != g_repl.end()) {
+            repl = it->second;
+            if (repl > 1) {
+                fx_status s2 = split_class(b, 0, st);
+                if (s2 != FX_OK && s2 != FX_EUNSUPPORTED) return fail(s2);
+            }
+        } else if (tune && b->classes[0].members.size() >= 2 * (size_t)b->classes[0].group) {
+            const int L1 = (int)b->classes.size();
+            double t1 = -1.0, t2 = -1.0;
+            for (int rep = 0; rep < 3; ++rep) {
+                const double a = time_full(b, L1, st);
+                if (rep > 0 && a >= 0 && (t1 < 0 || a < t1)) t1 = a;
+            }
+            fx_status s2 = split_class(b, 0, st);
+            if (s2 == FX_OK) {
+                const int L2 = (int)b->classes.size();
+                for (int rep = 0; rep < 3; ++rep) {
+                    const double a = time_full(b, L2, st);
+                    if (rep > 0 && a >= 0 && (t2 < 0 || a < t2)) t2 = a;
+                }
+                if (t2 >= 0 && (t1 < 0 || t2 < t1)) repl = 2;
+                else merge_class(b, 0);
+            } else if (s2 != FX_EUNSUPPORTED) {
+                return fail(s2);
+            }
+            g_repl[bkey] = repl;
+            dirty = true;
+        }
+    }
+    const int ncl = (int)b->classes.size();
     // lane concurrency: every class on its own lane, or all on the caller's stream
     b->concurrency = 1;
-    if (ncls > 1) {
+    if (ncl > 1) {
         auto it = g_conc.find(bkey);
         if (it != g_conc.end()) {
-            b->concurrency = std::min(it->second, ncls);
+            b->concurrency = std::min(it->second, ncl);
         } else if (tune) {
             // whole runs, alternating between the two forms, best of two each after one warm-up
             double t1 = -1.0, tn = -1.0;
             for (int rep = 0; rep < 3; ++rep) {
-                const double a = time_full(b, 1, st), c = time_full(b, ncls, st);
+                const double a = time_full(b, 1, st), c = time_full(b, ncl, st);
                 if (rep == 0) continue;
                 if (a >= 0 && (t1 < 0 || a < t1)) t1 = a;
                 if (c >= 0 && (tn < 0 || c < tn)) tn = c;
             }
-            b->concurrency = (tn >= 0 && (t1 < 0 || tn < t1)) ? ncls : 1;
+            b->concurrency = (tn >= 0 && (t1 < 0 || tn < t1)) ? ncl : 1;
             g_conc[bkey] = b->concurrency;
             dirty = true;
         } else {
-            b->concurrency = ncls;
+            b->concurrency = ncl;
         }
     }
-    if (const char* e = std::getenv("FX_BATCH_LANES")) b->concurrency = std::max(1, std::min(ncls, std::atoi(e)));
+    if (const char* e = std::getenv("FX_BATCH_LANES")) b->concurrency = std::max(1, std::min(ncl, std::atoi(e)));
+    b->tuned_concurrency = b->concurrency;
     if (hipStreamSynchronize(st) != hipSuccess) {
         set_error("batch set-up run failed");
         return fail(FX_EDEVICE);
@@ -683,6 +795,18 @@ fx_status fx_batch_class(fx_batch* b, int32_t i, fx_plan** plan, int32_t* member
     if (members) *members = (int32_t)c.members.size();
     if (group) *group = c.group;
     if (lane) *lane = b->concurrency > 1 ? c.lane % b->concurrency : 0;
+    return FX_OK;
+}
+
+fx_status fx_batch_set_lanes(fx_batch* b, int32_t lanes) {
+    if (!b) { set_error("batch is NULL"); return FX_EINVAL; }
+    if (lanes < 0) { set_error("lanes must be >= 0"); return FX_EINVAL; }
+    const int ncl = (int)b->classes.size();
+    const int want = lanes == 0 ? b->tuned_concurrency : std::min(lanes, ncl);
+    if (want != b->concurrency) {
+        drop_graph(b);
+        b->concurrency = want;
+    }
     return FX_OK;
 }
 

@@ -114,6 +114,14 @@ def test_c4_ensemble_fp32_batched_against_oracle(fx):
         torch.cuda.synchronize()
         for a, r in zip(first_rho, rhos):
             assert torch.equal(a, r)
+    # one lane (every class on the caller's stream, one kernel at a time): the same bits
+    b.set_lanes(1)
+    with torch.cuda.stream(stream):
+        b.run(psis, psi_outs=outs, rho_outs=rhos)
+    torch.cuda.synchronize()
+    for a, r in zip(first_rho, rhos):
+        assert torch.equal(a, r)
+    b.set_lanes(0)
 
 
 def test_c4_ensemble_fp64_batched_against_oracle(fx):
