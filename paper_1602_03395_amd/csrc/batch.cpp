@@ -30,9 +30,10 @@
 // the last two runs per realization counts. Then the lane concurrency (all
 // classes in parallel, or one after the other) is decided on whole runs of the
 // batch, alternating between the two forms; before that, whether the largest class
-// runs as two replicas (two plans and workspaces, half of its items each, on two
-// lanes, so that two of its items run at once) is decided the same way. Results are
-// cached per process and, with FX_AUTOTUNE_CACHE=<file>, on disk.
+// runs as two or three replicas (plans and workspaces of their own, a share of its
+// items each, on lanes of their own, so that several of its items run at once) is
+// decided on whole runs as well. Results are cached per process and, with
+// FX_AUTOTUNE_CACHE=<file>, on disk.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -448,15 +449,15 @@ fx_status add_lane(fx_batch* b) {
     return FX_OK;
 }
 
-// Splits class k into two replicas: the second half of its members (a whole number of items) goes to
-// a copy of the class with a plan and workspace of its own, issued right after it on a lane of its
-// own, so that two items of the class run at once. Returns FX_EUNSUPPORTED when the class has fewer
-// than two items.
-fx_status split_class(fx_batch* b, size_t k, hipStream_t st) {
+// Splits class k: its members after the first keep_items items (0: half of them) go to a copy of the
+// class with a plan and workspace of its own, issued right after it on a lane of its own, so that
+// items of both run at once. Returns FX_EUNSUPPORTED when either part would be empty.
+fx_status split_class(fx_batch* b, size_t k, hipStream_t st, size_t keep_items = 0) {
     fx_batch::Class& c = b->classes[k];
     const size_t G = (size_t)c.group;
     const size_t items = (c.members.size() + G - 1) / G;
-    if (items < 2) return FX_EUNSUPPORTED;
+    if (keep_items == 0) keep_items = (items + 1) / 2;
+    if (items < 2 || keep_items >= items) return FX_EUNSUPPORTED;
     fx_batch::Class r;
     fx_status s = fx_plan_create(&c.plan->prob_in, &r.plan);
     if (s != FX_OK) return s;
@@ -464,7 +465,7 @@ fx_status split_class(fx_batch* b, size_t k, hipStream_t st) {
     r.tune = c.tune;
     r.group = c.group;
     r.cost = c.cost;
-    const size_t keep = ((items + 1) / 2) * G;
+    const size_t keep = keep_items * G;
     r.members.assign(c.members.begin() + keep, c.members.end());
     apply_tune(r.plan, r.tune, r.group);
     if ((s = ensure_workspace(r.plan)) == FX_OK) s = ensure_stage(b, r, r.group);
@@ -645,34 +646,57 @@ fx_status fx_batch_create(const fx_problem* probs, int32_t n, fx_batch** out) {
         }
         if (s != FX_OK) return fail(s);
     }
-    // replicas of the largest class: two items of it at once, on two lanes, when whole runs say so
+    // replicas of the largest class (R items of it at once, on R lanes), when whole runs say so
     {
+        // R replicas of class 0 from one: items split into near-equal whole-item parts
+        auto make_replicas = [&](int R) -> fx_status {
+            for (int r = 0; r + 1 < R; ++r) {
+                const fx_batch::Class& c = b->classes[r];
+                const size_t items = (c.members.size() + (size_t)c.group - 1) / (size_t)c.group;
+                fx_status s2 = split_class(b, (size_t)r, st, (items + (size_t)(R - r) - 1) / (size_t)(R - r));
+                if (s2 != FX_OK) return s2;
+            }
+            return FX_OK;
+        };
+        auto undo_replicas = [&](int R) {
+            for (int r = R - 2; r >= 0; --r) merge_class(b, (size_t)r);
+        };
+        auto best_of = [&]() {
+            const int L = (int)b->classes.size();
+            double t = -1.0;
+            for (int rep = 0; rep < 3; ++rep) {
+                const double a = time_full(b, L, st);
+                if (rep > 0 && a >= 0 && (t < 0 || a < t)) t = a;
+            }
+            return t;
+        };
         auto it = g_repl.find(bkey);
         int repl = 1;
-        if (it != g_repl.end()) {
-            repl = it->second;
+        const char* forced = std::getenv("FX_BATCH_REPLICAS");
+        if (forced || it != g_repl.end()) {
+            repl = forced ? std::max(1, std::min(4, std::atoi(forced))) : it->second;
             if (repl > 1) {
-                fx_status s2 = split_class(b, 0, st);
+                fx_status s2 = make_replicas(repl);
                 if (s2 != FX_OK && s2 != FX_EUNSUPPORTED) return fail(s2);
             }
         } else if (tune && b->classes[0].members.size() >= 2 * (size_t)b->classes[0].group) {
-            const int L1 = (int)b->classes.size();
-            double t1 = -1.0, t2 = -1.0;
-            for (int rep = 0; rep < 3; ++rep) {
-                const double a = time_full(b, L1, st);
-                if (rep > 0 && a >= 0 && (t1 < 0 || a < t1)) t1 = a;
-            }
-            fx_status s2 = split_class(b, 0, st);
-            if (s2 == FX_OK) {
-                const int L2 = (int)b->classes.size();
-                for (int rep = 0; rep < 3; ++rep) {
-                    const double a = time_full(b, L2, st);
-                    if (rep > 0 && a >= 0 && (t2 < 0 || a < t2)) t2 = a;
+            double best_t = best_of();
+            for (int R = 2; R <= 3; ++R) {
+                fx_status s2 = make_replicas(R);
+                if (s2 == FX_EUNSUPPORTED) { undo_replicas((int)b->classes.size() - ncls + 1); break; }
+                if (s2 != FX_OK) return fail(s2);
+                const double t = best_of();
+                undo_replicas(R);
+                if (t >= 0 && (best_t < 0 || t < best_t * 0.99)) {
+                    best_t = t;
+                    repl = R;
+                } else {
+                    break;
                 }
-                if (t2 >= 0 && (t1 < 0 || t2 < t1)) repl = 2;
-                else merge_class(b, 0);
-            } else if (s2 != FX_EUNSUPPORTED) {
-                return fail(s2);
+            }
+            if (repl > 1) {
+                fx_status s2 = make_replicas(repl);
+                if (s2 != FX_OK) return fail(s2);
             }
             g_repl[bkey] = repl;
             dirty = true;
