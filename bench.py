@@ -568,12 +568,6 @@ def main():
     roofline = None
     if pass_rows:
         dom = max(pass_rows, key=lambda r: r["avg_ms"] * r["launches_per_step"])
-        alone = [r for r in rows_alone if r["class"] == dom["class"] and r["key"] == dom["key"]]
-        if alone:
-            a = alone[0]
-            roofline["alone"] = {"achieved": a["tflops"], "frac": a["tflops"] / PEAK_FP32_TFLOPS,
-                                 "avg_launch_ms": a["avg_ms"],
-                                 "note": "the same launches with the classes one after the other on one stream"}
         ai = dom["flops"] / max(dom["bytes"], 1)
         if ai >= ridge:
             roofline = {"bound": "alu", "achieved": dom["tflops"], "peak": peak_alu, "unit": "TFLOP/s",
