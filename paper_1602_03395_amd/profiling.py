@@ -254,10 +254,34 @@ def passes(trace_csv: str, calls: int) -> str:
     return "\n".join(out)
 
 
+def phases(trace_csv: str, kernel: str, per_run: int, labels):
+    """Average duration (us) of one kernel's dispatches per run, counted from the end of the trace:
+    the last per_run dispatches belong to labels[-1], the per_run before them to labels[-2], ...; a
+    label "name*k" covers k runs. What precedes them is reported as "earlier"."""
+    d = sorted((int(r["Start_Timestamp"]), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+               for r in csv.DictReader(open(trace_csv)) if short_name(r["Kernel_Name"]) == kernel)
+    durs = [x for _, x in d]
+    out = ["| dispatches | runs | avg us |", "|---|---:|---:|"]
+    end = len(durs)
+    rows = []
+    for lab in reversed(labels):
+        name, _, k = lab.partition("*")
+        k = int(k) if k else 1
+        seg = durs[max(0, end - k * per_run):end]
+        end -= len(seg)
+        if seg:
+            rows.append("| %s | %d | %.1f |" % (name, k, sum(seg) / len(seg)))
+    if end > 0:
+        rows.append("| earlier (set-up) | | %.1f |" % (sum(durs[:end]) / end))
+    return "\n".join(out + list(reversed(rows)))
+
+
 if __name__ == "__main__":
     cmd = sys.argv[1]
     if cmd == "stats":
         print(stats(sys.argv[2]))
+    elif cmd == "phases":
+        print(phases(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5:]))
     elif cmd == "passes":
         print(passes(sys.argv[2], int(sys.argv[3])))
     elif cmd == "counters":
