@@ -232,10 +232,13 @@ template <typename T, bool INV> struct RegDFT<T, 12, INV> {
 
 // a(lane ^ m) within a wavefront. Masks 1 and 2 stay inside a quad of lanes and use a DPP
 // quad permutation (a VALU move without a trip through the LDS crossbar); other masks use
-// ds_bpermute through __shfl_xor. m is uniform over the wavefront.
+// ds_bpermute through __shfl_xor. m is uniform over the wavefront. The moves set bound_ctrl
+// (a disabled source lane reads 0; every call site runs with the whole quad active, so the
+// values are those of the plain move), which lets the compiler fold the move into the VOP2
+// add or subtract that consumes it as a DPP operand: one VALU instruction instead of two.
 __device__ __forceinline__ int dpp_quad_xor(int v, int m) {
-    return (m == 1) ? __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false)   // quad_perm [1, 0, 3, 2]
-                    : __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2, 3, 0, 1]
+    return (m == 1) ? __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true)   // quad_perm [1, 0, 3, 2]
+                    : __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);  // quad_perm [2, 3, 0, 1]
 }
 __device__ __forceinline__ float xor_lane(float v, int m) {
     if (m == 1 || m == 2) return __int_as_float(dpp_quad_xor(__float_as_int(v), m));
