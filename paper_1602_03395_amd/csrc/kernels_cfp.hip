@@ -395,7 +395,9 @@ __device__ __forceinline__ C<T> lane_twiddles_x(C<T>* wst, int n2, const C<T>* t
     C<T> c = mk<T>(1, 0);
 #pragma unroll
     for (int s = 0; s < LP; ++s) {
-        const C<T> t = tw[(n2 & ((1 << s) - 1)) * (M >> (s + 1))];  // exp(-2 pi i (n2 mod 2^s) / 2^(s+1))
+        // exp(-2 pi i (n2 mod 2^s) / 2^(s+1)); exactly 1 at stage 0, whose factor is then the real
+        // sign +-1 (lane_bfly relies on it)
+        const C<T> t = (s == 0) ? mk<T>(1, 0) : tw[(n2 & ((1 << s) - 1)) * (M >> (s + 1))];
         const C<T> w = INV ? mk<T>(t.x, -t.y) : t;
         if ((n2 >> s) & 1) {
             wst[s] = mk<T>(-w.x, w.y);  // -conj(w)
@@ -415,10 +417,19 @@ __device__ __forceinline__ C<T> lane_twiddles_x(C<T>* wst, int n2, const C<T>* t
 // a_up - conj(w) a_lo = -conj(w) (a_lo - w a_up), its true output times the unit factor
 // -conj(w). The factors of the stages where the lane is the upper one multiply up to c; the
 // result is multiplied by conj(c) = 1 / c at the end (fin from lane_twiddles_x).
+// One butterfly stage of these lane transforms: own + w * partner, the partner d lanes away. At
+// stage 0 (s = 0) lane_twiddles_x gives the real factor w = +-1, which takes two FMAs, not four.
+template <typename T>
+__device__ __forceinline__ C<T> lane_bfly(C<T> a, C<T> w, int d, int s) {
+    const C<T> b = shfl_xor_c<T>(a, d);
+    if (s == 0) return mk<T>(a.x + w.x * b.x, a.y + w.x * b.y);
+    return cfma<T>(a, w, b);
+}
+
 template <typename T, int LP>
 __device__ __forceinline__ C<T> lane_idft_x(C<T> a, const C<T>* wst, C<T> fin) {
 #pragma unroll
-    for (int s = 0; s < LP; ++s) a = cfma<T>(a, wst[s], shfl_xor_c<T>(a, 1 << s));
+    for (int s = 0; s < LP; ++s) a = lane_bfly<T>(a, wst[s], 1 << s, s);
     return cmul<T>(a, fin);
 }
 
@@ -886,10 +897,10 @@ __global__ __launch_bounds__(kThreads) void k_ERW(const C<T>* __restrict__ in, C
                 }
                 // inverse: over k2 (lo lanes), twiddle, over k1 (n2 lanes)
 #pragma unroll
-                for (int s = 0; s < LNL; ++s) a = cfma<T>(a, w1[s], shfl_xor_c<T>(a, 1 << s));
+                for (int s = 0; s < LNL; ++s) a = lane_bfly<T>(a, w1[s], 1 << s, s);
                 a = cmul<T>(a, m2[0]);
 #pragma unroll
-                for (int s = 0; s < 3; ++s) a = cfma<T>(a, w3[s], shfl_xor_c<T>(a, NL << s));
+                for (int s = 0; s < 3; ++s) a = lane_bfly<T>(a, w3[s], NL << s, s);
                 a = cmul<T>(a, fin3);
             } else {
                 // the other two n2 bits summed in full: the lane holds k1 = V/2 b0 + j, j < V/2
@@ -901,7 +912,7 @@ __global__ __launch_bounds__(kThreads) void k_ERW(const C<T>* __restrict__ in, C
 #pragma unroll
                 for (int j = 0; j < HV; ++j) {
 #pragma unroll
-                    for (int s = 0; s < LNL; ++s) v[j] = cfma<T>(v[j], w1[s], shfl_xor_c<T>(v[j], 1 << s));
+                    for (int s = 0; s < LNL; ++s) v[j] = lane_bfly<T>(v[j], w1[s], 1 << s, s);
                     v[j] = cmul<T>(v[j], m2[j]);
                 }
                 a = mk<T>(0, 0);
@@ -1080,10 +1091,10 @@ __global__ __launch_bounds__(kThreads) void k_ERG(const C<T>* __restrict__ in, C
             for (int t = 0; t < VG; ++t) {
                 C<T> b = v[t];
 #pragma unroll
-                for (int s = 0; s < LNL; ++s) b = cfma<T>(b, w1[s], shfl_xor_c<T>(b, 1 << s));
+                for (int s = 0; s < LNL; ++s) b = lane_bfly<T>(b, w1[s], 1 << s, s);
                 b = cmul<T>(b, m2[t]);
 #pragma unroll
-                for (int s = 0; s < LG; ++s) b = cfma<T>(b, w3[s], shfl_xor_c<T>(b, NL << s));
+                for (int s = 0; s < LG; ++s) b = lane_bfly<T>(b, w3[s], NL << s, s);
                 a[t] = cmul<T>(b, m3[t]);
             }
             RegDFT<T, VG, true>::run(a);
@@ -1331,7 +1342,7 @@ __global__ __launch_bounds__(kThreads) void k_EHG(const C<T>* __restrict__ in, C
 #pragma unroll
             for (int j = 0; j < V; ++j) {
 #pragma unroll
-                for (int s = 0; s < LNL; ++s) v[j] = cfma<T>(v[j], w1[s], shfl_xor_c<T>(v[j], 1 << s));
+                for (int s = 0; s < LNL; ++s) v[j] = lane_bfly<T>(v[j], w1[s], 1 << s, s);
                 v[j] = cmul<T>(v[j], it1[j]);
             }
             RegDFT<T, V, true>::run(v);
@@ -2074,7 +2085,7 @@ __global__ __launch_bounds__(kThreads) void k_AAHR(const C<T>* __restrict__ in, 
 #pragma unroll
         for (int st = 0; st < LK; ++st) {
 #pragma unroll
-            for (int c1 = 0; c1 < R; ++c1) h[c1] = cfma<T>(h[c1], wsv[st], shfl_xor_c<T>(h[c1], 1 << st));
+            for (int c1 = 0; c1 < R; ++c1) h[c1] = lane_bfly<T>(h[c1], wsv[st], 1 << st, st);
         }
 #pragma unroll
         for (int c1 = 0; c1 < R; ++c1) h[c1] = cmul<T>(h[c1], w1v[c1]);
@@ -2092,7 +2103,7 @@ __global__ __launch_bounds__(kThreads) void k_AAHR(const C<T>* __restrict__ in, 
 #pragma unroll
         for (int st = 0; st < LK; ++st) {
 #pragma unroll
-            for (int c1 = 0; c1 < R; ++c1) h[c1] = cfma<T>(h[c1], wsu[st], shfl_xor_c<T>(h[c1], 1 << st));
+            for (int c1 = 0; c1 < R; ++c1) h[c1] = lane_bfly<T>(h[c1], wsu[st], 1 << st, st);
         }
 #pragma unroll
         for (int c1 = 0; c1 < R; ++c1) h[c1] = cmul<T>(h[c1], w1u[c1]);
@@ -2307,7 +2318,7 @@ __global__ __launch_bounds__(kThreads) void k_AHK(const C<T>* __restrict__ in, C
 #pragma unroll
         for (int st = 0; st < LK; ++st) {
 #pragma unroll
-            for (int c1 = 0; c1 < R; ++c1) h[c1] = cfma<T>(h[c1], wst[st], shfl_xor_c<T>(h[c1], 1 << st));
+            for (int c1 = 0; c1 < R; ++c1) h[c1] = lane_bfly<T>(h[c1], wst[st], 1 << st, st);
         }
 #pragma unroll
         for (int c1 = 0; c1 < R; ++c1) h[c1] = cmul<T>(h[c1], w1[c1]);
