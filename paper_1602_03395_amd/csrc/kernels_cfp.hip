@@ -322,6 +322,80 @@ __device__ __forceinline__ void reduce_scatter_full(C<T>* v, int n2) {
     }
 }
 
+// a(lane ^ x) within each quad with x = 3 for quad lanes 0, 1 and x = 2 for lanes 2, 3: the quad
+// permutation [3, 2, 0, 1] (step 1 of reduce_scatter_rot)
+__device__ __forceinline__ int dpp_quad_3201(int v) { return __builtin_amdgcn_mov_dpp(v, 0x4B, 0xF, 0xF, true); }
+__device__ __forceinline__ float quad_3201(float v) { return __int_as_float(dpp_quad_3201(__float_as_int(v))); }
+__device__ __forceinline__ double quad_3201(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_quad_3201((int)(b & 0xffffffffLL));
+    const int hi = dpp_quad_3201((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// a(source lane) with the source given as a byte address (4 x lane index) for ds_bpermute
+__device__ __forceinline__ float bperm_lane(float v, int addr) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double bperm_lane(double v, int addr) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Lane spectral shifts of reduce_scatter_rot: s(n2) = bitrev(n2 mod P) over log2 P bits, and the part
+// s'(n2) = s(n2) - (n2 mod 2) P / 2 that a table arranged for reduce_scatter_x (odd rows already
+// turned by P / 2) still needs.
+template <int P>
+__device__ __forceinline__ int rot_shift(int n2) {
+    constexpr int L = ilog2c(P);
+    int s = 0;
+#pragma unroll
+    for (int b = 0; b < L; ++b) s |= ((n2 >> b) & 1) << (L - 1 - b);
+    return s;
+}
+template <int P>
+__device__ __forceinline__ int rot_shift_rest(int n2) { return rot_shift<P>(n2) - (n2 & 1) * (P / 2); }
+
+// ds_bpermute byte addresses of steps 2 .. log2 P - 1 of reduce_scatter_rot for the lane at wave
+// position lane (n2 = lane mod G, G >= P): partner n2 ^ x_j with x_1 = 2 or 3 (bit 1 of n2 set or
+// not) and x_j = 2^j | (bit j of n2 ? 0 : x_(j-1)).
+template <int P>
+__device__ __forceinline__ void rot_addrs(int* addr, int lane, int n2) {
+    constexpr int L = ilog2c(P);
+    int x = ((n2 >> 1) & 1) ? 2 : 3;
+#pragma unroll
+    for (int j = 2; j < L; ++j) {
+        x = (1 << j) | (((n2 >> j) & 1) ? 0 : x);
+        addr[j - 2] = (lane ^ x) * 4;
+    }
+}
+
+// Select-free reduce-scatter over the low log2 P lane bits for lanes whose P values come shifted by
+// s(n2) = bitrev(n2 mod P), i.e. position p holds spectral index (p + s) mod P (the lane's input
+// times exp(-2 pi i s n1 / P), its table row turned to match). Every step keeps positions [0, h)
+// and adds positions [h, 2h) of one partner lane: the lane pairs of each step hold equal indices
+// there and disjoint partial sums. Partners: step 0 n2 ^ 1, step 1 the quad permutation
+// [3, 2, 0, 1], later steps ds_bpermute at addr (rot_addrs). Lane n2 ends with the sum of index
+// bitrev(n2 mod P), the value reduce_step leaves it.
+template <typename T, int P>
+__device__ __forceinline__ void reduce_scatter_rot(C<T>* v, const int* addr) {
+    constexpr int L = ilog2c(P);
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        const int h = P >> (j + 1);
+#pragma unroll
+        for (int i = 0; i < h; ++i) {
+            const C<T> b = v[i + h];
+            C<T> r;
+            if (j == 0) r = shfl_xor_c<T>(b, 1);
+            else if (j == 1) r = mk<T>(quad_3201(b.x), quad_3201(b.y));
+            else r = mk<T>(bperm_lane(b.x, addr[j - 2]), bperm_lane(b.y, addr[j - 2]));
+            v[i] = cadd<T>(v[i], r);
+        }
+    }
+}
+
 // Every lane of a line ends with all P sums over the G = 2^lgG lanes (any P).
 template <typename T, int P>
 __device__ __forceinline__ void reduce_all(C<T>* v, int lgG) {
@@ -464,7 +538,7 @@ __device__ __forceinline__ void copy_rows_to_lds(C<T>* dst, const C<T>* __restri
 }
 
 template <typename T, int P, bool LANEINV>
-__global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && P <= 8) ? 4 : 1))) void k_ER(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
                                                  PassGeom g, int lgG, const C<T>* __restrict__ TA,
                                                  const C<T>* __restrict__ HT) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -490,10 +564,17 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
     int base = 0;
     for (int s = 0; s < lk; ++s) base += ((n2 >> s) & 1) * ((P >> s) >> 1);
     const bool writer = (n2 >> lk) == 0 || lgG <= LP;
-    // HT is the table arranged for reduce_scatter_x (pow2 P). With the lane transform the odd
-    // lane's input is modulated by (-1)^n1 (applied once per tile below), which exchanges the
-    // halves of its spectrum.
-    const bool odd_flip = LANEINV && (n2 & 1) && lgG >= 1;
+    // With the lane transform (power-of-two P <= G) and P <= 8 the lane's input is modulated by
+    // exp(-2 pi i s n1 / P), s = bitrev(n2 mod P), once per tile below, and its table row (HT,
+    // [q][n2][r]) is turned by s to match, so the sum over the lanes is reduce_scatter_rot. For
+    // P >= 16 (where the modulation of P values per tile costs more than the selects it saves over
+    // the few terms of a tile) HT is the table arranged for reduce_scatter_x, and the odd lane's
+    // input is modulated by (-1)^n1, which exchanges the halves of its spectrum.
+    constexpr bool ROT = LANEINV && P <= 8;
+    int raddr[LP > 2 ? LP - 2 : 1];
+    if constexpr (ROT) rot_addrs<P>(raddr, (int)threadIdx.x & (kWave - 1), n2);
+    const int rsh = ROT ? rot_shift<P>(n2) : 0;
+    const bool odd_flip = LANEINV && !ROT && (n2 & 1) && lgG >= 1;
     // P = 6 with g = 8: the odd lane's input times (-1)^i moves its spectrum by 3, and it reads its
     // table row rotated by 3 to match (see the sum over the lanes below)
     const bool six = (P == 6) && lgG == 3;
@@ -575,6 +656,12 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
 #pragma unroll
             for (int i = 1; i < P; i += 2) x[i] = mk<T>(-x[i].x, -x[i].y);
         }
+        if constexpr (ROT) {
+            // x[i] exp(-2 pi i s i / P): position p of the lane's spectrum holds index p + s
+            const C<T>* twp = (const C<T>*)ax.tw;
+#pragma unroll
+            for (int i = 1; i < P; ++i) x[i] = cmul<T>(x[i], twp[((rsh * i) & (P - 1)) << lgG]);
+        }
         for (int q = qlo; q < qhi; ++q) {
             if (q > qlo && (q - qlo) % kErStage == 0) {
                 // next round of table rows (the previous round's reads are done first)
@@ -602,8 +689,13 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
                         va[r] = cmul<T>(va[r], h0[r]);
                         vb[r] = cmul<T>(vb[r], h1[r]);
                     }
-                    reduce_scatter_full<T, P>(va, n2);
-                    reduce_scatter_full<T, P>(vb, n2);
+                    if constexpr (ROT) {
+                        reduce_scatter_rot<T, P>(va, raddr);
+                        reduce_scatter_rot<T, P>(vb, raddr);
+                    } else {
+                        reduce_scatter_full<T, P>(va, n2);
+                        reduce_scatter_full<T, P>(vb, n2);
+                    }
                     C<T> sa = va[0], sb = vb[0];
                     for (int s = LP; s < lgG; ++s) {
                         sa = cadd<T>(sa, shfl_xor_c<T>(sa, 1 << s));
@@ -660,7 +752,8 @@ __global__ __launch_bounds__(kThreads) void k_ER(const C<T>* __restrict__ in, C<
             }
             if constexpr (LANEINV) {
                 // sum over the lanes first, then one inverse transform across the P lanes
-                reduce_scatter_full<T, P>(v, n2);
+                if constexpr (ROT) reduce_scatter_rot<T, P>(v, raddr);
+                else reduce_scatter_full<T, P>(v, n2);
                 C<T> s0 = v[0];
                 for (int s = LP; s < lgG; ++s) s0 = cadd<T>(s0, shfl_xor_c<T>(s0, 1 << s));
                 s0 = lane_idft_x<T, LP>(s0, wst, fin);
@@ -1395,9 +1488,15 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
     const C<T> fin = lane_twiddles_x<T, LP>(wst, n2, (const C<T>*)ax.tw, M);
     // power-of-two P with G >= P: reduce-scatter and one shuffle; otherwise all-reduce and pick
     const bool scatter = kPow2<P> && G >= P;
-    // HT is the table arranged for reduce_scatter_x (pow2 P); on the scatter path the odd lane's
-    // input is modulated by (-1)^n1 as well (once per tile)
-    const bool odd_flip = scatter && (n2 & 1) && lgG >= 1;
+    // on the scatter path with P <= 8 the lane's input is modulated by exp(-2 pi i s n1 / P),
+    // s = bitrev(n2 mod P), once per tile, its table row comes turned by s, and the lanes are summed
+    // by reduce_scatter_rot; for P >= 16 the odd lane's input is modulated by (-1)^n1 and HT is the
+    // table arranged for reduce_scatter_x (as for G < P)
+    constexpr bool ROT = kPow2<P> && P <= 8;
+    int raddr[LP > 2 ? LP - 2 : 1];
+    if constexpr (ROT) rot_addrs<P>(raddr, lane, n2);
+    const int rsh = ROT ? rot_shift<P>(n2) : 0;
+    const bool odd_flip = scatter && !ROT && (n2 & 1) && lgG >= 1;
     const int nta = g.qn * P;
     // r(nbar) of the lane's outputs nbar = n2 + G k is r0 + k d (mod P)
     const int r0 = (int)(((int64_t)n2 * ax.lg) % P);
@@ -1431,6 +1530,11 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
 #pragma unroll
             for (int i = 1; i < P; i += 2) x[i] = mk<T>(-x[i].x, -x[i].y);
         }
+        if (ROT && scatter) {
+            const C<T>* twp = (const C<T>*)ax.tw;
+#pragma unroll
+            for (int i = 1; i < P; ++i) x[i] = cmul<T>(x[i], twp[((rsh * i) & (P - 1)) << lgG]);
+        }
         __syncthreads();
         for (int q = g.qb; q < g.qb + g.qn; ++q) {
             const C<T>* ta = TAs + (q - g.qb) * P;
@@ -1443,7 +1547,8 @@ __global__ __launch_bounds__(kThreads) void k_EAR(const C<T>* __restrict__ in, C
 #pragma unroll
             for (int r = 0; r < P; ++r) v[r] = cmul<T>(v[r], h[r]);
             if (scatter) {
-                reduce_scatter_x<T, P>(v, n2, lgG);
+                if constexpr (ROT) reduce_scatter_rot<T, P>(v, raddr);
+                else reduce_scatter_x<T, P>(v, n2, lgG);
                 C<T> s0 = v[0];
                 for (int s = LP; s < lgG; ++s) s0 = cadd<T>(s0, shfl_xor_c<T>(s0, 1 << s));
                 s0 = lane_idft_x<T, LP>(s0, wst, fin);  // lane n2 < P now holds E[n2]
@@ -2647,7 +2752,7 @@ constexpr int kEwWaves = 8;
 constexpr size_t kEwStageBytes = 65536;  // HT rows of the pass staged when they fit
 
 template <typename T, int P, bool HST>
-__global__ __launch_bounds__(kEwWaves * kWave) void k_EAW(const C<T>* __restrict__ in, C<T>* __restrict__ out,
+__global__ __launch_bounds__(kEwWaves * kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_EAW(const C<T>* __restrict__ in, C<T>* __restrict__ out,
                                                          AxisDev ax, PassGeom g, int accumulate,
                                                          T* __restrict__ rho, const C<T>* __restrict__ TA,
                                                          const C<T>* __restrict__ HT) {
@@ -2671,14 +2776,21 @@ __global__ __launch_bounds__(kEwWaves * kWave) void k_EAW(const C<T>* __restrict
         TAs[e] = TA[(int64_t)(g.qb + qq) * M + G * i];
         Tfs[e] = Tf[(int64_t)(g.qb + qq) * M + i];
     }
+    // power-of-two P >= 4 with the rows staged: the lanes' spectra are shifted by bitrev(n2 mod P)
+    // and summed by the select-free reduce_scatter_rot
+    constexpr bool ROT = kPow2<P> && HST && P >= 4;
     if constexpr (HST) {
-        // P = 6: the odd lanes' rows rotated by 3 (see below)
+        // P = 6: the odd lanes' rows rotated by 3 (see below); ROT: lane m2's row turned by the
+        // rest s'(m2) of its shift (HT comes with the odd rows turned by P / 2)
         const C<T>* hsrc = HT + (int64_t)g.qb * M;
         for (int e = tid; e < qn * M; e += kEwWaves * kWave) {
             int src = e;
             if constexpr (P == 6) {
                 const int qq = e / M, rem = e - qq * M, r = rem / G, m2 = rem - r * G;
                 src = qq * M + ((r + 3 * (m2 & 1)) % 6) * G + m2;
+            } else if constexpr (ROT) {
+                const int qq = e / M, rem = e - qq * M, r = rem / G, m2 = rem - r * G;
+                src = qq * M + ((r + rot_shift_rest<P>(m2)) & (P - 1)) * G + m2;
             }
             Hst[e] = hsrc[src];
         }
@@ -2689,7 +2801,10 @@ __global__ __launch_bounds__(kEwWaves * kWave) void k_EAW(const C<T>* __restrict
     // P = 6: the odd lane's input times (-1)^i moves its spectrum by 3, and it reads its table row
     // rotated by 3 to match, so both lanes of the first reduce step keep values 0..2
     constexpr bool SIX = (P == 6);
-    const bool odd_flip = (P2 || SIX) && (n2 & 1);
+    const bool odd_flip = !ROT && (P2 || SIX) && (n2 & 1);
+    int raddr[LP > 2 ? LP - 2 : 1];
+    if constexpr (ROT) rot_addrs<P>(raddr, lane, n2);
+    const int rsh = ROT ? rot_shift<P>(n2) : 0;  // the lane's spectral shift s(n2)
     C<T> wst[LP > 0 ? LP : 1];
     C<T> fin = mk<T>(1, 0);
     if constexpr (P2) fin = lane_twiddles_x<T, LP>(wst, n2, (const C<T>*)ax.tw, M);
@@ -2720,12 +2835,6 @@ __global__ __launch_bounds__(kEwWaves * kWave) void k_EAW(const C<T>* __restrict
         }
     }
     const int qbr = g.qb % G;
-    C<T> ctw[G];
-#pragma unroll
-    for (int c = 0; c < G; ++c) {
-        const C<T> t = tw[((qbr * c) % G) * P];
-        ctw[c] = mk<T>(t.x, -t.y);
-    }
     // tiles: each wave is a worker; the waves of a workgroup take consecutive tiles and every XCD
     // (workgroup id mod 8) a contiguous range, so neighbouring strided tiles share one L2
     const int64_t ntl = g.Qin * g.ntiles;  // < 2^31 (host check)
@@ -2750,6 +2859,11 @@ __global__ __launch_bounds__(kEwWaves * kWave) void k_EAW(const C<T>* __restrict
         if (odd_flip) {
 #pragma unroll
             for (int i = 1; i < P; i += 2) x[i] = mk<T>(-x[i].x, -x[i].y);
+        }
+        if constexpr (ROT) {
+            // x[i] exp(-2 pi i s i / P) moves the lane's spectrum by s: position p holds index p + s
+#pragma unroll
+            for (int i = 1; i < P; ++i) x[i] = cmul<T>(x[i], tw[((rsh * i) & (P - 1)) * G]);
         }
         C<T> hj[G];
 #pragma unroll
@@ -2812,13 +2926,15 @@ __global__ __launch_bounds__(kEwWaves * kWave) void k_EAW(const C<T>* __restrict
                     sa = cfma<T>(cfma<T>(aa[0], c6[0], aa[1]), c6[1], aa[2]);
                     if constexpr (PAIR) sb = cfma<T>(cfma<T>(ab[0], c6[0], ab[1]), c6[1], ab[2]);
                 } else if constexpr (P2) {
-                    reduce_scatter_x<T, P>(va, n2, 3);
+                    if constexpr (ROT) reduce_scatter_rot<T, P>(va, raddr);
+                    else reduce_scatter_x<T, P>(va, n2, 3);
                     sa = va[0];
 #pragma unroll
                     for (int s = LP; s < 3; ++s) sa = cadd<T>(sa, shfl_xor_c<T>(sa, 1 << s));
                     sa = lane_idft_x<T, LP>(sa, wst, fin);  // lane n2 now holds E_q[n2 mod P]
                     if constexpr (PAIR) {
-                        reduce_scatter_x<T, P>(vb, n2, 3);
+                        if constexpr (ROT) reduce_scatter_rot<T, P>(vb, raddr);
+                        else reduce_scatter_x<T, P>(vb, n2, 3);
                         sb = vb[0];
 #pragma unroll
                         for (int s = LP; s < 3; ++s) sb = cadd<T>(sb, shfl_xor_c<T>(sb, 1 << s));
@@ -2857,7 +2973,9 @@ __global__ __launch_bounds__(kEwWaves * kWave) void k_EAW(const C<T>* __restrict
         if (live && holds) {
 #pragma unroll
             for (int c = 0; c < G; ++c) {
-                C<T> v = cmul<T>(hj[c], ctw[c]);
+                // exp(2 pi i qb c / 8), read per tile rather than held in registers across it
+                const C<T> t = tw[((qbr * c) % G) * P];
+                C<T> v = cmulc<T>(hj[c], t);
                 const int nb = n0u + P * c;
                 const int64_t off = (g.S == 1) ? ((qi * g.A + tl.a0 + l) * M + nb)
                                                : (((qi * g.A + tl.a0) * M + nb) * g.S + tl.s0 + l);

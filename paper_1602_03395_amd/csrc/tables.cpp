@@ -123,16 +123,27 @@ void build_ht(AxisTables& t, int64_t M, int64_t lam) {
             }
         }
     }
-    // HTx once more in [q][n2][r] order, for kernels whose lanes read their own P values of a row
-    // straight from memory
+    // The table once more in [q][n2][r] order, for kernels whose lanes read their own P values of a
+    // row contiguously. For power-of-two P <= min(g, 8) those kernels shift lane n2's spectrum by
+    // s = bitrev(n2 mod P) (its input times exp(-2 pi i s n1 / P)), which makes every step of the
+    // reduction over the lanes select-free, so the lane's row is turned by s: HTl[q][n2][r] =
+    // HT[q][(r + s) mod P][n2] (for P = 2 this is HTx). Otherwise HTl is HTx reordered.
     t.HTl.assign(t.HTx.size(), 0.0);
+    int lgp = 0;
+    while ((int64_t(1) << lgp) < P) ++lgp;
+    const bool rot = p2 && P >= 2 && P <= 8 && g >= P;
     for (int64_t q = 0; q < lam; ++q)
-        for (int64_t n2 = 0; n2 < g; ++n2)
+        for (int64_t n2 = 0; n2 < g; ++n2) {
+            int64_t sh = 0;
+            for (int b = 0; b < lgp; ++b) sh |= ((n2 >> b) & 1) << (lgp - 1 - b);
             for (int64_t r = 0; r < P; ++r) {
-                const size_t d = 2 * (size_t)((q * g + n2) * P + r), src = at(q, r, n2);
-                t.HTl[d] = t.HTx[src];
-                t.HTl[d + 1] = t.HTx[src + 1];
+                const size_t d = 2 * (size_t)((q * g + n2) * P + r);
+                const size_t src = rot ? at(q, (r + sh) % P, n2) : at(q, r, n2);
+                const std::vector<double>& from = rot ? t.HT : t.HTx;
+                t.HTl[d] = from[src];
+                t.HTl[d + 1] = from[src + 1];
             }
+        }
 }
 
 }  // namespace
