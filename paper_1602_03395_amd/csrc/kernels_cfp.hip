@@ -2765,6 +2765,10 @@ __global__ __launch_bounds__(kEwWaves * kWave) __attribute__((amdgpu_waves_per_e
     C<T>* TAs = (C<T>*)smem;         // [q - qb][i] = TA_q[8 i]
     C<T>* Tfs = TAs + qn * P;        // [q - qb][n0] = Tf_q[n0]
     C<T>* Hst = Tfs + qn * P;        // [q - qb][r][n2] (HST)
+    // FP32: the eight accumulators of a tile wait in LDS, [wave][j][lane], not in registers, which
+    // keeps the paired term loop within the registers of four waves per SIMD
+    constexpr bool HJL = sizeof(T) == 4;
+    C<T>* Hjs = Hst + (HST ? qn * M : 0);
     const int tid = (int)threadIdx.x;
     const int w = tid / kWave;
     const int lane = tid % kWave;
@@ -2865,9 +2869,11 @@ __global__ __launch_bounds__(kEwWaves * kWave) __attribute__((amdgpu_waves_per_e
 #pragma unroll
             for (int i = 1; i < P; ++i) x[i] = cmul<T>(x[i], tw[((rsh * i) & (P - 1)) * G]);
         }
-        C<T> hj[G];
+        C<T> hj[HJL ? 1 : G];
+        if constexpr (!HJL) {
 #pragma unroll
-        for (int j = 0; j < G; ++j) hj[j] = mk<T>(0, 0);
+            for (int j = 0; j < G; ++j) hj[j] = mk<T>(0, 0);
+        }
         // FP32: the chains of slots j and j + 1 run together, two terms (q, q + 1) per iteration, so
         // their sequences of cross-lane steps are independent and interleave; FP64 keeps one term
         // per iteration, as two would not fit the registers of four waves per SIMD
@@ -2961,21 +2967,29 @@ __global__ __launch_bounds__(kEwWaves * kWave) __attribute__((amdgpu_waves_per_e
                 acca = cfma<T>(acca, Tfs[qq * P + n0u], sa);
                 if (two) accb = cfma<T>(accb, Tfs[qb2 * P + n0u], sb);
             }
+            if constexpr (HJL) {
+                Hjs[(w * G + j) * kWave + lane] = acca;
+                if constexpr (PAIR) Hjs[(w * G + j + 1) * kWave + lane] = accb;
+            } else {
 #pragma unroll
-            for (int jj = 0; jj < G; jj += JS)
-                if (jj == j) {
-                    hj[jj] = acca;
-                    if constexpr (PAIR) hj[jj + 1] = accb;
-                }
+                for (int jj = 0; jj < G; jj += JS)
+                    if (jj == j) {
+                        hj[jj] = acca;
+                        if constexpr (PAIR) hj[jj + 1] = accb;
+                    }
+            }
         }
         // the 8-point inverse over j of the output group (l, n0u); lanes n2 >= P hold copies
-        RegDFT<T, G, true>::run(hj);
+        C<T> hv[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) hv[j] = HJL ? Hjs[(w * G + j) * kWave + lane] : hj[HJL ? 0 : j];
+        RegDFT<T, G, true>::run(hv);
         if (live && holds) {
 #pragma unroll
             for (int c = 0; c < G; ++c) {
                 // exp(2 pi i qb c / 8), read per tile rather than held in registers across it
                 const C<T> t = tw[((qbr * c) % G) * P];
-                C<T> v = cmulc<T>(hj[c], t);
+                C<T> v = cmulc<T>(hv[c], t);
                 const int nb = n0u + P * c;
                 const int64_t off = (g.S == 1) ? ((qi * g.A + tl.a0 + l) * M + nb)
                                                : (((qi * g.A + tl.a0) * M + nb) * g.S + tl.s0 + l);
@@ -2992,8 +3006,10 @@ hipError_t launch_eaw(const void* in, void* out, const AxisDev& ax, const PassGe
                       hipStream_t st) {
     const size_t stage = (size_t)g.qn * ax.M * sizeof(C<T>);
     const bool hst = stage <= kEwStageBytes;
-    // the pass's table rows staged in LDS once per workgroup when they fit kEwStageBytes
-    const size_t lds = ((size_t)2 * g.qn * P + (hst ? (size_t)g.qn * ax.M : 0)) * sizeof(C<T>);
+    // the pass's table rows staged in LDS once per workgroup when they fit kEwStageBytes; FP32 adds
+    // the accumulators of the waves' tiles (8 per lane)
+    const size_t hjl = sizeof(T) == 4 ? (size_t)kEwWaves * 8 * kWave : 0;
+    const size_t lds = ((size_t)2 * g.qn * P + (hst ? (size_t)g.qn * ax.M : 0) + hjl) * sizeof(C<T>);
     const int64_t units = (g.Qin * g.ntiles + kEwWaves - 1) / kEwWaves;
     int64_t blocks = (units + 7) / 8 * 8;
     const int64_t cap = (int64_t)(2 * cu_count() + 7) / 8 * 8;  // persistent: the staged rows are reused
@@ -3139,7 +3155,8 @@ bool eaw_applicable(bool dbl, int M, int g, int qn) {
     const int P = M / 8;
     if (!(P == 2 || P == 3 || P == 4 || P == 6 || P == 8)) return false;
     const size_t cs = dbl ? 16 : 8;
-    return (size_t)2 * qn * P * cs <= (size_t)lds_limit_bytes();
+    const size_t hjl = dbl ? 0 : (size_t)kEwWaves * 8 * kWave * cs;  // the FP32 accumulators
+    return (size_t)2 * qn * P * cs + hjl <= (size_t)lds_limit_bytes();
 }
 
 int eaw_tile_lines() { return 8; }
