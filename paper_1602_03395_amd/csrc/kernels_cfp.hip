@@ -506,6 +506,14 @@ __device__ __forceinline__ C<T> lane_idft_x(C<T> a, const C<T>* wst, C<T> fin) {
     for (int s = 0; s < LP; ++s) a = lane_bfly<T>(a, wst[s], 1 << s, s);
     return cmul<T>(a, fin);
 }
+// The same without the final rescale: the lane's output times c, for callers that apply conj(c)
+// (fin) once to a sum of many such outputs.
+template <typename T, int LP>
+__device__ __forceinline__ C<T> lane_idft_nofin(C<T> a, const C<T>* wst) {
+#pragma unroll
+    for (int s = 0; s < LP; ++s) a = lane_bfly<T>(a, wst[s], 1 << s, s);
+    return a;
+}
 
 // Terms whose chirp-folded table rows (M values each) are staged in LDS at a time.
 constexpr int kErStage = 4;
@@ -2738,16 +2746,19 @@ hipError_t launch_asr_T(const void* in, void* out, const AxisDev& ax, const Pass
 // (l, n2) keeps its P inputs x[8 i + n2] in registers, forms E_q for each term q as the register E
 // kernel does and, as lane u = n2 < P holding E_q[u], adds Tf_q[n0] E_q[u] into the partial sum
 // H[j], j = (q - qb) mod 8, of its output group n0 (r(n0) = u). The terms run j by j (q = qb + j,
-// qb + j + 8, ...), so the running sum is one register and each finished H[j] goes to its slot of
-// the lane's register array once per j. After the last term the lane applies the 8-point inverse
-// transform of the structured accumulate (presf):
+// qb + j + 8, ...), so the running sum is one register and each finished H[j] goes to its slot (a
+// register array in FP64, LDS in FP32) once per j. After the last term the lane applies the 8-point
+// inverse transform of the structured accumulate (presf):
 //   out[n0 + P c] = exp(2 pi i qb c / 8) sum_j exp(2 pi i j c / 8) H[j],   c < 8,
 // and writes its 8 outputs. The sum over the 8 lanes of a line and the P-point inverse are, for a
-// power-of-two P, the butterfly reduce-scatter and the cross-lane inverse of the register E kernel;
-// for P = 3 and 6 every lane applies the P-point inverse to its own HT-weighted values, pads them
-// to 8 and the lanes' results are added by the select form of the reduce-scatter (lane n2 ends
-// with value bitrev3(n2)). There is no workgroup barrier after the table rows of the pass (TA, HT,
-// Tf) are staged in LDS, once per workgroup of a persistent grid.
+// power-of-two P, a reduce-scatter (the rotated, select-free one when the rows are staged and
+// P >= 4) and the cross-lane inverse of the register E kernel, whose final per-lane rescale is
+// applied once to the H[j] instead of to every term; for P = 6 one select-free step over the lane
+// pair, the other two lane bits summed in full, and a 6-term inverse for the lane's output; for
+// P = 3 every lane applies the P-point inverse to its own HT-weighted values, pads them to 8 and
+// the lanes' results are added by the select form of the reduce-scatter (lane n2 ends with value
+// bitrev3(n2)). There is no workgroup barrier after the table rows of the pass (TA, HT, Tf) are
+// staged in LDS, once per workgroup of a persistent grid.
 constexpr int kEwWaves = 8;
 constexpr size_t kEwStageBytes = 65536;  // HT rows of the pass staged when they fit
 
@@ -2937,14 +2948,15 @@ __global__ __launch_bounds__(kEwWaves * kWave) __attribute__((amdgpu_waves_per_e
                     sa = va[0];
 #pragma unroll
                     for (int s = LP; s < 3; ++s) sa = cadd<T>(sa, shfl_xor_c<T>(sa, 1 << s));
-                    sa = lane_idft_x<T, LP>(sa, wst, fin);  // lane n2 now holds E_q[n2 mod P]
+                    // lane n2 now holds E_q[n2 mod P] / fin; fin is applied to the accumulators
+                    sa = lane_idft_nofin<T, LP>(sa, wst);
                     if constexpr (PAIR) {
                         if constexpr (ROT) reduce_scatter_rot<T, P>(vb, raddr);
                         else reduce_scatter_x<T, P>(vb, n2, 3);
                         sb = vb[0];
 #pragma unroll
                         for (int s = LP; s < 3; ++s) sb = cadd<T>(sb, shfl_xor_c<T>(sb, 1 << s));
-                        sb = lane_idft_x<T, LP>(sb, wst, fin);
+                        sb = lane_idft_nofin<T, LP>(sb, wst);
                     }
                 } else {
                     // the P values padded to 8 and summed over the 8 lanes by the select form of the
@@ -2983,6 +2995,11 @@ __global__ __launch_bounds__(kEwWaves * kWave) __attribute__((amdgpu_waves_per_e
         C<T> hv[G];
 #pragma unroll
         for (int j = 0; j < G; ++j) hv[j] = HJL ? Hjs[(w * G + j) * kWave + lane] : hj[HJL ? 0 : j];
+        if constexpr (P2) {
+            // the lane's rescale of the cross-lane inverse, once for the sums of all terms
+#pragma unroll
+            for (int j = 0; j < G; ++j) hv[j] = cmul<T>(hv[j], fin);
+        }
         RegDFT<T, G, true>::run(hv);
         if (live && holds) {
 #pragma unroll
