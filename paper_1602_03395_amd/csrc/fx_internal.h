@@ -39,7 +39,8 @@ struct AxisDev {
     const void* tw = nullptr;
     const void* HT = nullptr;  // [lam][P][g] chirp-folded table of the register E kernel (or null)
     const void* HTx = nullptr; // HT arranged for the select-free first reduction step (or null)
-    const void* HTl = nullptr; // HTx in [lam][g][P] order (each lane's P values contiguous)
+    const void* HTl = nullptr; // [lam][g][P] (each lane's P values contiguous): for power-of-two
+                               // P <= min(g, 8) row n2 turned by bitrev(n2 mod P), else HTx reordered
     int M = 1;        // axis length
     int P = 1;        // M / g: number of distinct n'' values (output-pruned length)
     int g = 1;        // gcd(lam, M)
@@ -119,7 +120,7 @@ struct AxisTables {
     std::vector<double> TA, TB, Tf, tw;  // interleaved re,im; [lam][M] for TA/TB/Tf, [M] for tw
     std::vector<double> HT;              // [lam][P][g] when requested, else empty
     std::vector<double> HTx;             // HT for odd n2 lanes swapped or sign-modulated (see build_ht)
-    std::vector<double> HTl;             // HTx in [lam][g][P] order
+    std::vector<double> HTl;             // [lam][g][P], rows turned for the rotated reduction (see build_ht)
 };
 struct AxisParams {
     int64_t M = 1;

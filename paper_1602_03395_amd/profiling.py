@@ -82,11 +82,26 @@ KERNEL_SOURCES = ("kernels.hip", "kernels_p2.hip", "kernels_ct.hip", "kernels_cf
                   "fx_internal.h")
 
 
-def kernels_hash() -> str:
+def code_lines(text: str):
+    """The lines of a source with its // comments, trailing blanks and empty lines dropped: an edit
+    of comments alone leaves the hash of the kernel sources, and so the stored counters, valid."""
+    for line in text.splitlines():
+        line = line.split("//", 1)[0].rstrip()
+        if line:
+            yield line
+
+
+def kernels_hash(sources: dict | None = None) -> str:
+    """Hash of the code of the kernel sources (files under csrc/, or the given name -> text)."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(HERE, "csrc", name), "rb") as f:
-            h.update(f.read())
+        if sources is not None:
+            text = sources[name]
+        else:
+            with open(os.path.join(HERE, "csrc", name), encoding="utf-8") as f:
+                text = f.read()
+        for line in code_lines(text):
+            h.update(line.encode("utf-8") + b"\n")
     return h.hexdigest()[:16]
 
 
