@@ -545,10 +545,11 @@ __device__ __forceinline__ void copy_rows_to_lds(C<T>* dst, const C<T>* __restri
     }
 }
 
+// FP32 with P <= 8: at most 128 registers (four waves per SIMD)
 template <typename T, int P, bool LANEINV>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && P <= 8) ? 4 : 1))) void k_ER(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax,
-                                                 PassGeom g, int lgG, const C<T>* __restrict__ TA,
-                                                 const C<T>* __restrict__ HT) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && P <= 8) ? 4 : 1)))
+void k_ER(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax, PassGeom g, int lgG,
+          const C<T>* __restrict__ TA, const C<T>* __restrict__ HT) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int LP = (P >= 32) ? 5 : (P >= 16) ? 4 : (P >= 8) ? 3 : (P >= 4) ? 2 : (P >= 2) ? 1 : 0;
     const int M = ax.M;
@@ -2762,11 +2763,11 @@ hipError_t launch_asr_T(const void* in, void* out, const AxisDev& ax, const Pass
 constexpr int kEwWaves = 8;
 constexpr size_t kEwStageBytes = 65536;  // HT rows of the pass staged when they fit
 
+// FP32: at most 128 registers, so that the two resident workgroups of 8 waves (4 per SIMD) fit
 template <typename T, int P, bool HST>
-__global__ __launch_bounds__(kEwWaves * kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_EAW(const C<T>* __restrict__ in, C<T>* __restrict__ out,
-                                                         AxisDev ax, PassGeom g, int accumulate,
-                                                         T* __restrict__ rho, const C<T>* __restrict__ TA,
-                                                         const C<T>* __restrict__ HT) {
+__global__ __launch_bounds__(kEwWaves * kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
+void k_EAW(const C<T>* __restrict__ in, C<T>* __restrict__ out, AxisDev ax, PassGeom g, int accumulate,
+           T* __restrict__ rho, const C<T>* __restrict__ TA, const C<T>* __restrict__ HT) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int G = 8;
     constexpr int M = G * P;

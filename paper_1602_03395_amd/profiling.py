@@ -83,8 +83,7 @@ KERNEL_SOURCES = ("kernels.hip", "kernels_p2.hip", "kernels_ct.hip", "kernels_cf
 
 
 def code_lines(text: str):
-    """The lines of a source with its // comments, trailing blanks and empty lines dropped: an edit
-    of comments alone leaves the hash of the kernel sources, and so the stored counters, valid."""
+    """The lines of a source with its // comments, trailing blanks and empty lines dropped."""
     for line in text.splitlines():
         line = line.split("//", 1)[0].rstrip()
         if line:
@@ -92,7 +91,9 @@ def code_lines(text: str):
 
 
 def kernels_hash(sources: dict | None = None) -> str:
-    """Hash of the code of the kernel sources (files under csrc/, or the given name -> text)."""
+    """Hash of the code of the kernel sources (files under csrc/, or the given name -> text), with
+    comments and all white space removed: an edit of comments or layout alone leaves it, and so
+    the stored counters, valid."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
         if sources is not None:
@@ -100,8 +101,8 @@ def kernels_hash(sources: dict | None = None) -> str:
         else:
             with open(os.path.join(HERE, "csrc", name), encoding="utf-8") as f:
                 text = f.read()
-        for line in code_lines(text):
-            h.update(line.encode("utf-8") + b"\n")
+        code = "".join("".join(line.split()) for line in code_lines(text))
+        h.update(name.encode("utf-8") + b"\0" + code.encode("utf-8") + b"\0")
     return h.hexdigest()[:16]
 
 

@@ -1,5 +1,5 @@
 """Host logic of the profile summaries: the hash that ties stored HBM counters to the kernel sources
-ignores comments and blank lines but not code; pass kinds are read from kernel names."""
+ignores comments and layout but not code; pass kinds are read from kernel names."""
 
 import os
 
@@ -18,13 +18,18 @@ def test_hash_of_files_equals_hash_of_their_text():
     assert pr.kernels_hash() == pr.kernels_hash(_sources())
 
 
-def test_comment_edits_keep_the_hash_and_code_edits_change_it():
+def test_comment_and_layout_edits_keep_the_hash_and_code_edits_change_it():
     src = _sources()
     base = pr.kernels_hash(src)
     name = "kernels_cfp.hip"
     commented = dict(src)
     commented[name] = "// a new comment line\n\n" + src[name].replace("\n", "  // trailing note\n", 3)
     assert pr.kernels_hash(commented) == base
+    reflowed = dict(src)
+    snippet = "    const int tid = (int)threadIdx.x;"
+    assert snippet in src[name]
+    reflowed[name] = src[name].replace(snippet, "    const int tid =\n        (int) threadIdx.x ;")
+    assert pr.kernels_hash(reflowed) == base
     edited = dict(src)
     edited[name] = src[name] + "\nstatic int extra_symbol = 1;\n"
     assert pr.kernels_hash(edited) != base
