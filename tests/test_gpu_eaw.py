@@ -39,6 +39,10 @@ CASES = [
     ((48, 20), (8, 5), (0.9, 1.0), 12.0),    # strided lines, P = 6
     ((24, 16, 12), (16, 8, 3), (1.0, 1.0, 1.2), 10.0),  # 3-D, EA along axis 0 with P = 3
     ((32, 16, 24), (40, 8, 2), (1.0, 0.7, 1.0), 25.0),  # 3-D, P = 4
+    # table rows too large to stage in LDS (qn M beyond 64 KiB; FP64 only for the second case): the
+    # kernel reads them from memory and keeps the first-step flip instead of the rotated reduction
+    ((64,), (136,), (1.0,), 60.0),           # P = 8
+    ((64, 4), (72, 2), (1.0, 0.9), 40.0),    # P = 8, strided
 ]
 
 
